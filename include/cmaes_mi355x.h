@@ -1,0 +1,197 @@
+/*
+ * cmaes_mi355x.h - C ABI of the MI355X (gfx950) IPOP-CMA-ES generation path.
+ *
+ * The library minimises a blackbox f: R^n -> R by probing points and reading
+ * their values (paper Sec. 1, problem statement).  One call of
+ * cmaes_generation() runs one CMA-ES iteration (Alg. 1 loop body, Sec. 2.1):
+ * sample lambda points with eq. (1), evaluate them, rank them, update the
+ * mean, the two evolution paths, the step size sigma and the covariance C with
+ * the rank-one plus rank-mu update of eq. (2)/(3), and, every kappa
+ * generations, re-run the eigendecomposition C = B D^2 B^T.  The restart loop
+ * of Alg. 2 (Sec. 2.2) is cmaes_restart_ipop() / cmaes_ipop_run().
+ *
+ * Conventions
+ *  - Every function returns CMAES_OK (0) or a negative CMAES_E* code; no
+ *    exception crosses the ABI.  cmaes_last_error() returns a thread-local
+ *    message describing the last failure.
+ *  - Matrices are column-major.  Candidate k of a population is column k.
+ *  - Unless stated otherwise every pointer argument is HOST memory owned by
+ *    the caller; the library copies from / into it before returning and never
+ *    keeps it.  All device memory is owned by the handle and freed by
+ *    cmaes_destroy() / cmaes_batch_destroy().
+ *  - Work is queued on the handle's HIP stream (options.stream, NULL = the
+ *    library's own stream).  Calls that hand data back to the host
+ *    synchronise that stream; cmaes_generation() itself may return before the
+ *    device has finished.
+ *  - A handle is not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef CMAES_MI355X_H
+#define CMAES_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define CMAES_OK 0
+#define CMAES_EINVAL (-1)   /* bad argument (size, pointer, enum)            */
+#define CMAES_ENOMEM (-2)   /* device or host allocation failed              */
+#define CMAES_EDEVICE (-3)  /* HIP runtime error or no gfx950 device          */
+#define CMAES_ESTATE (-4)   /* call not valid in the handle's current state   */
+#define CMAES_EKMAX (-5)    /* restart would exceed K_max (Alg. 2 loop end)   */
+#define CMAES_ENUMERIC (-6) /* non-finite values, eigen solver did not converge */
+
+/* ---- enums -------------------------------------------------------------- */
+typedef enum {
+  CMAES_FP64 = 0,        /* every step in float64                              */
+  CMAES_MIXED = 1,       /* sampling, fitness, rank-mu SYRK in float32 MFMA;
+                            eigensolve, paths, sigma, C in float64             */
+  CMAES_MIXED_BF16X3 = 2 /* as MIXED, y = B D z as three bf16 split products   */
+} cmaes_precision_t;
+
+typedef enum {
+  CMAES_OBJ_NONE = 0,      /* no fused objective: host ask/tell only           */
+  CMAES_OBJ_SPHERE = 1,    /* sum_i u_i^2                                      */
+  CMAES_OBJ_ELLIPSOID = 2, /* sum_i 10^(6 (i-1)/(n-1)) u_i^2                   */
+  CMAES_OBJ_RASTRIGIN = 3  /* 10 n + sum_i (u_i^2 - 10 cos(2 pi u_i))          */
+} cmaes_objective_t;       /* u = R (x - x*), R = I and x* = 0 when not given  */
+
+/* Stop bits (reading of the stopping conditions named in Sec. 2.2). */
+#define CMAES_STOP_TOLHISTFUN (1u << 0)
+#define CMAES_STOP_TOLFUN (1u << 1)
+#define CMAES_STOP_TOLX (1u << 2)
+#define CMAES_STOP_NOEFFECTAXIS (1u << 3)
+#define CMAES_STOP_NOEFFECTCOORD (1u << 4)
+#define CMAES_STOP_CONDITIONCOV (1u << 5)
+#define CMAES_STOP_FTARGET (1u << 6)
+#define CMAES_STOP_MAXGEN (1u << 7)
+#define CMAES_STOP_MAXEVALS (1u << 8)
+#define CMAES_STOP_NUMERIC (1u << 9)
+
+/* ---- options ------------------------------------------------------------ */
+typedef struct {
+  int32_t precision;      /* cmaes_precision_t (default CMAES_MIXED)              */
+  int32_t eigen_interval; /* kappa; 0 = max(1, ceil(1/(10 n (c1+cmu))))          */
+  int32_t k_max;          /* Alg. 2 K_max (default 256)                          */
+  int32_t max_gens;       /* per descent; 0 = no limit                           */
+  int64_t max_evals;      /* whole run (Alg. 2 'budget'); 0 = no limit            */
+  double box_lo, box_hi;  /* search box of the initial mean (default [-4, 4])     */
+  double f_target;        /* stop when best f < f_target (default 1e-8)           */
+  double tol_hist_fun;    /* default 1e-12                                        */
+  double tol_fun;         /* default 1e-12                                        */
+  double tol_x_factor;    /* TolX = tol_x_factor * sigma0 (default 1e-12)         */
+  double max_condition;   /* ConditionCov threshold on cond(C) (default 1e14)     */
+  void* stream;           /* hipStream_t to run on; NULL = library-owned stream   */
+} cmaes_options_t;
+
+/* Fill *opt with the defaults listed above.  Returns CMAES_EINVAL if opt is NULL. */
+int cmaes_default_options(cmaes_options_t* opt);
+
+/* ---- state snapshot ----------------------------------------------------- */
+/* Scalars are always filled by cmaes_state().  Each pointer is an optional
+ * caller-owned host buffer (NULL = not copied): m, p_sigma, p_c, D, x_best
+ * hold n doubles; C and B hold n*n doubles (column-major); f holds lambda
+ * doubles (fitness of the last generation, candidate order) and order holds
+ * lambda int32 (order[r] = candidate of rank r, ascending f, ties by index,
+ * NaN last).  cmaes_set_state() reads n, lambda, gen, sigma and every
+ * non-NULL buffer among m, C, B, D, p_sigma, p_c; other fields are ignored. */
+typedef struct {
+  int32_t n, lambda, mu, restart;
+  int64_t gen;         /* generations in the current descent                   */
+  int64_t evals;       /* evaluations in the current descent                   */
+  int64_t total_evals; /* evaluations over all descents of this handle         */
+  double sigma;
+  double f_best;       /* best f over all descents of this handle              */
+  uint32_t stop;       /* CMAES_STOP_* bits of the current descent             */
+  int32_t kappa;       /* eigendecomposition interval in use                   */
+  int32_t eig_sweeps;  /* Jacobi sweeps used by the last eigendecomposition    */
+  int32_t reserved;
+  double* m;
+  double* C;
+  double* B;
+  double* D;
+  double* p_sigma;
+  double* p_c;
+  double* x_best;
+  double* f;
+  int32_t* order;
+} cmaes_state_t;
+
+typedef struct cmaes cmaes_t; /* opaque; create -> destroy */
+
+/* Create a descent for dimension n (>= 1) and population lambda (<= 0 selects
+ * 4 + floor(3 ln n); otherwise >= 2), initial step size sigma0 > 0 and a
+ * 64-bit seed.  The initial mean is uniform in [box_lo, box_hi]^n drawn from
+ * the seed (Sec. 4.1); C = B = D = I, p_sigma = p_c = 0.  Device memory is
+ * allocated on the current HIP device.  Options may be changed with
+ * cmaes_set_options() before the first generation.  Returns NULL on failure
+ * (reason in cmaes_last_error()). */
+cmaes_t* cmaes_create(int n, int lambda, double sigma0, uint64_t seed);
+
+/* Free every resource of h (NULL is a no-op). */
+void cmaes_destroy(cmaes_t* h);
+
+/* Replace the options.  Changing precision or stream is only allowed before
+ * the first generation of a descent (CMAES_ESTATE otherwise); a new box
+ * redraws the initial mean if no generation has run yet. */
+int cmaes_set_options(cmaes_t* h, const cmaes_options_t* opt);
+
+/* Read the options in use into *opt. */
+int cmaes_get_options(const cmaes_t* h, cmaes_options_t* opt);
+
+/* Select the fused objective.  R: n*n column-major rotation (NULL = identity);
+ * xstar: n values (NULL = origin).  Both are copied to the device. */
+int cmaes_set_objective(cmaes_t* h, int kind, const double* R, const double* xstar);
+
+/* One full generation on the device with the fused objective (Alg. 1 body).
+ * CMAES_ESTATE if no objective is set or the descent has stopped. */
+int cmaes_generation(cmaes_t* h);
+
+/* Parity hook: as cmaes_generation() but with the n*lambda normal matrix Z
+ * (column-major, column k = z_k of eq. (1)) supplied by the caller. */
+int cmaes_generation_with_z(cmaes_t* h, const double* Z);
+
+/* Host blackbox path, first half: sample the generation's points
+ * x_k = m + sigma B D z_k into X (n*lambda, column-major). */
+int cmaes_ask(cmaes_t* h, double* X);
+
+/* Host blackbox path, second half: supply the lambda fitness values of the
+ * points returned by the last cmaes_ask() (NaN counts as +inf) and run the
+ * rest of the generation.  CMAES_ESTATE without a pending ask. */
+int cmaes_tell(cmaes_t* h, const double* f);
+
+/* Alg. 2 restart: lambda <- 2 lambda (K <- 2K), a fresh mean from the seed
+ * stream, sigma = sigma0, C = B = D = I, zero paths; the best point over all
+ * descents is kept.  CMAES_EKMAX if 2K would exceed K_max (nothing changes). */
+int cmaes_restart_ipop(cmaes_t* h);
+
+/* Run Alg. 2 on the fused objective: generations until a stop bit fires,
+ * then restart with doubled lambda, until K > K_max, f_best < f_target or
+ * the evaluation budget is spent.  Writes the number of descents run into
+ * *descents (may be NULL).  Returns CMAES_OK when the loop ended normally. */
+int cmaes_ipop_run(cmaes_t* h, int* descents);
+
+/* Copy the state out (synchronises the stream).  See cmaes_state_t. */
+int cmaes_state(const cmaes_t* h, cmaes_state_t* out);
+
+/* Overwrite the state (test and resume hook).  n and lambda must match the
+ * handle.  Clears the stop bits and the f-history of the descent. */
+int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in);
+
+/* Device time of the phases of the last generation in microseconds, measured
+ * with HIP events when timing is enabled (cmaes_enable_timing).  out holds
+ * CMAES_NUM_PHASES doubles: sample, fitness, rank, update, covariance, eigen. */
+#define CMAES_NUM_PHASES 6
+int cmaes_enable_timing(cmaes_t* h, int on);
+int cmaes_phase_times(const cmaes_t* h, double* out);
+
+/* Thread-local message for the last failing call (never NULL). */
+const char* cmaes_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMAES_MI355X_H */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) IPOP-CMA-ES generation path.
+
+Python side of the C ABI in include/cmaes_mi355x.h (see ``binding``).  The
+package loads its in-tree HIP library on import and fails loudly if it is
+missing; nothing here computes a CMA-ES step on the host.
+"""
+
+from .binding import (CMAES, CmaesError, CmaesOptions, OBJECTIVES, PHASES, PRECISIONS, STOP_BITS,  # noqa: F401
+                      cmaes_ask, cmaes_create, cmaes_default_options, cmaes_destroy, cmaes_enable_timing,
+                      cmaes_generation, cmaes_generation_with_z, cmaes_get_options, cmaes_ipop_run,
+                      cmaes_last_error, cmaes_phase_times, cmaes_restart_ipop, cmaes_set_objective,
+                      cmaes_set_options, cmaes_set_state, cmaes_state, cmaes_tell, library, LIB_PATH)

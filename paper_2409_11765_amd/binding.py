@@ -1,0 +1,307 @@
+"""ctypes binding of libcmaes_mi355x.so (the C ABI in include/cmaes_mi355x.h).
+
+Argument marshalling only: every step of a generation runs in the library's
+HIP kernels.  Functions keep the C names; failures raise ``CmaesError`` with
+the library's message.  Host arrays are NumPy float64; matrices are passed in
+column-major order (column k = candidate k), so ``X[:, k]`` is point k.
+
+The library is loaded at import; a missing or unloadable library raises
+ImportError (there is no fallback implementation).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcmaes_mi355x.so")
+
+CMAES_OK, CMAES_EINVAL, CMAES_ENOMEM, CMAES_EDEVICE = 0, -1, -2, -3
+CMAES_ESTATE, CMAES_EKMAX, CMAES_ENUMERIC = -4, -5, -6
+CMAES_FP64, CMAES_MIXED, CMAES_MIXED_BF16X3 = 0, 1, 2
+OBJECTIVES = {"none": 0, "sphere": 1, "ellipsoid": 2, "rastrigin": 3}
+PRECISIONS = {"fp64": CMAES_FP64, "mixed": CMAES_MIXED, "mixed_bf16x3": CMAES_MIXED_BF16X3}
+STOP_BITS = ["tolhistfun", "tolfun", "tolx", "noeffectaxis", "noeffectcoord", "conditioncov",
+             "ftarget", "maxgen", "maxevals", "numeric"]
+NUM_PHASES = 6
+PHASES = ["sample", "fitness", "rank", "update", "covariance", "eigen"]
+
+
+class CmaesError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class CmaesOptions(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("eigen_interval", C.c_int32), ("k_max", C.c_int32),
+                ("max_gens", C.c_int32), ("max_evals", C.c_int64), ("box_lo", C.c_double),
+                ("box_hi", C.c_double), ("f_target", C.c_double), ("tol_hist_fun", C.c_double),
+                ("tol_fun", C.c_double), ("tol_x_factor", C.c_double), ("max_condition", C.c_double),
+                ("stream", C.c_void_p)]
+
+
+_PD = C.POINTER(C.c_double)
+_PI = C.POINTER(C.c_int32)
+
+
+class CmaesState(C.Structure):
+    _fields_ = [("n", C.c_int32), ("lambda_", C.c_int32), ("mu", C.c_int32), ("restart", C.c_int32),
+                ("gen", C.c_int64), ("evals", C.c_int64), ("total_evals", C.c_int64),
+                ("sigma", C.c_double), ("f_best", C.c_double), ("stop", C.c_uint32), ("kappa", C.c_int32),
+                ("eig_sweeps", C.c_int32), ("reserved", C.c_int32), ("m", _PD), ("C", _PD), ("B", _PD), ("D", _PD), ("p_sigma", _PD), ("p_c", _PD),
+                ("x_best", _PD), ("f", _PD), ("order", _PI)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    lib = C.CDLL(LIB_PATH)
+    H = C.c_void_p
+    sig = {
+        "cmaes_default_options": (C.c_int, [C.POINTER(CmaesOptions)]),
+        "cmaes_create": (H, [C.c_int, C.c_int, C.c_double, C.c_uint64]),
+        "cmaes_destroy": (None, [H]),
+        "cmaes_set_options": (C.c_int, [H, C.POINTER(CmaesOptions)]),
+        "cmaes_get_options": (C.c_int, [H, C.POINTER(CmaesOptions)]),
+        "cmaes_set_objective": (C.c_int, [H, C.c_int, _PD, _PD]),
+        "cmaes_generation": (C.c_int, [H]),
+        "cmaes_generation_with_z": (C.c_int, [H, _PD]),
+        "cmaes_ask": (C.c_int, [H, _PD]),
+        "cmaes_tell": (C.c_int, [H, _PD]),
+        "cmaes_restart_ipop": (C.c_int, [H]),
+        "cmaes_ipop_run": (C.c_int, [H, C.POINTER(C.c_int)]),
+        "cmaes_state": (C.c_int, [H, C.POINTER(CmaesState)]),
+        "cmaes_set_state": (C.c_int, [H, C.POINTER(CmaesState)]),
+        "cmaes_enable_timing": (C.c_int, [H, C.c_int]),
+        "cmaes_phase_times": (C.c_int, [H, _PD]),
+        "cmaes_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ["cmaes_default_options", "cmaes_create", "cmaes_destroy", "cmaes_set_options",
+            "cmaes_get_options", "cmaes_set_objective", "cmaes_generation", "cmaes_generation_with_z",
+            "cmaes_ask", "cmaes_tell", "cmaes_restart_ipop", "cmaes_ipop_run", "cmaes_state",
+            "cmaes_set_state", "cmaes_enable_timing", "cmaes_phase_times", "cmaes_last_error"]
+
+
+def library():
+    return _lib
+
+
+def cmaes_last_error() -> str:
+    return _lib.cmaes_last_error().decode()
+
+
+def _check(rc, allow=()):
+    if rc != CMAES_OK and rc not in allow:
+        raise CmaesError(rc, cmaes_last_error())
+    return rc
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_PD) if a is not None else None
+
+
+def _colmajor(a, shape):
+    a = np.asarray(a, dtype=np.float64)
+    if a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return np.asfortranarray(a)
+
+
+def cmaes_default_options() -> CmaesOptions:
+    o = CmaesOptions()
+    _check(_lib.cmaes_default_options(C.byref(o)))
+    return o
+
+
+def cmaes_create(n: int, lam: int, sigma0: float, seed: int):
+    h = _lib.cmaes_create(int(n), int(lam), float(sigma0), int(seed) & 0xFFFFFFFFFFFFFFFF)
+    if not h:
+        raise CmaesError(CMAES_EINVAL, cmaes_last_error())
+    return h
+
+
+def cmaes_destroy(h):
+    _lib.cmaes_destroy(h)
+
+
+def cmaes_set_options(h, opt: CmaesOptions):
+    _check(_lib.cmaes_set_options(h, C.byref(opt)))
+
+
+def cmaes_get_options(h) -> CmaesOptions:
+    o = CmaesOptions()
+    _check(_lib.cmaes_get_options(h, C.byref(o)))
+    return o
+
+
+def cmaes_set_objective(h, kind, n: int, R=None, xstar=None):
+    k = OBJECTIVES[kind] if isinstance(kind, str) else int(kind)
+    Rf = _colmajor(R, (n, n)) if R is not None else None
+    xs = np.ascontiguousarray(xstar, dtype=np.float64) if xstar is not None else None
+    _check(_lib.cmaes_set_objective(h, k, _dptr(Rf), _dptr(xs)))
+
+
+def cmaes_generation(h):
+    _check(_lib.cmaes_generation(h))
+
+
+def cmaes_generation_with_z(h, Z):
+    Zf = np.asfortranarray(np.asarray(Z, dtype=np.float64))
+    _check(_lib.cmaes_generation_with_z(h, _dptr(Zf)))
+
+
+def cmaes_ask(h, n: int, lam: int) -> np.ndarray:
+    X = np.empty((n, lam), dtype=np.float64, order="F")
+    _check(_lib.cmaes_ask(h, _dptr(X)))
+    return X
+
+
+def cmaes_tell(h, f):
+    fa = np.ascontiguousarray(f, dtype=np.float64)
+    _check(_lib.cmaes_tell(h, _dptr(fa)))
+
+
+def cmaes_restart_ipop(h) -> int:
+    return _check(_lib.cmaes_restart_ipop(h), allow=(CMAES_EKMAX,))
+
+
+def cmaes_ipop_run(h) -> int:
+    d = C.c_int(0)
+    _check(_lib.cmaes_ipop_run(h, C.byref(d)))
+    return d.value
+
+
+def cmaes_state(h, arrays: bool = True) -> dict:
+    s = CmaesState()
+    _check(_lib.cmaes_state(h, C.byref(s)))  # scalars first, to learn n and lambda
+    out = {"n": s.n, "lambda": s.lambda_, "mu": s.mu, "restart": s.restart, "gen": s.gen,
+           "evals": s.evals, "total_evals": s.total_evals, "sigma": s.sigma, "f_best": s.f_best,
+           "stop": s.stop, "kappa": s.kappa, "eig_sweeps": s.eig_sweeps}
+    if arrays:
+        n, lam = s.n, s.lambda_
+        bufs = {k: np.zeros(n) for k in ("m", "D", "p_sigma", "p_c", "x_best")}
+        bufs["C"] = np.zeros((n, n), order="F")
+        bufs["B"] = np.zeros((n, n), order="F")
+        bufs["f"] = np.zeros(lam)
+        order = np.zeros(lam, dtype=np.int32)
+        for k, v in bufs.items():
+            setattr(s, k, _dptr(v))
+        s.order = order.ctypes.data_as(_PI)
+        _check(_lib.cmaes_state(h, C.byref(s)))
+        out.update(bufs)
+        out["order"] = order
+        out["sigma"], out["f_best"], out["stop"] = s.sigma, s.f_best, s.stop
+    out["stop_names"] = [nm for i, nm in enumerate(STOP_BITS) if out["stop"] >> i & 1]
+    return out
+
+
+def cmaes_set_state(h, st: dict):
+    s = CmaesState()
+    s.n, s.lambda_ = int(st["n"]), int(st["lambda"])
+    s.gen, s.sigma = int(st.get("gen", 0)), float(st["sigma"])
+    keep = []
+    n = s.n
+    for k in ("m", "D", "p_sigma", "p_c"):
+        if st.get(k) is not None:
+            a = np.ascontiguousarray(st[k], dtype=np.float64)
+            keep.append(a)
+            setattr(s, k, _dptr(a))
+    for k in ("C", "B"):
+        if st.get(k) is not None:
+            a = _colmajor(st[k], (n, n))
+            keep.append(a)
+            setattr(s, k, _dptr(a))
+    _check(_lib.cmaes_set_state(h, C.byref(s)))
+
+
+def cmaes_enable_timing(h, on: bool = True):
+    _check(_lib.cmaes_enable_timing(h, 1 if on else 0))
+
+
+def cmaes_phase_times(h) -> dict:
+    out = np.zeros(NUM_PHASES)
+    _check(_lib.cmaes_phase_times(h, _dptr(out)))
+    return dict(zip(PHASES, out.tolist()))
+
+
+class CMAES:
+    """Owning wrapper of one handle (one descent plus its IPOP restarts)."""
+
+    def __init__(self, n, lam=0, sigma0=2.0, seed=0, precision="mixed", objective=None, R=None,
+                 xstar=None, **options):
+        self.h = cmaes_create(n, lam, sigma0, seed)
+        self.n = n
+        opt = cmaes_default_options()
+        opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        for k, v in options.items():
+            if k == "stream":
+                v = C.c_void_p(v) if v else None
+            setattr(opt, k, v)
+        cmaes_set_options(self.h, opt)
+        if objective is not None:
+            cmaes_set_objective(self.h, objective, n, R, xstar)
+
+    def close(self):
+        if self.h:
+            cmaes_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def lam(self):
+        return self.state(arrays=False)["lambda"]
+
+    def generation(self):
+        cmaes_generation(self.h)
+
+    def generation_with_z(self, Z):
+        cmaes_generation_with_z(self.h, Z)
+
+    def ask(self):
+        s = self.state(arrays=False)
+        return cmaes_ask(self.h, s["n"], s["lambda"])
+
+    def tell(self, f):
+        cmaes_tell(self.h, f)
+
+    def restart_ipop(self):
+        return cmaes_restart_ipop(self.h)
+
+    def ipop_run(self):
+        return cmaes_ipop_run(self.h)
+
+    def state(self, arrays=True):
+        return cmaes_state(self.h, arrays)
+
+    def set_state(self, st):
+        cmaes_set_state(self.h, st)
+
+    def enable_timing(self, on=True):
+        cmaes_enable_timing(self.h, on)
+
+    def phase_times(self):
+        return cmaes_phase_times(self.h)

@@ -1,0 +1,755 @@
+// C ABI: handle life cycle, the generation pipeline and the IPOP restart loop
+// (Alg. 1 and Alg. 2 of the paper).  See include/cmaes_mi355x.h.
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cmaes_mi355x.h"
+#include "internal.h"
+
+namespace cmx {
+
+static thread_local std::string g_err = "no error";
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+}  // namespace cmx
+
+using namespace cmx;
+
+namespace {
+
+// tutorial default parameters (positive weights), identical to the oracle's reading
+struct HostParams {
+  KParams kp;
+  std::vector<double> w, sqrtw;
+};
+
+HostParams make_params(int n, int lam, int kappa_opt) {
+  HostParams hp;
+  KParams& k = hp.kp;
+  k.n = n;
+  k.lam = lam;
+  k.mu = lam / 2;
+  hp.w.resize(k.mu);
+  hp.sqrtw.resize(k.mu);
+  double sw = 0.0;
+  for (int i = 0; i < k.mu; ++i) {
+    hp.w[i] = std::log((lam + 1) / 2.0) - std::log(static_cast<double>(i + 1));
+    sw += hp.w[i];
+  }
+  double s2 = 0.0;
+  for (int i = 0; i < k.mu; ++i) {
+    hp.w[i] /= sw;
+    s2 += hp.w[i] * hp.w[i];
+    hp.sqrtw[i] = std::sqrt(hp.w[i]);
+  }
+  k.mueff = 1.0 / s2;
+  k.cs = (k.mueff + 2.0) / (n + k.mueff + 5.0);
+  k.ds = 1.0 + 2.0 * std::max(0.0, std::sqrt((k.mueff - 1.0) / (n + 1.0)) - 1.0) + k.cs;
+  k.cc = (4.0 + k.mueff / n) / (n + 4.0 + 2.0 * k.mueff / n);
+  k.c1 = 2.0 / ((n + 1.3) * (n + 1.3) + k.mueff);
+  k.cmu = std::min(1.0 - k.c1, 2.0 * (k.mueff - 2.0 + 1.0 / k.mueff) / ((n + 2.0) * (n + 2.0) + k.mueff));
+  k.chin = std::sqrt(static_cast<double>(n)) * (1.0 - 1.0 / (4.0 * n) + 1.0 / (21.0 * n * n));
+  k.kappa = kappa_opt > 0 ? kappa_opt
+                          : std::max(1, static_cast<int>(std::ceil(1.0 / (10.0 * n * (k.c1 + k.cmu)))));
+  return hp;
+}
+
+int default_lambda(int n) { return 4 + static_cast<int>(std::floor(3.0 * std::log(static_cast<double>(n)))); }
+
+template <typename P>
+int dev_alloc(P** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes) != hipSuccess) return fail(CMAES_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  if (hipMemset(q, 0, bytes) != hipSuccess) return fail(CMAES_EDEVICE, "hipMemset failed");
+  *p = static_cast<P*>(q);
+  return 0;
+}
+
+template <typename P>
+void dev_free(P*& p) {
+  if (p) (void)hipFree(const_cast<void*>(static_cast<const void*>(p)));
+  p = nullptr;
+}
+
+}  // namespace
+
+struct cmaes {
+  int n = 0, lam = 0, lam0 = 0, K = 1, restart = 0, ldn = 0;
+  double sigma0 = 1.0;
+  uint64_t seed = 0;
+  cmaes_options_t opt{};
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  bool fp64 = false;
+  HostParams hp;
+  StopParams sp{};
+  int64_t gen = 0, evals = 0, total_evals = 0;
+  int obj_kind = CMAES_OBJ_NONE;
+  bool have_R = false, have_xstar = false;
+  std::vector<double> R_host, xstar_host;
+  bool ask_pending = false;
+  bool allocated = false;
+  int cap_lam = 0, cap_mu = 0, hist_cap = 0;
+  bool timing = false;
+  hipEvent_t ev[CMAES_NUM_PHASES + 1] = {};
+  double phase_us[CMAES_NUM_PHASES] = {};
+  int last_sweeps = 0;
+
+  // float64 state
+  DevScalars* sc = nullptr;
+  double *m = nullptr, *ps = nullptr, *pc = nullptr, *C = nullptr, *B = nullptr, *D = nullptr;
+  double *w = nullptr, *sqrtw = nullptr, *x_best = nullptr, *hist = nullptr, *d = nullptr;
+  double *xstar = nullptr, *Rd = nullptr, *yw = nullptr, *zw = nullptr;
+  double *part_yw = nullptr, *part_zw = nullptr, *part_bz = nullptr, *f = nullptr, *X = nullptr;
+  int32_t* order = nullptr;
+  // sampling-precision buffers
+  void *BD = nullptr, *Rt = nullptr, *Z = nullptr, *Y = nullptr, *Ysel = nullptr, *coef = nullptr;
+  void* partial = nullptr;
+  void* syrk_work = nullptr;
+  double* u = nullptr;
+  EigWork ew{};
+};
+
+namespace {
+
+size_t esz(const cmaes* h) { return h->fp64 ? sizeof(double) : sizeof(float); }
+
+void free_pop_buffers(cmaes* h) {
+  dev_free(h->Z);
+  dev_free(h->Y);
+  dev_free(h->Ysel);
+  dev_free(h->partial);
+  dev_free(h->part_yw);
+  dev_free(h->part_zw);
+  dev_free(h->f);
+  dev_free(h->X);
+  dev_free(h->order);
+  dev_free(h->w);
+  dev_free(h->sqrtw);
+  dev_free(h->hist);
+  dev_free(h->syrk_work);
+  h->cap_lam = h->cap_mu = h->hist_cap = 0;
+}
+
+void free_all(cmaes* h) {
+  free_pop_buffers(h);
+  dev_free(h->sc);
+  dev_free(h->m);
+  dev_free(h->ps);
+  dev_free(h->pc);
+  dev_free(h->C);
+  dev_free(h->B);
+  dev_free(h->D);
+  dev_free(h->x_best);
+  dev_free(h->d);
+  dev_free(h->u);
+  dev_free(h->xstar);
+  dev_free(h->Rd);
+  dev_free(h->yw);
+  dev_free(h->zw);
+  dev_free(h->part_bz);
+  dev_free(h->BD);
+  dev_free(h->Rt);
+  dev_free(h->coef);
+  dev_free(h->ew.A);
+  dev_free(h->ew.V);
+  dev_free(h->ew.Q);
+  dev_free(h->ew.T);
+  dev_free(h->ew.flags);
+  dev_free(h->ew.evals);
+  dev_free(h->ew.perm);
+  dev_free(h->ew.sign);
+  h->allocated = false;
+}
+
+int hist_len_for(int n, int lam) { return 10 + static_cast<int>(std::ceil(30.0 * n / lam)); }
+
+void refresh_stop_params(cmaes* h) {
+  StopParams& s = h->sp;
+  s.tol_hist_fun = h->opt.tol_hist_fun;
+  s.tol_fun = h->opt.tol_fun;
+  s.tolx = h->opt.tol_x_factor * h->sigma0;
+  s.max_condition = h->opt.max_condition;
+  s.f_target = h->opt.f_target;
+  s.max_gens = h->opt.max_gens;
+  s.max_evals = 0;  // the evaluation budget is a whole-run limit checked by the host loop
+  s.hist_len = hist_len_for(h->n, h->lam);
+}
+
+// population-size dependent buffers
+int alloc_pop(cmaes* h) {
+  const int n = h->n, ldn = h->ldn, lam = h->lam, mu = h->hp.kp.mu;
+  if (lam <= h->cap_lam && mu <= h->cap_mu && hist_len_for(n, lam) <= h->hist_cap) return 0;
+  free_pop_buffers(h);
+  const size_t e = esz(h);
+  int rc = 0;
+  const int row_tiles = ceil_div(n, 64);
+  if ((rc = dev_alloc(&h->Z, e * ldn * lam)) || (rc = dev_alloc(&h->Y, e * ldn * lam)) ||
+      (rc = dev_alloc(&h->Ysel, e * ldn * mu)) || (rc = dev_alloc(&h->partial, 8ull * row_tiles * lam)) ||
+      (rc = dev_alloc(&h->part_yw, 8ull * ceil_div(mu, 64) * n)) ||
+      (rc = dev_alloc(&h->part_zw, 8ull * ceil_div(mu, 64) * n)) || (rc = dev_alloc(&h->f, 8ull * lam)) ||
+      (rc = dev_alloc(&h->order, 4ull * 2 * lam)) || (rc = dev_alloc(&h->w, 8ull * mu)) ||
+      (rc = dev_alloc(&h->sqrtw, 8ull * mu)) || (rc = dev_alloc(&h->hist, 8ull * hist_len_for(n, lam))))
+    return rc;
+  {
+    int ntl, splits, kspan;
+    size_t we;
+    syrk_plan(h->fp64, n, mu, &ntl, &splits, &kspan, &we);
+    if ((rc = dev_alloc(&h->syrk_work, e * we))) return rc;
+  }
+  h->cap_lam = lam;
+  h->cap_mu = mu;
+  h->hist_cap = hist_len_for(n, lam);
+  return 0;
+}
+
+int alloc_fixed(cmaes* h) {
+  const int n = h->n, ldn = h->ldn;
+  const size_t e = esz(h);
+  const size_t nn = static_cast<size_t>(ldn) * n;
+  const int N = round_up(n, 32);
+  h->ew.N = N;
+  int rc = 0;
+  if ((rc = dev_alloc(&h->sc, sizeof(DevScalars))) || (rc = dev_alloc(&h->m, 8ull * ldn)) ||
+      (rc = dev_alloc(&h->ps, 8ull * ldn)) || (rc = dev_alloc(&h->pc, 8ull * ldn)) ||
+      (rc = dev_alloc(&h->C, 8 * nn)) || (rc = dev_alloc(&h->B, 8 * nn)) || (rc = dev_alloc(&h->D, 8ull * ldn)) ||
+      (rc = dev_alloc(&h->x_best, 8ull * ldn)) || (rc = dev_alloc(&h->d, 8ull * ldn)) ||
+      (rc = dev_alloc(&h->u, 8ull * ldn)) ||
+      (rc = dev_alloc(&h->xstar, 8ull * ldn)) || (rc = dev_alloc(&h->Rd, 8 * nn)) ||
+      (rc = dev_alloc(&h->yw, 8ull * ldn)) || (rc = dev_alloc(&h->zw, 8ull * ldn)) ||
+      (rc = dev_alloc(&h->part_bz, 8ull * ceil_div(n, 64) * n)) || (rc = dev_alloc(&h->BD, e * nn)) ||
+      (rc = dev_alloc(&h->Rt, e * nn)) || (rc = dev_alloc(&h->coef, e * ldn)) ||
+      (rc = dev_alloc(&h->ew.A, 8ull * N * N)) || (rc = dev_alloc(&h->ew.V, 8ull * N * N)) ||
+      (rc = dev_alloc(&h->ew.Q, 8ull * (N / 32) * 32 * 32)) || (rc = dev_alloc(&h->ew.T, 8 * nn)) ||
+      (rc = dev_alloc(&h->ew.flags, 16)) || (rc = dev_alloc(&h->ew.evals, 8ull * 3 * N)) ||
+      (rc = dev_alloc(&h->ew.perm, 4ull * N)) || (rc = dev_alloc(&h->ew.sign, 8ull * N)))
+    return rc;
+  return 0;
+}
+
+int upload_params(cmaes* h) {
+  CMX_HIP(hipMemcpyAsync(h->w, h->hp.w.data(), 8 * h->hp.w.size(), hipMemcpyHostToDevice, h->st));
+  CMX_HIP(hipMemcpyAsync(h->sqrtw, h->hp.sqrtw.data(), 8 * h->hp.sqrtw.size(), hipMemcpyHostToDevice, h->st));
+  CMX_HIP(hipStreamSynchronize(h->st));
+  return 0;
+}
+
+// objective-dependent device data in the sampling precision
+int upload_objective_derived(cmaes* h);
+
+int upload_objective(cmaes* h) {
+  const int n = h->n;
+  if (h->have_R)
+    CMX_HIP(hipMemcpy2D(h->Rd, 8ull * h->ldn, h->R_host.data(), 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
+  if (h->have_xstar) CMX_HIP(hipMemcpy(h->xstar, h->xstar_host.data(), 8ull * n, hipMemcpyHostToDevice));
+  return upload_objective_derived(h);
+}
+
+int upload_objective_derived(cmaes* h) {
+  const int n = h->n;
+  std::vector<double> coef(n, 1.0);
+  if (n > 1)
+    for (int i = 0; i < n; ++i) coef[i] = std::pow(10.0, 6.0 * i / (n - 1));
+  if (h->fp64) {
+    CMX_HIP(hipMemcpy(h->coef, coef.data(), 8ull * n, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> cf(coef.begin(), coef.end());
+    CMX_HIP(hipMemcpy(h->coef, cf.data(), 4ull * n, hipMemcpyHostToDevice));
+  }
+  if (h->have_R) {
+    CMX_HIP(launch_to_precision(h->st, h->fp64, h->Rd, h->ldn, h->Rt, h->ldn, n, n));
+    CMX_HIP(hipStreamSynchronize(h->st));
+  }
+  return 0;
+}
+
+// fresh descent: Alg. 2 initialisation line
+int init_descent(cmaes* h, bool fresh) {
+  const int n = h->n;
+  DevScalars s{};
+  CMX_HIP(hipMemcpy(&s, h->sc, sizeof(s), hipMemcpyDeviceToHost));
+  const double f_best = fresh ? HUGE_VAL : s.f_best;
+  std::memset(&s, 0, sizeof(s));
+  s.sigma = h->sigma0;
+  s.sigma0 = h->sigma0;
+  s.f_best = f_best;
+  s.eig_ok = 1;
+  CMX_HIP(hipMemcpy(h->sc, &s, sizeof(s), hipMemcpyHostToDevice));
+  CMX_HIP(launch_init_mean(h->st, h->m, n, h->opt.box_lo, h->opt.box_hi, h->seed, static_cast<uint32_t>(h->restart)));
+  CMX_HIP(hipMemsetAsync(h->ps, 0, 8ull * h->ldn, h->st));
+  CMX_HIP(hipMemsetAsync(h->pc, 0, 8ull * h->ldn, h->st));
+  CMX_HIP(launch_set_identity(h->st, h->C, n, h->ldn));
+  CMX_HIP(launch_set_identity(h->st, h->B, n, h->ldn));
+  std::vector<double> ones(n, 1.0);
+  CMX_HIP(hipMemcpyAsync(h->D, ones.data(), 8ull * n, hipMemcpyHostToDevice, h->st));
+  CMX_HIP(launch_to_precision(h->st, h->fp64, h->B, h->ldn, h->BD, h->ldn, n, n));
+  CMX_HIP(hipStreamSynchronize(h->st));
+  h->gen = 0;
+  h->evals = 0;
+  h->ask_pending = false;
+  refresh_stop_params(h);
+  return 0;
+}
+
+int ensure_ready(cmaes* h) {
+  if (h->allocated) return alloc_pop(h);
+  h->fp64 = (h->opt.precision == CMAES_FP64);
+  int rc;
+  if ((rc = alloc_fixed(h)) || (rc = alloc_pop(h))) {
+    free_all(h);
+    return rc;
+  }
+  h->allocated = true;
+  if ((rc = upload_params(h)) || (rc = init_descent(h, true))) return rc;
+  if (h->obj_kind != CMAES_OBJ_NONE && (rc = upload_objective(h))) return rc;
+  return 0;
+}
+
+void rec(cmaes* h, int i) {
+  if (h->timing) (void)hipEventRecord(h->ev[i], h->st);
+}
+
+int phase_sample(cmaes* h, const double* Zhost) {
+  const int n = h->n, lam = h->lam, ldn = h->ldn;
+  rec(h, 0);
+  if (Zhost) {
+    // caller-supplied z: stage as float64 then convert to the sampling precision
+    if (h->fp64) {
+      CMX_HIP(hipMemcpy2DAsync(h->Z, 8ull * ldn, Zhost, 8ull * n, 8ull * n, lam, hipMemcpyHostToDevice, h->st));
+    } else {
+      std::vector<float> zf(static_cast<size_t>(ldn) * lam, 0.0f);
+      for (int k = 0; k < lam; ++k)
+        for (int i = 0; i < n; ++i) zf[static_cast<size_t>(k) * ldn + i] = static_cast<float>(Zhost[static_cast<size_t>(k) * n + i]);
+      CMX_HIP(hipMemcpyAsync(h->Z, zf.data(), 4ull * zf.size(), hipMemcpyHostToDevice, h->st));
+      CMX_HIP(hipStreamSynchronize(h->st));
+    }
+  } else {
+    CMX_HIP(launch_normals(h->st, h->Z, h->fp64, ldn, n, lam, h->seed, static_cast<uint32_t>(h->restart), h->sc));
+  }
+  CMX_HIP(launch_sample_gemm(h->st, h->fp64, n, lam, h->BD, ldn, h->Z, ldn, h->Y, ldn));
+  rec(h, 1);
+  return 0;
+}
+
+int phase_fitness(cmaes* h) {
+  const int n = h->n, lam = h->lam, ldn = h->ldn;
+  CMX_HIP(launch_shift(h->st, n, h->have_R ? h->Rd : nullptr, ldn, h->m, h->have_xstar ? h->xstar : nullptr, h->u,
+                       h->part_bz, h->d));
+  FitnessArgs fa{h->obj_kind, h->d, h->coef, h->sc, h->partial, lam};
+  int tiles = 0;
+  if (h->have_R)
+    CMX_HIP(launch_fitness_gemm(h->st, h->fp64, n, lam, h->Rt, ldn, h->Y, ldn, fa, &tiles));
+  else
+    CMX_HIP(launch_fitness_direct(h->st, h->fp64, n, lam, h->Y, ldn, fa, &tiles));
+  CMX_HIP(launch_fitness_reduce(h->st, h->fp64, h->obj_kind, n, lam, h->partial, lam, tiles, h->f));
+  return 0;
+}
+
+int phase_update(cmaes* h) {
+  const int n = h->n, lam = h->lam, ldn = h->ldn, mu = h->hp.kp.mu;
+  rec(h, 2);
+  CMX_HIP(launch_rank(h->st, h->f, lam, h->order));
+  CMX_HIP(launch_best(h->st, h->fp64, n, lam, h->f, h->order, h->Y, ldn, h->m, h->x_best, h->hist, h->sp.hist_len, h->sc));
+  rec(h, 3);
+  int nch = 0, nchb = 0;
+  CMX_HIP(launch_recombine(h->st, h->fp64, n, lam, mu, h->Y, h->Z, ldn, h->order, h->w, h->sqrtw, h->Ysel, ldn,
+                           h->part_yw, h->part_zw, &nch));
+  CMX_HIP(launch_reduce_yz(h->st, n, nch, h->part_yw, h->part_zw, h->yw, h->zw));
+  CMX_HIP(launch_matvec(h->st, n, h->B, ldn, h->zw, h->part_bz, &nchb));
+  CMX_HIP(launch_vec_update(h->st, h->hp.kp, nchb, h->part_bz, h->yw, h->m, h->ps, h->pc, h->sc));
+  rec(h, 4);
+  CMX_HIP(launch_syrk_update(h->st, h->fp64, n, mu, h->Ysel, ldn, h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc,
+                             h->syrk_work));
+  rec(h, 5);
+  h->gen += 1;
+  h->evals += lam;
+  h->total_evals += lam;
+  if (h->gen % h->hp.kp.kappa == 0) {
+    const int rc = eigen_solve(h->st, n, h->C, ldn, h->B, ldn, h->D, h->BD, h->fp64, ldn, h->ew, h->sc, 30,
+                               &h->last_sweeps);
+    if (rc == CMAES_ENUMERIC) {
+      // no usable decomposition: report it through the ConditionCov stop bit
+      const int32_t zero = 0;
+      CMX_HIP(hipMemcpyAsync(reinterpret_cast<char*>(h->sc) + offsetof(DevScalars, eig_ok), &zero, sizeof(zero),
+                             hipMemcpyHostToDevice, h->st));
+      CMX_HIP(hipStreamSynchronize(h->st));
+    } else if (rc != 0) {
+      return rc;
+    }
+  }
+  CMX_HIP(launch_stop(h->st, h->hp.kp, h->sp, h->m, h->C, ldn, h->B, ldn, h->D, h->pc, h->hist, h->sc));
+  rec(h, 6);
+  if (h->timing) {
+    CMX_HIP(hipEventSynchronize(h->ev[6]));
+    float ms = 0.f;
+    // phases: sample | fitness | rank | update | covariance | eigen
+    const int a[CMAES_NUM_PHASES] = {0, 1, 2, 3, 4, 5};
+    const int b[CMAES_NUM_PHASES] = {1, 2, 3, 4, 5, 6};
+    for (int i = 0; i < CMAES_NUM_PHASES; ++i) {
+      (void)hipEventElapsedTime(&ms, h->ev[a[i]], h->ev[b[i]]);
+      h->phase_us[i] = 1000.0 * ms;
+    }
+  }
+  return 0;
+}
+
+int check(const cmaes* h) {
+  if (!h) return fail(CMAES_EINVAL, "null handle");
+  return 0;
+}
+
+int read_scalars(const cmaes* h, DevScalars* s) {
+  CMX_HIP(hipMemcpyAsync(s, h->sc, sizeof(*s), hipMemcpyDeviceToHost, h->st));
+  CMX_HIP(hipStreamSynchronize(h->st));
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cmaes_default_options(cmaes_options_t* o) {
+  if (!o) return fail(CMAES_EINVAL, "null options");
+  std::memset(o, 0, sizeof(*o));
+  o->precision = CMAES_MIXED;
+  o->eigen_interval = 0;
+  o->k_max = 256;
+  o->max_gens = 0;
+  o->max_evals = 0;
+  o->box_lo = -4.0;
+  o->box_hi = 4.0;
+  o->f_target = 1e-8;
+  o->tol_hist_fun = 1e-12;
+  o->tol_fun = 1e-12;
+  o->tol_x_factor = 1e-12;
+  o->max_condition = 1e14;
+  o->stream = nullptr;
+  return CMAES_OK;
+}
+
+const char* cmaes_last_error(void) { return g_err.c_str(); }
+
+cmaes_t* cmaes_create(int n, int lambda, double sigma0, uint64_t seed) {
+  if (n < 1) {
+    set_error("n must be >= 1");
+    return nullptr;
+  }
+  if (lambda <= 0) lambda = default_lambda(n);
+  if (lambda < 2) {
+    set_error("lambda must be >= 2");
+    return nullptr;
+  }
+  if (!(sigma0 > 0.0) || !std::isfinite(sigma0)) {
+    set_error("sigma0 must be positive and finite");
+    return nullptr;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    set_error("no HIP device available");
+    return nullptr;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    set_error(std::string("this library is built for gfx950, found ") + prop.gcnArchName);
+    return nullptr;
+  }
+  cmaes* h = new (std::nothrow) cmaes();
+  if (!h) {
+    set_error("host allocation failed");
+    return nullptr;
+  }
+  h->n = n;
+  h->lam = h->lam0 = lambda;
+  h->sigma0 = sigma0;
+  h->seed = seed;
+  h->ldn = round_up(n, 4);
+  cmaes_default_options(&h->opt);
+  if (hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking) != hipSuccess) {
+    set_error("hipStreamCreate failed");
+    delete h;
+    return nullptr;
+  }
+  h->own_stream = true;
+  for (auto& e : h->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      set_error("hipEventCreate failed");
+      cmaes_destroy(h);
+      return nullptr;
+    }
+  h->hp = make_params(n, lambda, 0);
+  refresh_stop_params(h);
+  return h;
+}
+
+void cmaes_destroy(cmaes_t* h) {
+  if (!h) return;
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  free_all(h);
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
+  delete h;
+}
+
+int cmaes_set_options(cmaes_t* h, const cmaes_options_t* o) {
+  if (int rc = check(h)) return rc;
+  if (!o) return fail(CMAES_EINVAL, "null options");
+  if (o->precision < CMAES_FP64 || o->precision > CMAES_MIXED_BF16X3)
+    return fail(CMAES_EINVAL, "unknown precision");
+  if (o->k_max < 1 || !(o->box_hi > o->box_lo) || o->eigen_interval < 0 || o->max_gens < 0 || o->max_evals < 0)
+    return fail(CMAES_EINVAL, "invalid option value");
+  const bool started = h->allocated && (h->gen > 0 || h->restart > 0);
+  const bool prec_change = (o->precision == CMAES_FP64) != (h->opt.precision == CMAES_FP64);
+  if (started && (prec_change || o->stream != h->opt.stream))
+    return fail(CMAES_ESTATE, "precision and stream can only change before the first generation");
+  if (h->allocated && prec_change) free_all(h);  // re-created lazily in the new precision
+  const bool box_change = o->box_lo != h->opt.box_lo || o->box_hi != h->opt.box_hi;
+  if (o->stream != h->opt.stream) {
+    if (h->st) (void)hipStreamSynchronize(h->st);
+    if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
+    if (o->stream) {
+      h->st = static_cast<hipStream_t>(o->stream);
+      h->own_stream = false;
+    } else {
+      CMX_HIP(hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking));
+      h->own_stream = true;
+    }
+  }
+  h->opt = *o;
+  h->hp = make_params(h->n, h->lam, o->eigen_interval);
+  refresh_stop_params(h);
+  if (h->allocated) {
+    if (int rc = alloc_pop(h)) return rc;
+    if (int rc = upload_params(h)) return rc;
+    if (!started && box_change) return init_descent(h, true);
+    if (h->obj_kind != CMAES_OBJ_NONE) return upload_objective_derived(h);
+  }
+  return CMAES_OK;
+}
+
+int cmaes_get_options(const cmaes_t* h, cmaes_options_t* o) {
+  if (int rc = check(h)) return rc;
+  if (!o) return fail(CMAES_EINVAL, "null options");
+  *o = h->opt;
+  return CMAES_OK;
+}
+
+int cmaes_set_objective(cmaes_t* h, int kind, const double* R, const double* xstar) {
+  if (int rc = check(h)) return rc;
+  if (kind < CMAES_OBJ_NONE || kind > CMAES_OBJ_RASTRIGIN) return fail(CMAES_EINVAL, "unknown objective");
+  const size_t n = static_cast<size_t>(h->n);
+  h->have_R = R != nullptr;
+  h->have_xstar = xstar != nullptr;
+  h->R_host.assign(R ? R : R, R ? R + n * n : R);
+  h->xstar_host.assign(xstar ? xstar : xstar, xstar ? xstar + n : xstar);
+  h->obj_kind = kind;
+  if (!h->allocated) return ensure_ready(h);
+  if (kind == CMAES_OBJ_NONE) return CMAES_OK;
+  CMX_HIP(hipStreamSynchronize(h->st));
+  return upload_objective(h);
+}
+
+int cmaes_generation(cmaes_t* h) {
+  if (int rc = check(h)) return rc;
+  if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "no fused objective set (use ask/tell)");
+  if (int rc = ensure_ready(h)) return rc;
+  if (int rc = phase_sample(h, nullptr)) return rc;
+  if (int rc = phase_fitness(h)) return rc;
+  return phase_update(h);
+}
+
+int cmaes_generation_with_z(cmaes_t* h, const double* Z) {
+  if (int rc = check(h)) return rc;
+  if (!Z) return fail(CMAES_EINVAL, "null Z");
+  if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "no fused objective set");
+  if (int rc = ensure_ready(h)) return rc;
+  if (int rc = phase_sample(h, Z)) return rc;
+  if (int rc = phase_fitness(h)) return rc;
+  return phase_update(h);
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+__global__ void k_points(int n, int lam, const double* __restrict__ m, const T* __restrict__ Y, int ldy,
+                         const DevScalars* __restrict__ sc, double* __restrict__ X) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * lam) return;
+  const int k = static_cast<int>(idx / n), i = static_cast<int>(idx % n);
+  X[idx] = m[i] + sc->sigma * static_cast<double>(Y[static_cast<int64_t>(k) * ldy + i]);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cmaes_ask(cmaes_t* h, double* X) {
+  if (int rc = check(h)) return rc;
+  if (!X) return fail(CMAES_EINVAL, "null X");
+  if (int rc = ensure_ready(h)) return rc;
+  const int n = h->n, lam = h->lam;
+  if (!h->X || h->cap_lam < lam) {
+    dev_free(h->X);
+    if (int rc = dev_alloc(&h->X, 8ull * n * h->cap_lam)) return rc;
+  }
+  if (int rc = phase_sample(h, nullptr)) return rc;
+  const int64_t total = static_cast<int64_t>(n) * lam;
+  const int blocks = static_cast<int>((total + 255) / 256);
+  if (h->fp64)
+    k_points<double><<<blocks, 256, 0, h->st>>>(n, lam, h->m, static_cast<const double*>(h->Y), h->ldn, h->sc, h->X);
+  else
+    k_points<float><<<blocks, 256, 0, h->st>>>(n, lam, h->m, static_cast<const float*>(h->Y), h->ldn, h->sc, h->X);
+  CMX_HIP(hipGetLastError());
+  CMX_HIP(hipMemcpyAsync(X, h->X, 8ull * total, hipMemcpyDeviceToHost, h->st));
+  CMX_HIP(hipStreamSynchronize(h->st));
+  h->ask_pending = true;
+  return CMAES_OK;
+}
+
+int cmaes_tell(cmaes_t* h, const double* f) {
+  if (int rc = check(h)) return rc;
+  if (!f) return fail(CMAES_EINVAL, "null f");
+  if (!h->ask_pending) return fail(CMAES_ESTATE, "cmaes_tell without a pending cmaes_ask");
+  CMX_HIP(hipMemcpyAsync(h->f, f, 8ull * h->lam, hipMemcpyHostToDevice, h->st));
+  h->ask_pending = false;
+  return phase_update(h);
+}
+
+int cmaes_restart_ipop(cmaes_t* h) {
+  if (int rc = check(h)) return rc;
+  if (2 * h->K > h->opt.k_max) return fail(CMAES_EKMAX, "K would exceed K_max");
+  if (int rc = ensure_ready(h)) return rc;
+  CMX_HIP(hipStreamSynchronize(h->st));
+  h->K *= 2;
+  h->restart += 1;
+  h->lam = h->K * h->lam0;
+  h->hp = make_params(h->n, h->lam, h->opt.eigen_interval);
+  if (int rc = alloc_pop(h)) return rc;
+  if (int rc = upload_params(h)) return rc;
+  return init_descent(h, false);
+}
+
+int cmaes_ipop_run(cmaes_t* h, int* descents) {
+  if (int rc = check(h)) return rc;
+  if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "no fused objective set");
+  int count = 1;
+  for (;;) {
+    if (int rc = cmaes_generation(h)) return rc;
+    DevScalars s;
+    if (int rc = read_scalars(h, &s)) return rc;
+    const bool budget = h->opt.max_evals > 0 && h->total_evals >= h->opt.max_evals;
+    if (s.stop || budget) {
+      if (s.f_best < h->opt.f_target || budget) break;
+      const int rc = cmaes_restart_ipop(h);
+      if (rc == CMAES_EKMAX) break;
+      if (rc) return rc;
+      ++count;
+    }
+  }
+  if (descents) *descents = count;
+  return CMAES_OK;
+}
+
+int cmaes_state(const cmaes_t* hc, cmaes_state_t* out) {
+  if (int rc = check(hc)) return rc;
+  if (!out) return fail(CMAES_EINVAL, "null state");
+  cmaes_t* h = const_cast<cmaes_t*>(hc);
+  if (int rc = ensure_ready(h)) return rc;
+  DevScalars s;
+  if (int rc = read_scalars(h, &s)) return rc;
+  const int n = h->n, ldn = h->ldn;
+  out->n = n;
+  out->lambda = h->lam;
+  out->mu = h->hp.kp.mu;
+  out->restart = h->restart;
+  out->gen = h->gen;
+  out->evals = h->evals;
+  out->total_evals = h->total_evals;
+  out->sigma = s.sigma;
+  out->f_best = s.f_best;
+  out->stop = s.stop;
+  out->kappa = h->hp.kp.kappa;
+  out->eig_sweeps = h->last_sweeps;
+  out->reserved = 0;
+  auto vec = [&](double* dst, const double* src) -> int {
+    if (dst) CMX_HIP(hipMemcpy(dst, src, 8ull * n, hipMemcpyDeviceToHost));
+    return 0;
+  };
+  auto mat = [&](double* dst, const double* src) -> int {
+    if (dst) CMX_HIP(hipMemcpy2D(dst, 8ull * n, src, 8ull * ldn, 8ull * n, n, hipMemcpyDeviceToHost));
+    return 0;
+  };
+  int rc;
+  if ((rc = vec(out->m, h->m)) || (rc = vec(out->p_sigma, h->ps)) || (rc = vec(out->p_c, h->pc)) ||
+      (rc = vec(out->D, h->D)) || (rc = vec(out->x_best, h->x_best)) || (rc = mat(out->C, h->C)) ||
+      (rc = mat(out->B, h->B)))
+    return rc;
+  if (out->f) CMX_HIP(hipMemcpy(out->f, h->f, 8ull * h->lam, hipMemcpyDeviceToHost));
+  if (out->order) CMX_HIP(hipMemcpy(out->order, h->order, 4ull * h->lam, hipMemcpyDeviceToHost));
+  return CMAES_OK;
+}
+
+int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in) {
+  if (int rc = check(h)) return rc;
+  if (!in) return fail(CMAES_EINVAL, "null state");
+  if (in->n != h->n || in->lambda != h->lam) return fail(CMAES_EINVAL, "n / lambda do not match the handle");
+  if (!(in->sigma > 0.0) || in->gen < 0) return fail(CMAES_EINVAL, "sigma must be > 0 and gen >= 0");
+  if (int rc = ensure_ready(h)) return rc;
+  const int n = h->n, ldn = h->ldn;
+  CMX_HIP(hipStreamSynchronize(h->st));
+  DevScalars s;
+  CMX_HIP(hipMemcpy(&s, h->sc, sizeof(s), hipMemcpyDeviceToHost));
+  s.sigma = in->sigma;
+  s.gen = in->gen;
+  s.stop = 0;
+  s.hist_count = 0;
+  s.eig_ok = 1;
+  CMX_HIP(hipMemcpy(h->sc, &s, sizeof(s), hipMemcpyHostToDevice));
+  h->gen = in->gen;
+  if (in->m) CMX_HIP(hipMemcpy(h->m, in->m, 8ull * n, hipMemcpyHostToDevice));
+  if (in->p_sigma) CMX_HIP(hipMemcpy(h->ps, in->p_sigma, 8ull * n, hipMemcpyHostToDevice));
+  if (in->p_c) CMX_HIP(hipMemcpy(h->pc, in->p_c, 8ull * n, hipMemcpyHostToDevice));
+  if (in->D) CMX_HIP(hipMemcpy(h->D, in->D, 8ull * n, hipMemcpyHostToDevice));
+  if (in->C) CMX_HIP(hipMemcpy2D(h->C, 8ull * ldn, in->C, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
+  if (in->B) CMX_HIP(hipMemcpy2D(h->B, 8ull * ldn, in->B, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
+  if (in->B || in->D) {
+    // B D in the sampling precision
+    std::vector<double> Bh(static_cast<size_t>(n) * n), Dh(n);
+    CMX_HIP(hipMemcpy2D(Bh.data(), 8ull * n, h->B, 8ull * ldn, 8ull * n, n, hipMemcpyDeviceToHost));
+    CMX_HIP(hipMemcpy(Dh.data(), h->D, 8ull * n, hipMemcpyDeviceToHost));
+    for (int c = 0; c < n; ++c)
+      for (int r = 0; r < n; ++r) Bh[static_cast<size_t>(c) * n + r] *= Dh[c];
+    CMX_HIP(hipMemcpy2D(h->ew.T, 8ull * ldn, Bh.data(), 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
+    CMX_HIP(launch_to_precision(h->st, h->fp64, h->ew.T, ldn, h->BD, ldn, n, n));
+    CMX_HIP(hipStreamSynchronize(h->st));
+  }
+  h->ask_pending = false;
+  return CMAES_OK;
+}
+
+int cmaes_enable_timing(cmaes_t* h, int on) {
+  if (int rc = check(h)) return rc;
+  h->timing = on != 0;
+  return CMAES_OK;
+}
+
+int cmaes_phase_times(const cmaes_t* h, double* out) {
+  if (int rc = check(h)) return rc;
+  if (!out) return fail(CMAES_EINVAL, "null output");
+  for (int i = 0; i < CMAES_NUM_PHASES; ++i) out[i] = h->phase_us[i];
+  return CMAES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,524 @@
+// MFMA tile GEMMs of the generation (gfx950 matrix cores).
+//
+//  * Sampling, Sec. 3.1 / eq. (1): Y = (B D) [z_1 .. z_lambda].  The paper's
+//    m-matrix is never formed: kernels that need x use m + sigma y.
+//  * Fitness: the objective terms of u = R (x - x*) = d + sigma (R y), with
+//    d = R (m - x*) in float64, are reduced inside the epilogue of R * Y, so
+//    the n x lambda matrix R Y never reaches HBM.  Unrotated objectives reduce
+//    the terms of d + sigma y straight from Y.
+//  * Covariance, eq. (3): C <- a C + c1 pc pc^T + cmu * Yhat Yhat^T with
+//    Yhat = [sqrt(w_i) y_{i:lambda}] (n x mu); only lower tiles are computed
+//    and the epilogue mirrors them (SYRK).
+//  * FP64 products of the eigensolver (B^T C B, B V).
+//
+// float: v_mfma_f32_32x32x2_f32, 128x128 block tile, 4 waves of 64x64.
+// double: v_mfma_f64_16x16x4_f64, 64x64 block tile, 4 waves of 32x32.
+// Operands are staged through LDS in k-major layout (m / n contiguous) so
+// every MFMA operand read is a conflict-free row of 32 (16) consecutive
+// elements; global loads are 16-byte vectors along the contiguous dimension.
+// Reductions inside epilogues run in a fixed order (no atomics), so results
+// are bitwise reproducible.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace cmx {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Cfg;
+template <>
+struct Cfg<float> {
+  static constexpr int BM = 128, BN = 128, BK = 16;
+  static constexpr int MB = 32;  // MFMA block edge
+  static constexpr int KS = 2;   // MFMA k per instruction
+  static constexpr int WM = 64, WN = 64;
+  static constexpr int VEC = 4;  // elements per 16-byte load
+  static constexpr int NACC = 16;
+  static constexpr int PAD = 4;
+  using acc_t = floatx16;
+  using vec_t = float4;
+  __device__ static acc_t mfma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  // row of accumulator element r held by lane l (column = l % 32)
+  __device__ static int acc_row(int r, int l) { return (r >> 2) * 8 + (l >> 5) * 4 + (r & 3); }
+};
+template <>
+struct Cfg<double> {
+  static constexpr int BM = 64, BN = 64, BK = 16;
+  static constexpr int MB = 16;
+  static constexpr int KS = 4;
+  static constexpr int WM = 32, WN = 32;
+  static constexpr int VEC = 2;
+  static constexpr int NACC = 4;
+  static constexpr int PAD = 2;
+  using acc_t = doublex4;
+  using vec_t = double2;
+  __device__ static acc_t mfma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // v_mfma_f64_16x16x4_f64 keeps rows lane/16, lane/16 + 4, + 8, + 12 in a lane
+  __device__ static int acc_row(int r, int l) { return (l >> 4) + 4 * r; }
+};
+
+template <typename T>
+__device__ __forceinline__ void vload(const T* p, T (&v)[Cfg<T>::VEC]) {
+  typename Cfg<T>::vec_t x = *reinterpret_cast<const typename Cfg<T>::vec_t*>(p);
+  if constexpr (Cfg<T>::VEC == 4) {
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else {
+    v[0] = x.x; v[1] = x.y;
+  }
+}
+
+// Load the (rows x BK) slab of an operand whose element (r, k) is at
+//   P[r + k*ld]   (KCONTIG = false: r contiguous)   or
+//   P[k + r*ld]   (KCONTIG = true:  k contiguous),
+// rows r0.., k0.., into registers (2 vectors per thread), zero outside
+// [0, R) x [0, K).
+template <typename T, int ROWS, bool KCONTIG>
+struct SlabLoader {
+  static constexpr int VEC = Cfg<T>::VEC, BK = Cfg<T>::BK;
+  static constexpr int PASSES = ROWS * BK / VEC / 256;
+  T v[PASSES][VEC];
+
+  __device__ void load(const T* __restrict__ P, int ld, int R, int K, int r0, int k0) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int p = 0; p < PASSES; ++p) {
+      int r, k;
+      if constexpr (!KCONTIG) {
+        constexpr int PER_COL = ROWS / VEC;
+        const int q = p * 256 + t;
+        r = r0 + (q % PER_COL) * VEC;
+        k = k0 + q / PER_COL;
+        if (k < K && r + VEC <= R) {
+          vload<T>(P + static_cast<int64_t>(k) * ld + r, v[p]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < VEC; ++c)
+            v[p][c] = (k < K && r + c < R) ? P[static_cast<int64_t>(k) * ld + r + c] : T(0);
+        }
+      } else {
+        constexpr int PER_ROW = BK / VEC;
+        const int q = p * 256 + t;
+        k = k0 + (q % PER_ROW) * VEC;
+        r = r0 + q / PER_ROW;
+        if (r < R && k + VEC <= K) {
+          vload<T>(P + static_cast<int64_t>(r) * ld + k, v[p]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < VEC; ++c)
+            v[p][c] = (r < R && k + c < K) ? P[static_cast<int64_t>(r) * ld + k + c] : T(0);
+        }
+      }
+    }
+  }
+
+  // store into LDS laid out as S[k][ROWS + PAD]
+  __device__ void store(T* S) const {
+    constexpr int LD = ROWS + Cfg<T>::PAD;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int p = 0; p < PASSES; ++p) {
+      if constexpr (!KCONTIG) {
+        constexpr int PER_COL = ROWS / VEC;
+        const int q = p * 256 + t;
+        const int r = (q % PER_COL) * VEC, k = q / PER_COL;
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) S[k * LD + r + c] = v[p][c];
+      } else {
+        constexpr int PER_ROW = BK / VEC;
+        const int q = p * 256 + t;
+        const int k = (q % PER_ROW) * VEC, r = q / PER_ROW;
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) S[(k + c) * LD + r] = v[p][c];
+      }
+    }
+  }
+};
+
+// Main loop: acc[i][j] += opA(tile) * opB(tile) for one block tile (m0, n0).
+// TA: A is stored K x M (element (m,k) at A[k + m*lda]); otherwise M x K.
+// TB: B is stored N x K (element (k,n) at B[n + k*ldb]); otherwise K x N.
+template <typename T, bool TA, bool TB>
+__device__ __forceinline__ void gemm_mainloop(int M, int N, int K, const T* __restrict__ A, int lda,
+                                              const T* __restrict__ B, int ldb, int m0, int n0,
+                                              T* As, T* Bs, typename Cfg<T>::acc_t (&acc)[2][2]) {
+  using C = Cfg<T>;
+  constexpr int LDA = C::BM + C::PAD, LDB = C::BN + C::PAD;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < C::NACC; ++r) acc[i][j][r] = T(0);
+
+  SlabLoader<T, C::BM, TA> la;   // TA -> k contiguous in memory
+  SlabLoader<T, C::BN, !TB> lb;  // !TB -> k contiguous in memory
+  const int nk = (K + C::BK - 1) / C::BK;
+  if (nk == 0) return;
+  la.load(A, lda, M, K, m0, 0);
+  lb.load(B, ldb, N, K, n0, 0);
+  la.store(As);
+  lb.store(Bs);
+  __syncthreads();
+  const int kidx = lane / C::MB, midx = lane % C::MB;
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) {
+      la.load(A, lda, M, K, m0, (kt + 1) * C::BK);
+      lb.load(B, ldb, N, K, n0, (kt + 1) * C::BK);
+    }
+#pragma unroll
+    for (int kk = 0; kk < C::BK; kk += C::KS) {
+      T a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[(kk + kidx) * LDA + wm * C::WM + i * C::MB + midx];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[(kk + kidx) * LDB + wn * C::WN + j * C::MB + midx];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = C::mfma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      la.store(As);
+      lb.store(Bs);
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- epilogues
+
+template <typename T>
+struct EpiStore {
+  T* C;
+  int ldc;
+  __device__ void operator()(const typename Cfg<T>::acc_t (&acc)[2][2], int M, int N, int m0, int n0,
+                             T*) const {
+    using Cf = Cfg<T>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = n0 + wn * Cf::WN + j * Cf::MB + lane % Cf::MB;
+        if (col >= N) continue;
+#pragma unroll
+        for (int r = 0; r < Cf::NACC; ++r) {
+          const int row = m0 + wm * Cf::WM + i * Cf::MB + Cf::acc_row(r, lane);
+          if (row < M) C[static_cast<int64_t>(col) * ldc + row] = acc[i][j][r];
+        }
+      }
+  }
+};
+
+// objective term of one coordinate; Rastrigin uses the identity
+// 10 - 10 cos(2 pi u) = 20 sin^2(pi u), which keeps full relative accuracy
+// near the optimum where the cosine form cancels.
+template <typename T>
+__device__ __forceinline__ T objective_term(int kind, T u, T coef) {
+  if (kind == 3) {
+    T s;
+    if constexpr (sizeof(T) == 4) s = sinpif(u); else s = sinpi(u);
+    return u * u + T(20) * s * s;
+  }
+  if (kind == 2) return coef * u * u;
+  return u * u;
+}
+
+template <typename T>
+struct EpiFitness {
+  int kind;
+  const double* d;
+  const T* coef;
+  const DevScalars* sc;
+  T* partial;
+  int ldp;
+  __device__ void operator()(const typename Cfg<T>::acc_t (&acc)[2][2], int M, int N, int m0, int n0,
+                             T* smem) const {
+    using Cf = Cfg<T>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const T sigma = static_cast<T>(sc->sigma);
+    T s[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      T sum = T(0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < Cf::NACC; ++r) {
+          const int row = m0 + wm * Cf::WM + i * Cf::MB + Cf::acc_row(r, lane);
+          if (row < M) {
+            const T u = static_cast<T>(d[row]) + sigma * acc[i][j][r];
+            sum += objective_term<T>(kind, u, kind == 2 ? coef[row] : T(1));
+          }
+        }
+      // lanes sharing a column hold different row groups: fold them in a fixed order
+      if constexpr (Cf::MB == 32) {
+        sum += __shfl_xor(sum, 32);
+      } else {
+        sum += __shfl_xor(sum, 16);
+        sum += __shfl_xor(sum, 32);
+      }
+      s[j] = sum;
+    }
+    // combine the two waves stacked along m (wm = 0, 1) through LDS
+    __syncthreads();
+    if (lane < Cf::MB) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) smem[wm * Cf::BN + wn * Cf::WN + j * Cf::MB + lane] = s[j];
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < Cf::BN) {
+      const int col = n0 + t;
+      if (col < N) partial[static_cast<int64_t>(m0 / Cf::BM) * ldp + col] = smem[t] + smem[Cf::BN + t];
+    }
+  }
+};
+
+// ------------------------------------------------------------------ kernels
+
+template <typename T, bool TA, bool TB, class Epi>
+__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const T* __restrict__ A, int lda,
+                                              const T* __restrict__ B, int ldb, Epi epi) {
+  using C = Cfg<T>;
+  __shared__ T As[C::BK * (C::BM + C::PAD)];
+  __shared__ T Bs[C::BK * (C::BN + C::PAD)];
+  const int tiles_m = (M + C::BM - 1) / C::BM;
+  const int m0 = (blockIdx.x % tiles_m) * C::BM;
+  const int n0 = (blockIdx.x / tiles_m) * C::BN;
+  typename C::acc_t acc[2][2];
+  gemm_mainloop<T, TA, TB>(M, N, K, A, lda, B, ldb, m0, n0, As, Bs, acc);
+  epi(acc, M, N, m0, n0, As);
+}
+
+__device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
+  tm = static_cast<int>((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+  while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
+  while (tm * (tm + 1) / 2 > t) --tm;
+  tn = t - tm * (tm + 1) / 2;
+}
+
+// Rank-mu SYRK, split over k (the mu selected points) so that the few lower
+// tiles of an n x n result still fill the GPU: block (t, s) writes the partial
+// product of lower tile t over k-range s into its own slot of `work`.
+template <typename T>
+__global__ void __launch_bounds__(256) k_syrk_part(int n, int K, int kspan, const T* __restrict__ Y, int ldy,
+                                                   T* __restrict__ work, int ntl) {
+  using C = Cfg<T>;
+  __shared__ T As[C::BK * (C::BM + C::PAD)];
+  __shared__ T Bs[C::BK * (C::BN + C::PAD)];
+  const int t = blockIdx.x % ntl, s = blockIdx.x / ntl;
+  int tm, tn;
+  lower_tile(t, tm, tn);
+  const int k0 = s * kspan, k1 = min(K, k0 + kspan);
+  typename C::acc_t acc[2][2];
+  const T* Yk = Y + static_cast<int64_t>(k0) * ldy;
+  // A = Yhat (n x K, rows contiguous), B = Yhat^T stored N x K -> TB
+  gemm_mainloop<T, false, true>(n, n, max(0, k1 - k0), Yk, ldy, Yk, ldy, tm * C::BM, tn * C::BN, As, Bs, acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  T* out = work + (static_cast<int64_t>(s) * ntl + t) * (C::BM * C::BN);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wn * C::WN + j * C::MB + lane % C::MB;
+#pragma unroll
+      for (int r = 0; r < C::NACC; ++r) {
+        const int row = wm * C::WM + i * C::MB + C::acc_row(r, lane);
+        out[col * C::BM + row] = acc[i][j][r];
+      }
+    }
+}
+
+// C <- a C + c1 pc pc^T + cmu * sum_s partial_s  (lower triangle, mirrored);
+// the split partials are summed in ascending order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_syrk_epi(int n, int ntl, int splits, const T* __restrict__ work,
+                                                  double* __restrict__ C, int ldc, const double* __restrict__ pc,
+                                                  double c1, double cmu, const DevScalars* __restrict__ sc) {
+  using Cf = Cfg<T>;
+  constexpr int TILE = Cf::BM * Cf::BN;
+  constexpr int PER = TILE / (16 * 256);
+  const int t = blockIdx.x / 16, part = blockIdx.x % 16;
+  int tm, tn;
+  lower_tile(t, tm, tn);
+  const double a = sc->c_coef;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = (part * PER + q) * 256 + threadIdx.x;
+    const int row = tm * Cf::BM + e % Cf::BM, col = tn * Cf::BN + e / Cf::BM;
+    if (row >= n || col >= n || row < col) continue;
+    double acc = 0.0;
+    for (int s = 0; s < splits; ++s) acc += static_cast<double>(work[(static_cast<int64_t>(s) * ntl + t) * TILE + e]);
+    const int64_t at = static_cast<int64_t>(col) * ldc + row;
+    const double v = a * C[at] + c1 * pc[row] * pc[col] + cmu * acc;
+    C[at] = v;
+    if (row != col) C[static_cast<int64_t>(row) * ldc + col] = v;
+  }
+}
+
+template <typename T, bool TA, bool TB, class Epi>
+hipError_t run_gemm(hipStream_t st, int M, int N, int K, const T* A, int lda, const T* B, int ldb,
+                    const Epi& epi) {
+  using C = Cfg<T>;
+  const int tiles = ceil_div(M, C::BM) * ceil_div(N, C::BN);
+  if (tiles == 0) return hipSuccess;
+  k_gemm<T, TA, TB, Epi><<<tiles, 256, 0, st>>>(M, N, K, A, lda, B, ldb, epi);
+  return hipGetLastError();
+}
+
+// Direct (unrotated) fitness: u = d + sigma * y read from Y, one block per
+// (row tile, column tile) with the same partial layout as the GEMM epilogue.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fitness_direct(int n, int lam, const T* __restrict__ Y, int ldy,
+                                                        EpiFitness<T> epi) {
+  using C = Cfg<T>;
+  const int tiles_m = (n + C::BM - 1) / C::BM;
+  const int m0 = (blockIdx.x % tiles_m) * C::BM;
+  const int n0 = (blockIdx.x / tiles_m) * C::BN;
+  // one thread per column of the tile, rows summed in ascending order
+  const int t = threadIdx.x;
+  if (t >= C::BN) return;
+  const int col = n0 + t;
+  if (col >= lam) return;
+  const T sigma = static_cast<T>(epi.sc->sigma);
+  const T* y = Y + static_cast<int64_t>(col) * ldy;
+  T sum = T(0);
+  const int mend = min(m0 + C::BM, n);
+  for (int row = m0; row < mend; ++row) {
+    const T u = static_cast<T>(epi.d[row]) + sigma * y[row];
+    sum += objective_term<T>(epi.kind, u, epi.kind == 2 ? epi.coef[row] : T(1));
+  }
+  epi.partial[static_cast<int64_t>(m0 / C::BM) * epi.ldp + col] = sum;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fitness_reduce(int lam, const T* __restrict__ partial, int ldp,
+                                                        int tiles, double add, double* __restrict__ f) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= lam) return;
+  double s = 0.0;
+  for (int t = 0; t < tiles; ++t) s += static_cast<double>(partial[static_cast<int64_t>(t) * ldp + k]);
+  f[k] = s + add;
+}
+
+}  // namespace
+
+hipError_t launch_sample_gemm(hipStream_t st, bool fp64, int n, int lam, const void* BD, int ldbd,
+                              const void* Z, int ldz, void* Y, int ldy) {
+  if (fp64)
+    return run_gemm<double, false, false>(st, n, lam, n, static_cast<const double*>(BD), ldbd,
+                                          static_cast<const double*>(Z), ldz,
+                                          EpiStore<double>{static_cast<double*>(Y), ldy});
+  return run_gemm<float, false, false>(st, n, lam, n, static_cast<const float*>(BD), ldbd,
+                                       static_cast<const float*>(Z), ldz,
+                                       EpiStore<float>{static_cast<float*>(Y), ldy});
+}
+
+hipError_t launch_fitness_gemm(hipStream_t st, bool fp64, int n, int lam, const void* R, int ldr,
+                               const void* Y, int ldy, const FitnessArgs& fa, int* row_tiles) {
+  if (fp64) {
+    *row_tiles = ceil_div(n, Cfg<double>::BM);
+    EpiFitness<double> e{fa.kind, fa.d, static_cast<const double*>(fa.coef), fa.sc,
+                         static_cast<double*>(fa.partial), fa.ld_partial};
+    return run_gemm<double, false, false>(st, n, lam, n, static_cast<const double*>(R), ldr,
+                                          static_cast<const double*>(Y), ldy, e);
+  }
+  *row_tiles = ceil_div(n, Cfg<float>::BM);
+  EpiFitness<float> e{fa.kind, fa.d, static_cast<const float*>(fa.coef), fa.sc,
+                      static_cast<float*>(fa.partial), fa.ld_partial};
+  return run_gemm<float, false, false>(st, n, lam, n, static_cast<const float*>(R), ldr,
+                                       static_cast<const float*>(Y), ldy, e);
+}
+
+hipError_t launch_fitness_direct(hipStream_t st, bool fp64, int n, int lam, const void* Y, int ldy,
+                                 const FitnessArgs& fa, int* row_tiles) {
+  if (fp64) {
+    using C = Cfg<double>;
+    *row_tiles = ceil_div(n, C::BM);
+    EpiFitness<double> e{fa.kind, fa.d, static_cast<const double*>(fa.coef), fa.sc,
+                         static_cast<double*>(fa.partial), fa.ld_partial};
+    const int tiles = *row_tiles * ceil_div(lam, C::BN);
+    k_fitness_direct<double><<<tiles, 256, 0, st>>>(n, lam, static_cast<const double*>(Y), ldy, e);
+  } else {
+    using C = Cfg<float>;
+    *row_tiles = ceil_div(n, C::BM);
+    EpiFitness<float> e{fa.kind, fa.d, static_cast<const float*>(fa.coef), fa.sc,
+                        static_cast<float*>(fa.partial), fa.ld_partial};
+    const int tiles = *row_tiles * ceil_div(lam, C::BN);
+    k_fitness_direct<float><<<tiles, 256, 0, st>>>(n, lam, static_cast<const float*>(Y), ldy, e);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fitness_reduce(hipStream_t st, bool fp64, int kind, int n, int lam,
+                                 const void* partial, int ld_partial, int row_tiles, double* f) {
+  (void)kind;
+  (void)n;
+  const int blocks = ceil_div(lam, 256);
+  if (fp64)
+    k_fitness_reduce<double><<<blocks, 256, 0, st>>>(lam, static_cast<const double*>(partial),
+                                                     ld_partial, row_tiles, 0.0, f);
+  else
+    k_fitness_reduce<float><<<blocks, 256, 0, st>>>(lam, static_cast<const float*>(partial), ld_partial,
+                                                    row_tiles, 0.0, f);
+  return hipGetLastError();
+}
+
+void syrk_plan(bool fp64, int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems) {
+  const int bm = fp64 ? Cfg<double>::BM : Cfg<float>::BM;
+  const int bk = Cfg<float>::BK;
+  const int tm = ceil_div(n, bm);
+  *ntl = tm * (tm + 1) / 2;
+  int s = ceil_div(512, *ntl);
+  s = std::max(1, std::min(s, ceil_div(K, 64)));
+  *kspan = round_up(ceil_div(std::max(K, 1), s), bk);
+  *splits = ceil_div(std::max(K, 1), *kspan);
+  *work_elems = static_cast<size_t>(*splits) * (*ntl) * bm * bm;
+}
+
+hipError_t launch_syrk_update(hipStream_t st, bool fp64, int n, int mu, const void* Ysel, int ldsel,
+                              double* C, int ldc, const double* pc, double c1, double cmu,
+                              const DevScalars* sc, void* work) {
+  int ntl, splits, kspan;
+  size_t we;
+  syrk_plan(fp64, n, mu, &ntl, &splits, &kspan, &we);
+  if (fp64) {
+    k_syrk_part<double><<<ntl * splits, 256, 0, st>>>(n, mu, kspan, static_cast<const double*>(Ysel), ldsel,
+                                                      static_cast<double*>(work), ntl);
+    k_syrk_epi<double><<<ntl * 16, 256, 0, st>>>(n, ntl, splits, static_cast<const double*>(work), C, ldc, pc, c1,
+                                                 cmu, sc);
+  } else {
+    k_syrk_part<float><<<ntl * splits, 256, 0, st>>>(n, mu, kspan, static_cast<const float*>(Ysel), ldsel,
+                                                     static_cast<float*>(work), ntl);
+    k_syrk_epi<float><<<ntl * 16, 256, 0, st>>>(n, ntl, splits, static_cast<const float*>(work), C, ldc, pc, c1,
+                                                cmu, sc);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A, int lda,
+                        const double* B, int ldb, double* C, int ldc) {
+  EpiStore<double> e{C, ldc};
+  if (!ta && !tb) return run_gemm<double, false, false>(st, M, N, K, A, lda, B, ldb, e);
+  if (ta && !tb) return run_gemm<double, true, false>(st, M, N, K, A, lda, B, ldb, e);
+  if (!ta && tb) return run_gemm<double, false, true>(st, M, N, K, A, lda, B, ldb, e);
+  return run_gemm<double, true, true>(st, M, N, K, A, lda, B, ldb, e);
+}
+
+}  // namespace cmx

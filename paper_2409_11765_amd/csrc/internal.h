@@ -1,0 +1,139 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace cmx {
+
+// Device-resident scalars of one descent.  Kernels read sigma and the
+// generation counter from here, so a generation can be queued without any
+// host round trip.
+struct DevScalars {
+  double sigma;       // step size (eq. (1))
+  double f_best;      // best f over all descents of the handle
+  double ps_norm;     // ||p_sigma|| after the update
+  double hsig;        // 1 or 0 (p_c stall)
+  double c_coef;      // a = 1 - c1 - cmu + (1-hsig) c1 cc (2-cc)
+  double f_gen_min;   // fitness range of the current generation
+  double f_gen_max;
+  double sigma0;
+  int64_t gen;        // generation within the descent
+  int64_t evals;      // evaluations within the descent
+  uint32_t stop;      // stop bits of the descent
+  int32_t eig_ok;     // last eigendecomposition positive definite
+  int32_t hist_count; // entries written into the f-history ring
+  int32_t jac_sweeps; // sweeps used by the last eigensolve
+};
+
+// Strategy parameters passed by value to kernels.
+struct KParams {
+  int n, lam, mu, kappa;
+  double mueff, cs, ds, cc, c1, cmu, chin;
+};
+
+struct StopParams {
+  double tol_hist_fun, tol_fun, tolx, max_condition, f_target;
+  int64_t max_gens, max_evals;
+  int hist_len;
+};
+
+// ---- error plumbing -------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+#define CMX_HIP(expr)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return ::cmx::fail(-3, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+inline int round_up(int a, int b) { return ceil_div(a, b) * b; }
+
+// ---- launchers (each queues work on `st` and returns a hipError_t) --------
+// random numbers
+hipError_t launch_normals(hipStream_t st, void* Z, bool fp64, int ldz, int n, int lam,
+                          uint64_t seed, uint32_t restart, const DevScalars* sc);
+hipError_t launch_init_mean(hipStream_t st, double* m, int n, double lo, double hi,
+                            uint64_t seed, uint32_t restart);
+
+// sampling GEMM Y = BD * Z (store), fitness GEMM on R*Y (or on Y when R is
+// absent) writing per-row-tile partial sums of the objective terms.
+struct FitnessArgs {
+  int kind;                 // cmaes_objective_t
+  const double* d;          // n: R (m - x*) (or m - x*)
+  const void* coef;         // n: per-row weights (ellipsoid), element type = T
+  const DevScalars* sc;     // sigma
+  void* partial;            // [row_tiles][lam] partial sums, element type = T
+  int ld_partial;
+};
+hipError_t launch_sample_gemm(hipStream_t st, bool fp64, int n, int lam, const void* BD, int ldbd,
+                              const void* Z, int ldz, void* Y, int ldy);
+hipError_t launch_fitness_gemm(hipStream_t st, bool fp64, int n, int lam, const void* R, int ldr,
+                               const void* Y, int ldy, const FitnessArgs& fa, int* row_tiles);
+hipError_t launch_fitness_direct(hipStream_t st, bool fp64, int n, int lam, const void* Y, int ldy,
+                                 const FitnessArgs& fa, int* row_tiles);
+hipError_t launch_fitness_reduce(hipStream_t st, bool fp64, int kind, int n, int lam,
+                                 const void* partial, int ld_partial, int row_tiles, double* f);
+
+// ranking
+hipError_t launch_rank(hipStream_t st, const double* f, int lam, int32_t* order);
+
+// recombination and vector updates
+hipError_t launch_recombine(hipStream_t st, bool fp64, int n, int lam, int mu, const void* Y,
+                            const void* Z, int ld, const int32_t* order, const double* w,
+                            const double* sqrtw, void* Ysel, int ldsel, double* part_yw,
+                            double* part_zw, int* nchunks);
+hipError_t launch_reduce_yz(hipStream_t st, int n, int nchunks, const double* part_yw,
+                            const double* part_zw, double* yw, double* zw);
+hipError_t launch_matvec(hipStream_t st, int n, const double* B, int ldb, const double* x,
+                         double* part, int* nchunks);
+hipError_t launch_vec_update(hipStream_t st, const KParams& kp, int nchunks, const double* part_bz,
+                             const double* yw, double* m, double* ps, double* pc, DevScalars* sc);
+hipError_t launch_best(hipStream_t st, bool fp64, int n, int lam, const double* f,
+                       const int32_t* order, const void* Y, int ldy, const double* m,
+                       double* x_best, double* hist, int hist_len, DevScalars* sc);
+
+// covariance update C <- a C + c1 pc pc^T + cmu Ysel Ysel^T (lower tiles + mirror)
+void syrk_plan(bool fp64, int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems);
+hipError_t launch_syrk_update(hipStream_t st, bool fp64, int n, int mu, const void* Ysel, int ldsel,
+                              double* C, int ldc, const double* pc, double c1, double cmu,
+                              const DevScalars* sc, void* work);
+
+// generic FP64 GEMM: C = op(A) * op(B), column-major
+hipError_t launch_dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
+                        int lda, const double* B, int ldb, double* C, int ldc);
+
+// eigensolver
+struct EigWork {
+  int N;          // padded size (multiple of 32)
+  double* A;      // N*N
+  double* V;      // N*N
+  double* Q;      // (N/32) * 32*32
+  double* T;      // n*n scratch
+  int* flags;     // [0] = significant rotation seen in this sweep
+  double* evals;  // N
+  int32_t* perm;  // N
+  double* sign;   // N
+};
+int eigen_solve(hipStream_t st, int n, const double* C, int ldc, double* B, int ldb, double* D,
+                void* BD, bool fp64_bd, int ldbd, EigWork& w, DevScalars* sc, int max_sweeps,
+                int* sweeps_out);
+
+// stop tests
+hipError_t launch_stop(hipStream_t st, const KParams& kp, const StopParams& sp, const double* m,
+                       const double* C, int ldc, const double* B, int ldb, const double* D,
+                       const double* pc, const double* hist, DevScalars* sc);
+
+// misc
+hipError_t launch_set_identity(hipStream_t st, double* A, int n, int ld);
+hipError_t launch_to_precision(hipStream_t st, bool fp64, const double* src, int ld_src, void* dst,
+                               int ld_dst, int rows, int cols);
+// d = R (m - x*) with R, x* optional; u and part are scratch (n and ceil(n/64) n)
+hipError_t launch_shift(hipStream_t st, int n, const double* R, int ldr, const double* m, const double* xstar,
+                        double* u, double* part, double* d);
+
+}  // namespace cmx

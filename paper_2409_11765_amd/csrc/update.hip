@@ -1,0 +1,387 @@
+// Ranking, recombination and the float64 vector updates of one generation
+// (Alg. 1 'update' line, Sec. 2.1), plus the stopping tests (Sec. 2.2).
+//
+// Readings shared with the oracle (no formula is printed in the paper):
+// tutorial default rates, positive weights w_1..w_mu summing to one, the
+// cumulative step-size path p_sigma built from C^{-1/2} y_w = B z_w, the
+// h_sigma stall of p_c, sigma <- sigma exp((cs/ds)(||p_sigma||/chi_n - 1)).
+// All reductions use a fixed order (no floating-point atomics), so a run is
+// bitwise reproducible.
+#include "internal.h"
+
+namespace cmx {
+
+namespace {
+
+__device__ __forceinline__ double rank_key(double v) { return v != v ? __builtin_inf() : v; }
+
+// Rank by counting: rank(i) = #{ j : f_j < f_i or (f_j == f_i and j < i) },
+// NaN counted as +inf.  Keys (f, index) are distinct, so the ranks form a
+// permutation and the result is the stable ascending order.  The j range is
+// split over blockIdx.y; partial counts are summed with integer atomics
+// (order independent, hence deterministic).
+__global__ void __launch_bounds__(256) k_rank_count(const double* __restrict__ f, int lam, int span,
+                                                    int32_t* __restrict__ rank) {
+  __shared__ double sf[256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double fi = i < lam ? rank_key(f[i]) : 0.0;
+  const int j0 = blockIdx.y * span, j1 = min(lam, j0 + span);
+  int cnt = 0;
+  for (int base = j0; base < j1; base += 256) {
+    const int j = base + threadIdx.x;
+    sf[threadIdx.x] = j < j1 ? rank_key(f[j]) : 0.0;
+    __syncthreads();
+    const int lim = min(256, j1 - base);
+    for (int q = 0; q < lim; ++q) {
+      const double fj = sf[q];
+      cnt += (fj < fi) || (fj == fi && base + q < i);
+    }
+    __syncthreads();
+  }
+  if (i < lam && cnt) atomicAdd(&rank[i], cnt);
+}
+
+__global__ void k_scatter_order(const int32_t* __restrict__ rank, int lam, int32_t* __restrict__ order) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < lam) order[rank[i]] = i;
+}
+
+// y_w = sum_{r<mu} w_r y_{order[r]}, z_w likewise (float64 accumulation), and
+// Yhat[:, r] = sqrt(w_r) y_{order[r]} for the rank-mu SYRK.  Grid: rows x
+// chunks of 64 ranks; each chunk writes its own partial sums.
+template <typename T>
+__global__ void __launch_bounds__(256) k_recombine(int n, int mu, const T* __restrict__ Y,
+                                                   const T* __restrict__ Z, int ld,
+                                                   const int32_t* __restrict__ order,
+                                                   const double* __restrict__ w,
+                                                   const double* __restrict__ sqrtw, T* __restrict__ Ysel,
+                                                   int ldsel, double* __restrict__ part_yw,
+                                                   double* __restrict__ part_zw) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int r0 = blockIdx.y * 64, r1 = min(mu, r0 + 64);
+  double ay = 0.0, az = 0.0;
+  for (int r = r0; r < r1; ++r) {
+    const int64_t c = static_cast<int64_t>(order[r]) * ld;
+    const T y = Y[c + i];
+    const T z = Z[c + i];
+    ay += w[r] * static_cast<double>(y);
+    az += w[r] * static_cast<double>(z);
+    Ysel[static_cast<int64_t>(r) * ldsel + i] = static_cast<T>(sqrtw[r] * static_cast<double>(y));
+  }
+  part_yw[static_cast<int64_t>(blockIdx.y) * n + i] = ay;
+  part_zw[static_cast<int64_t>(blockIdx.y) * n + i] = az;
+}
+
+__global__ void k_reduce_yz(int n, int nchunks, const double* __restrict__ py, const double* __restrict__ pz,
+                            double* __restrict__ yw, double* __restrict__ zw) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0, b = 0.0;
+  for (int c = 0; c < nchunks; ++c) {
+    a += py[static_cast<int64_t>(c) * n + i];
+    b += pz[static_cast<int64_t>(c) * n + i];
+  }
+  yw[i] = a;
+  zw[i] = b;
+}
+
+// part[c][i] = sum_{j in chunk c} B[i + j ld] x[j]
+__global__ void __launch_bounds__(256) k_matvec(int n, const double* __restrict__ B, int ldb,
+                                                const double* __restrict__ x, double* __restrict__ part) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j0 = blockIdx.y * 64, j1 = min(n, j0 + 64);
+  double s = 0.0;
+  for (int j = j0; j < j1; ++j) s += B[static_cast<int64_t>(j) * ldb + i] * x[j];
+  part[static_cast<int64_t>(blockIdx.y) * n + i] = s;
+}
+
+template <int NT>
+__device__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// p_sigma, h_sigma, p_c, m, sigma and the covariance coefficient a.
+__global__ void __launch_bounds__(1024) k_vec_update(KParams kp, int nchunks, const double* __restrict__ part_bz,
+                                                     const double* __restrict__ yw, double* __restrict__ m,
+                                                     double* __restrict__ ps, double* __restrict__ pc,
+                                                     DevScalars* __restrict__ sc) {
+  __shared__ double red[1024];
+  const int n = kp.n;
+  const double sigma = sc->sigma;
+  const int64_t g = sc->gen;
+  const double fps = sqrt(kp.cs * (2.0 - kp.cs) * kp.mueff);
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    double bz = 0.0;
+    for (int c = 0; c < nchunks; ++c) bz += part_bz[static_cast<int64_t>(c) * n + i];
+    const double v = (1.0 - kp.cs) * ps[i] + fps * bz;
+    ps[i] = v;
+    acc += v * v;
+  }
+  const double nps = sqrt(block_sum<1024>(acc, red));
+  const double denom = sqrt(1.0 - pow(1.0 - kp.cs, 2.0 * static_cast<double>(g + 1)));
+  const double hsig = (nps / denom < (1.4 + 2.0 / (n + 1.0)) * kp.chin) ? 1.0 : 0.0;
+  const double fpc = hsig * sqrt(kp.cc * (2.0 - kp.cc) * kp.mueff);
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    pc[i] = (1.0 - kp.cc) * pc[i] + fpc * yw[i];
+    m[i] = m[i] + sigma * yw[i];
+  }
+  if (threadIdx.x == 0) {
+    sc->ps_norm = nps;
+    sc->hsig = hsig;
+    sc->c_coef = 1.0 - kp.c1 - kp.cmu + (1.0 - hsig) * kp.c1 * kp.cc * (2.0 - kp.cc);
+    sc->sigma = sigma * exp((kp.cs / kp.ds) * (nps / kp.chin - 1.0));
+    sc->gen = g + 1;
+    sc->evals += kp.lam;
+  }
+}
+
+// Best-so-far point and the f-history ring; runs before m and sigma move.
+template <typename T>
+__global__ void __launch_bounds__(256) k_best(int n, int lam, const double* __restrict__ f,
+                                              const int32_t* __restrict__ order, const T* __restrict__ Y,
+                                              int ldy, const double* __restrict__ m, double* __restrict__ x_best,
+                                              double* __restrict__ hist, int hist_len,
+                                              DevScalars* __restrict__ sc) {
+  const int i0 = order[0];
+  const double f0 = rank_key(f[i0]);
+  const double flast = rank_key(f[order[lam - 1]]);
+  const bool better = f0 < sc->f_best;
+  if (better) {
+    const double sigma = sc->sigma;
+    const T* y = Y + static_cast<int64_t>(i0) * ldy;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x_best[i] = m[i] + sigma * static_cast<double>(y[i]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    hist[sc->hist_count % hist_len] = f0;
+    sc->hist_count += 1;
+    sc->f_gen_min = f0;
+    sc->f_gen_max = flast;
+    if (better) sc->f_best = f0;
+  }
+}
+
+__device__ __forceinline__ int block_or(int v, int* red) {
+  __syncthreads();
+  if (threadIdx.x == 0) *red = 0;
+  __syncthreads();
+  if (v) atomicOr(red, v);
+  __syncthreads();
+  return *red;
+}
+
+__device__ __forceinline__ double block_max(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Stopping tests evaluated after the update (reading of Sec. 2.2; thresholds
+// of the original IPOP-CMA-ES paper).
+__global__ void __launch_bounds__(256) k_stop(KParams kp, StopParams sp, const double* __restrict__ m,
+                                              const double* __restrict__ C, int ldc,
+                                              const double* __restrict__ B, int ldb,
+                                              const double* __restrict__ D, const double* __restrict__ pc,
+                                              const double* __restrict__ hist, DevScalars* __restrict__ sc) {
+  __shared__ double red[256];
+  __shared__ int ired;
+  const int n = kp.n;
+  const double sigma = sc->sigma;
+  const int64_t g = sc->gen;
+  const int ax = static_cast<int>(g % n);
+  double maxsd = 0.0, maxpc = 0.0, dmax = 0.0, dmin_neg = -__builtin_inf();
+  int axis_moves = 0, coord_stuck = 0, nonfinite = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double cii = C[static_cast<int64_t>(i) * ldc + i];
+    const double sd = sqrt(cii);
+    maxsd = fmax(maxsd, sd);
+    maxpc = fmax(maxpc, fabs(pc[i]));
+    dmax = fmax(dmax, D[i]);
+    dmin_neg = fmax(dmin_neg, -D[i]);
+    const double mi = m[i];
+    if (mi + 0.1 * sigma * D[ax] * B[static_cast<int64_t>(ax) * ldb + i] != mi) axis_moves = 1;
+    if (mi + 0.2 * sigma * sd == mi) coord_stuck = 1;
+    if (!isfinite(mi) || !isfinite(cii) || !isfinite(pc[i]) || !isfinite(D[i])) nonfinite = 1;
+  }
+  maxsd = block_max(maxsd, red);
+  maxpc = block_max(maxpc, red);
+  dmax = block_max(dmax, red);
+  const double dmin = -block_max(dmin_neg, red);
+  axis_moves = block_or(axis_moves, &ired);
+  coord_stuck = block_or(coord_stuck, &ired);
+  nonfinite = block_or(nonfinite, &ired);
+  if (threadIdx.x != 0) return;
+  uint32_t bits = 0;
+  const int cnt = sc->hist_count;
+  if (cnt >= sp.hist_len) {
+    double hmin = __builtin_inf(), hmax = -__builtin_inf();
+    for (int q = 0; q < sp.hist_len; ++q) {
+      const double h = hist[(cnt - 1 - q) % sp.hist_len];
+      hmin = fmin(hmin, h);
+      hmax = fmax(hmax, h);
+    }
+    if (hmax - hmin < sp.tol_hist_fun) bits |= 1u << 0;
+    if (fmax(hmax, sc->f_gen_max) - fmin(hmin, sc->f_gen_min) < sp.tol_fun) bits |= 1u << 1;
+  }
+  if (sigma * maxsd < sp.tolx && sigma * maxpc < sp.tolx) bits |= 1u << 2;
+  if (!axis_moves) bits |= 1u << 3;
+  if (coord_stuck) bits |= 1u << 4;
+  if (!sc->eig_ok || !(dmin > 0.0) || (dmax / dmin) * (dmax / dmin) > sp.max_condition) bits |= 1u << 5;
+  if (sc->f_best < sp.f_target) bits |= 1u << 6;
+  if (sp.max_gens > 0 && g >= sp.max_gens) bits |= 1u << 7;
+  if (sp.max_evals > 0 && sc->evals >= sp.max_evals) bits |= 1u << 8;
+  if (nonfinite || !isfinite(sigma)) bits |= 1u << 9;
+  sc->stop = bits;
+}
+
+// u = m - x* (x* may be null = origin)
+__global__ void k_sub(int n, const double* __restrict__ m, const double* __restrict__ xs, double* __restrict__ u) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) u[i] = m[i] - (xs ? xs[i] : 0.0);
+}
+
+__global__ void k_reduce_vec(int n, int nchunks, const double* __restrict__ part, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  for (int c = 0; c < nchunks; ++c) a += part[static_cast<int64_t>(c) * n + i];
+  out[i] = a;
+}
+
+__global__ void k_set_identity(double* A, int n, int ld) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * ld) return;
+  const int col = static_cast<int>(idx / ld), row = static_cast<int>(idx % ld);
+  A[idx] = (row == col) ? 1.0 : 0.0;
+}
+
+template <typename T>
+__global__ void k_convert(const double* __restrict__ s, int lds, T* __restrict__ d, int ldd, int rows,
+                          int cols) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(rows) * cols) return;
+  const int c = static_cast<int>(idx / rows), r = static_cast<int>(idx % rows);
+  d[static_cast<int64_t>(c) * ldd + r] = static_cast<T>(s[static_cast<int64_t>(c) * lds + r]);
+}
+
+}  // namespace
+
+hipError_t launch_rank(hipStream_t st, const double* f, int lam, int32_t* order) {
+  // order[] doubles as the count array: zero it, count, then scatter into
+  // the upper half of a temporary... keep it simple: counts live in order+lam.
+  int32_t* rank = order + lam;
+  hipError_t e = hipMemsetAsync(rank, 0, sizeof(int32_t) * lam, st);
+  if (e != hipSuccess) return e;
+  const int splits = max(1, min(16, lam / 512));
+  const int span = ceil_div(lam, splits);
+  dim3 grid(ceil_div(lam, 256), splits);
+  k_rank_count<<<grid, 256, 0, st>>>(f, lam, span, rank);
+  k_scatter_order<<<ceil_div(lam, 256), 256, 0, st>>>(rank, lam, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_recombine(hipStream_t st, bool fp64, int n, int lam, int mu, const void* Y, const void* Z,
+                            int ld, const int32_t* order, const double* w, const double* sqrtw, void* Ysel,
+                            int ldsel, double* part_yw, double* part_zw, int* nchunks) {
+  (void)lam;
+  *nchunks = ceil_div(mu, 64);
+  dim3 grid(ceil_div(n, 256), *nchunks);
+  if (fp64)
+    k_recombine<double><<<grid, 256, 0, st>>>(n, mu, static_cast<const double*>(Y),
+                                              static_cast<const double*>(Z), ld, order, w, sqrtw,
+                                              static_cast<double*>(Ysel), ldsel, part_yw, part_zw);
+  else
+    k_recombine<float><<<grid, 256, 0, st>>>(n, mu, static_cast<const float*>(Y), static_cast<const float*>(Z),
+                                             ld, order, w, sqrtw, static_cast<float*>(Ysel), ldsel, part_yw,
+                                             part_zw);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_yz(hipStream_t st, int n, int nchunks, const double* part_yw, const double* part_zw,
+                            double* yw, double* zw) {
+  k_reduce_yz<<<ceil_div(n, 256), 256, 0, st>>>(n, nchunks, part_yw, part_zw, yw, zw);
+  return hipGetLastError();
+}
+
+hipError_t launch_matvec(hipStream_t st, int n, const double* B, int ldb, const double* x, double* part,
+                         int* nchunks) {
+  *nchunks = ceil_div(n, 64);
+  dim3 grid(ceil_div(n, 256), *nchunks);
+  k_matvec<<<grid, 256, 0, st>>>(n, B, ldb, x, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_update(hipStream_t st, const KParams& kp, int nchunks, const double* part_bz,
+                             const double* yw, double* m, double* ps, double* pc, DevScalars* sc) {
+  k_vec_update<<<1, 1024, 0, st>>>(kp, nchunks, part_bz, yw, m, ps, pc, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_best(hipStream_t st, bool fp64, int n, int lam, const double* f, const int32_t* order,
+                       const void* Y, int ldy, const double* m, double* x_best, double* hist, int hist_len,
+                       DevScalars* sc) {
+  if (fp64)
+    k_best<double><<<1, 256, 0, st>>>(n, lam, f, order, static_cast<const double*>(Y), ldy, m, x_best, hist,
+                                      hist_len, sc);
+  else
+    k_best<float><<<1, 256, 0, st>>>(n, lam, f, order, static_cast<const float*>(Y), ldy, m, x_best, hist,
+                                     hist_len, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_stop(hipStream_t st, const KParams& kp, const StopParams& sp, const double* m,
+                       const double* C, int ldc, const double* B, int ldb, const double* D,
+                       const double* pc, const double* hist, DevScalars* sc) {
+  k_stop<<<1, 256, 0, st>>>(kp, sp, m, C, ldc, B, ldb, D, pc, hist, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(hipStream_t st, int n, const double* R, int ldr, const double* m, const double* xstar,
+                        double* u, double* part, double* d) {
+  k_sub<<<ceil_div(n, 256), 256, 0, st>>>(n, m, xstar, R ? u : d);
+  if (R) {
+    const int nch = ceil_div(n, 64);
+    dim3 grid(ceil_div(n, 256), nch);
+    k_matvec<<<grid, 256, 0, st>>>(n, R, ldr, u, part);
+    k_reduce_vec<<<ceil_div(n, 256), 256, 0, st>>>(n, nch, part, d);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_set_identity(hipStream_t st, double* A, int n, int ld) {
+  const int64_t total = static_cast<int64_t>(n) * ld;
+  k_set_identity<<<static_cast<int>((total + 255) / 256), 256, 0, st>>>(A, n, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_precision(hipStream_t st, bool fp64, const double* src, int ld_src, void* dst, int ld_dst,
+                               int rows, int cols) {
+  const int64_t total = static_cast<int64_t>(rows) * cols;
+  const int blocks = static_cast<int>((total + 255) / 256);
+  if (blocks == 0) return hipSuccess;
+  if (fp64)
+    k_convert<double><<<blocks, 256, 0, st>>>(src, ld_src, static_cast<double*>(dst), ld_dst, rows, cols);
+  else
+    k_convert<float><<<blocks, 256, 0, st>>>(src, ld_src, static_cast<float*>(dst), ld_dst, rows, cols);
+  return hipGetLastError();
+}
+
+}  // namespace cmx

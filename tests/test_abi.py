@@ -1,0 +1,57 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function the header declares, and rejects bad arguments without a device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+def _declared():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(inc, fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(cmaes_[a-z_]+)\s*\(", txt))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("cmaes_create", "cmaes_generation", "cmaes_restart_ipop", "cmaes_state",
+                     "cmaes_destroy", "cmaes_set_state", "cmaes_generation_with_z", "cmaes_ask",
+                     "cmaes_tell", "cmaes_set_objective", "cmaes_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2409_11765_amd as P
+    lib = ctypes.CDLL(P.LIB_PATH)
+    missing = [n for n in sorted(_declared()) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_header():
+    import paper_2409_11765_amd.binding as B
+    # int32 x4, int64 x2, double x8, pointer -> 88 bytes on x86-64
+    assert ctypes.sizeof(B.CmaesOptions) == 4 * 4 + 8 + 8 * 7 + 8
+    assert B.CmaesState.m.offset == 4 * 4 + 8 * 3 + 8 * 2 + 4 + 4 + 4 + 4
+
+
+def test_default_options_and_errors_without_device():
+    import paper_2409_11765_amd as P
+    o = P.cmaes_default_options()
+    assert (o.precision, o.k_max, o.box_lo, o.box_hi, o.f_target) == (1, 256, -4.0, 4.0, 1e-8)
+    with pytest.raises(P.CmaesError):
+        P.cmaes_create(0, 10, 1.0, 1)          # n < 1
+    with pytest.raises(P.CmaesError):
+        P.cmaes_create(5, 1, 1.0, 1)           # lambda < 2
+    with pytest.raises(P.CmaesError):
+        P.cmaes_create(5, 10, -1.0, 1)         # sigma0 <= 0
+    assert isinstance(P.cmaes_last_error(), str)
