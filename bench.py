@@ -22,6 +22,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
+
+
+def kernel_work(n, lam, precision, N=None):
+    """Algorithmic work per launch of each timed kernel:
+    (amount, unit, peak, bound)."""
+    mu = lam // 2
+    N = N or 32 * ((n + 31) // 32)
+    q = N // 32                      # Jacobi block pairs per round
+    f32 = precision != "fp64"
+    mm = PEAK["fp32_mfma_tflops"] if f32 else PEAK["fp64_tflops"]
+    esz = 4 if f32 else 8
+    rot_flops = q * 31 * 16 * (6 * 32 * 2)           # one inner sweep: 16 rotations x 31 rounds per pair
+    apply_flops = (q * (q + 1) // 2) * 2 * 2 * 32 ** 3 + q * q * 2 * 32 ** 3
+    return {
+        "normals": (esz * n * lam, "GB/s", PEAK["hbm_gbs"], "hbm"),
+        "sample_gemm": (2.0 * n * n * lam, "TFLOP/s", mm, "mfma"),
+        "fitness": (2.0 * n * n * lam, "TFLOP/s", mm, "mfma"),
+        "syrk": (float(n) * (n + 1) * mu, "TFLOP/s", mm, "mfma"),
+        "eig_gemm": (2.0 * n ** 3, "TFLOP/s", PEAK["fp64_tflops"], "mfma"),
+        "jac_pair": (float(rot_flops), "TFLOP/s", PEAK["fp64_tflops"], "alu"),
+        "jac_apply": (float(apply_flops), "TFLOP/s", PEAK["fp64_tflops"], "mfma"),
+        "rank": (float(lam) * lam, "Gcmp/s", None, "alu"),
+    }
+
+
+def roofline_entry(name, kt, work):
+    amount, unit, peak, bound = work[name]
+    avg = kt[name]["avg_us"]
+    if not avg:
+        return None
+    scale = 1e12 if unit == "TFLOP/s" else 1e9
+    achieved = amount / (avg * 1e-6) / scale
+    return {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak if peak else None, "avg_launch_us": avg,
+            "launches_per_step": kt[name]["calls"], "work_per_launch": amount}
 METRIC = "evals/s + gens/s at n=1000, λ=6144 (mixed vs FP64); % of MFMA/HBM peak"
 
 
@@ -66,9 +101,22 @@ def run_gpu(P, torch, n, lam, precision, steps, warmup, seed, R, xs):
         wall = time.perf_counter() - wall0
         ms = t0.elapsed_time(t1) / steps
         st = es.state(arrays=False)
+        # per-kernel device time from HIP events around each launch, on the
+        # handle's stream (a separate pass: the events add a little overhead)
+        ksteps = max(2, min(steps, 5))
+        es.enable_kernel_timing(True)
+        for _ in range(ksteps):
+            es.generation()
+        torch.cuda.synchronize()
+        kt = es.kernel_times()
+        es.enable_kernel_timing(False)
+        for v in kt.values():
+            v["calls"] = v["calls"] / ksteps
+            v["total_us"] = v["total_us"] / ksteps
     finally:
         es.close()
-    return {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "phases_us": phases, "state": st}
+    return {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "phases_us": phases, "state": st,
+            "kernels": kt}
 
 
 def cpu_baseline(n, lam, seed, R, xs, budget_s):
@@ -150,9 +198,15 @@ def main():
         out["fp64"] = {"ms_per_step": fp64["ms_per_step"], "evals_per_s": lam * 1e3 / fp64["ms_per_step"],
                        "gens_per_s": 1e3 / fp64["ms_per_step"], "phases_us": fp64["phases_us"]}
         out["mixed_over_fp64"] = fp64["ms_per_step"] / mixed["ms_per_step"]
-    out["roofline"] = {"bound": "mfma", "kernel": "sampling GEMM (float32 MFMA)",
-                       "achieved": flop_sample / (ph["sample"] * 1e-6) / 1e12, "peak": PEAK["fp32_mfma_tflops"],
-                       "unit": "TFLOP/s", "frac": frac(flop_sample, ph["sample"]), "traffic": None}
+    kt = mixed["kernels"]
+    work = kernel_work(n, lam, a.precision)
+    per_kernel = {k: roofline_entry(k, kt, work) for k in kt if kt[k]["calls"]}
+    dom_k = max((k for k in kt if kt[k]["calls"]), key=lambda k: kt[k]["total_us"])
+    roof = dict(per_kernel[dom_k])
+    roof["traffic"] = None
+    roof["share_of_step"] = kt[dom_k]["total_us"] / (1e3 * mixed["ms_per_step"])
+    out["roofline"] = roof
+    out["kernels"] = {k: {**kt[k], "roofline": per_kernel.get(k)} for k in kt}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, lam, a.seed, R, xs, a.cpu_seconds)
     print(json.dumps(out), flush=True)

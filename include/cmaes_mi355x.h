@@ -187,6 +187,22 @@ int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in);
 int cmaes_enable_timing(cmaes_t* h, int on);
 int cmaes_phase_times(const cmaes_t* h, double* out);
 
+/* Per-kernel device time, measured with HIP events recorded around the
+ * launches of the kernels below while enabled (enabling resets the totals).
+ * cmaes_kernel_times() writes CMAES_NUM_KERNELS totals in microseconds and
+ * launch counts, indexed by the CMAES_KERNEL_* values. */
+#define CMAES_KERNEL_NORMALS 0     /* Philox + Box-Muller sampler               */
+#define CMAES_KERNEL_SAMPLE_GEMM 1 /* Y = B D Z                                 */
+#define CMAES_KERNEL_FITNESS 2     /* R Y with the objective epilogue           */
+#define CMAES_KERNEL_RANK 3        /* argsort of f                              */
+#define CMAES_KERNEL_SYRK 4        /* rank-mu SYRK + covariance epilogue        */
+#define CMAES_KERNEL_EIG_GEMM 5    /* float64 products of the eigensolver       */
+#define CMAES_KERNEL_JAC_PAIR 6    /* Jacobi pair diagonalisation               */
+#define CMAES_KERNEL_JAC_APPLY 7   /* Jacobi tile / eigenvector update          */
+#define CMAES_NUM_KERNELS 8
+int cmaes_enable_kernel_timing(cmaes_t* h, int on);
+int cmaes_kernel_times(const cmaes_t* h, double* total_us, int64_t* calls);
+
 /* Thread-local message for the last failing call (never NULL). */
 const char* cmaes_last_error(void);
 

@@ -27,6 +27,7 @@ PRECISIONS = {"fp64": CMAES_FP64, "mixed": CMAES_MIXED, "mixed_bf16x3": CMAES_MI
 STOP_BITS = ["tolhistfun", "tolfun", "tolx", "noeffectaxis", "noeffectcoord", "conditioncov",
              "ftarget", "maxgen", "maxevals", "numeric"]
 NUM_PHASES = 6
+KERNELS = ["normals", "sample_gemm", "fitness", "rank", "syrk", "eig_gemm", "jac_pair", "jac_apply"]
 PHASES = ["sample", "fitness", "rank", "update", "covariance", "eigen"]
 
 
@@ -79,6 +80,8 @@ def _load():
         "cmaes_set_state": (C.c_int, [H, C.POINTER(CmaesState)]),
         "cmaes_enable_timing": (C.c_int, [H, C.c_int]),
         "cmaes_phase_times": (C.c_int, [H, _PD]),
+        "cmaes_enable_kernel_timing": (C.c_int, [H, C.c_int]),
+        "cmaes_kernel_times": (C.c_int, [H, _PD, C.POINTER(C.c_int64)]),
         "cmaes_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -92,7 +95,8 @@ _lib = _load()
 EXPORTED = ["cmaes_default_options", "cmaes_create", "cmaes_destroy", "cmaes_set_options",
             "cmaes_get_options", "cmaes_set_objective", "cmaes_generation", "cmaes_generation_with_z",
             "cmaes_ask", "cmaes_tell", "cmaes_restart_ipop", "cmaes_ipop_run", "cmaes_state",
-            "cmaes_set_state", "cmaes_enable_timing", "cmaes_phase_times", "cmaes_last_error"]
+            "cmaes_set_state", "cmaes_enable_timing", "cmaes_phase_times", "cmaes_enable_kernel_timing",
+            "cmaes_kernel_times", "cmaes_last_error"]
 
 
 def library():
@@ -237,6 +241,18 @@ def cmaes_phase_times(h) -> dict:
     return dict(zip(PHASES, out.tolist()))
 
 
+def cmaes_enable_kernel_timing(h, on: bool = True):
+    _check(_lib.cmaes_enable_kernel_timing(h, 1 if on else 0))
+
+
+def cmaes_kernel_times(h) -> dict:
+    tot = np.zeros(len(KERNELS))
+    cnt = np.zeros(len(KERNELS), dtype=np.int64)
+    _check(_lib.cmaes_kernel_times(h, _dptr(tot), cnt.ctypes.data_as(C.POINTER(C.c_int64))))
+    return {k: {"total_us": float(t), "calls": int(c), "avg_us": float(t) / c if c else None}
+            for k, t, c in zip(KERNELS, tot, cnt)}
+
+
 class CMAES:
     """Owning wrapper of one handle (one descent plus its IPOP restarts)."""
 
@@ -305,3 +321,9 @@ class CMAES:
 
     def phase_times(self):
         return cmaes_phase_times(self.h)
+
+    def enable_kernel_timing(self, on=True):
+        cmaes_enable_kernel_timing(self.h, on)
+
+    def kernel_times(self):
+        return cmaes_kernel_times(self.h)

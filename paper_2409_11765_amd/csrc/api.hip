@@ -104,6 +104,7 @@ struct cmaes {
   hipEvent_t ev[CMAES_NUM_PHASES + 1] = {};
   double phase_us[CMAES_NUM_PHASES] = {};
   int last_sweeps = 0;
+  KTimer kt;
 
   // float64 state
   DevScalars* sc = nullptr;
@@ -334,9 +335,13 @@ int phase_sample(cmaes* h, const double* Zhost) {
       CMX_HIP(hipStreamSynchronize(h->st));
     }
   } else {
+    kt_begin(&h->kt, KID_NORMALS);
     CMX_HIP(launch_normals(h->st, h->Z, h->fp64, ldn, n, lam, h->seed, static_cast<uint32_t>(h->restart), h->sc));
+    kt_end(&h->kt);
   }
+  kt_begin(&h->kt, KID_SAMPLE_GEMM);
   CMX_HIP(launch_sample_gemm(h->st, h->fp64, n, lam, h->BD, ldn, h->Z, ldn, h->Y, ldn));
+  kt_end(&h->kt);
   rec(h, 1);
   return 0;
 }
@@ -347,10 +352,12 @@ int phase_fitness(cmaes* h) {
                        h->part_bz, h->d));
   FitnessArgs fa{h->obj_kind, h->d, h->coef, h->sc, h->partial, lam};
   int tiles = 0;
+  kt_begin(&h->kt, KID_FITNESS);
   if (h->have_R)
     CMX_HIP(launch_fitness_gemm(h->st, h->fp64, n, lam, h->Rt, ldn, h->Y, ldn, fa, &tiles));
   else
     CMX_HIP(launch_fitness_direct(h->st, h->fp64, n, lam, h->Y, ldn, fa, &tiles));
+  kt_end(&h->kt);
   CMX_HIP(launch_fitness_reduce(h->st, h->fp64, h->obj_kind, n, lam, h->partial, lam, tiles, h->f));
   return 0;
 }
@@ -358,7 +365,9 @@ int phase_fitness(cmaes* h) {
 int phase_update(cmaes* h) {
   const int n = h->n, lam = h->lam, ldn = h->ldn, mu = h->hp.kp.mu;
   rec(h, 2);
+  kt_begin(&h->kt, KID_RANK);
   CMX_HIP(launch_rank(h->st, h->f, lam, h->order));
+  kt_end(&h->kt);
   CMX_HIP(launch_best(h->st, h->fp64, n, lam, h->f, h->order, h->Y, ldn, h->m, h->x_best, h->hist, h->sp.hist_len, h->sc));
   rec(h, 3);
   int nch = 0, nchb = 0;
@@ -368,15 +377,17 @@ int phase_update(cmaes* h) {
   CMX_HIP(launch_matvec(h->st, n, h->B, ldn, h->zw, h->part_bz, &nchb));
   CMX_HIP(launch_vec_update(h->st, h->hp.kp, nchb, h->part_bz, h->yw, h->m, h->ps, h->pc, h->sc));
   rec(h, 4);
+  kt_begin(&h->kt, KID_SYRK);
   CMX_HIP(launch_syrk_update(h->st, h->fp64, n, mu, h->Ysel, ldn, h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc,
                              h->syrk_work));
+  kt_end(&h->kt);
   rec(h, 5);
   h->gen += 1;
   h->evals += lam;
   h->total_evals += lam;
   if (h->gen % h->hp.kp.kappa == 0) {
     const int rc = eigen_solve(h->st, n, h->C, ldn, h->B, ldn, h->D, h->BD, h->fp64, ldn, h->ew, h->sc, 30,
-                               &h->last_sweeps);
+                               &h->last_sweeps, &h->kt);
     if (rc == CMAES_ENUMERIC) {
       // no usable decomposition: report it through the ConditionCov stop bit
       const int32_t zero = 0;
@@ -389,6 +400,16 @@ int phase_update(cmaes* h) {
   }
   CMX_HIP(launch_stop(h->st, h->hp.kp, h->sp, h->m, h->C, ldn, h->B, ldn, h->D, h->pc, h->hist, h->sc));
   rec(h, 6);
+  if (h->kt.on && h->kt.used > 0) {
+    CMX_HIP(hipEventSynchronize(h->kt.ev[2 * h->kt.used - 1]));
+    for (int i = 0; i < h->kt.used; ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, h->kt.ev[2 * i], h->kt.ev[2 * i + 1]);
+      h->kt.total_us[h->kt.kid[i]] += 1000.0 * ms;
+      h->kt.calls[h->kt.kid[i]] += 1;
+    }
+    h->kt.used = 0;
+  }
   if (h->timing) {
     CMX_HIP(hipEventSynchronize(h->ev[6]));
     float ms = 0.f;
@@ -495,6 +516,8 @@ void cmaes_destroy(cmaes_t* h) {
   if (!h) return;
   if (h->st) (void)hipStreamSynchronize(h->st);
   free_all(h);
+  for (auto& e : h->kt.ev)
+    if (e) (void)hipEventDestroy(e);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
@@ -526,6 +549,7 @@ int cmaes_set_options(cmaes_t* h, const cmaes_options_t* o) {
     }
   }
   h->opt = *o;
+  h->kt.st = h->st;
   h->hp = make_params(h->n, h->lam, o->eigen_interval);
   refresh_stop_params(h);
   if (h->allocated) {
@@ -742,6 +766,31 @@ int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in) {
 int cmaes_enable_timing(cmaes_t* h, int on) {
   if (int rc = check(h)) return rc;
   h->timing = on != 0;
+  return CMAES_OK;
+}
+
+int cmaes_enable_kernel_timing(cmaes_t* h, int on) {
+  if (int rc = check(h)) return rc;
+  if (on && !h->kt.ev[0]) {
+    for (auto& e : h->kt.ev) CMX_HIP(hipEventCreate(&e));
+  }
+  h->kt.on = on != 0;
+  h->kt.st = h->st;
+  h->kt.used = 0;
+  for (int i = 0; i < KID_COUNT; ++i) {
+    h->kt.total_us[i] = 0.0;
+    h->kt.calls[i] = 0;
+  }
+  return CMAES_OK;
+}
+
+int cmaes_kernel_times(const cmaes_t* h, double* total_us, int64_t* calls) {
+  if (int rc = check(h)) return rc;
+  if (!total_us || !calls) return fail(CMAES_EINVAL, "null output");
+  for (int i = 0; i < KID_COUNT; ++i) {
+    total_us[i] = h->kt.total_us[i];
+    calls[i] = h->kt.calls[i];
+  }
   return CMAES_OK;
 }
 

@@ -377,15 +377,20 @@ __global__ void __launch_bounds__(256) k_permute(const double* __restrict__ Bn, 
 }  // namespace
 
 int eigen_solve(hipStream_t st, int n, const double* C, int ldc, double* B, int ldb, double* D, void* BD,
-                bool fp64_bd, int ldbd, EigWork& w, DevScalars* sc, int max_sweeps, int* sweeps_out) {
+                bool fp64_bd, int ldbd, EigWork& w, DevScalars* sc, int max_sweeps, int* sweeps_out,
+                KTimer* kt) {
   const int N = w.N;
   const int p = N / kNB;
   const int64_t NN = static_cast<int64_t>(N) * N;
   k_fill<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.A, NN, 0.0);
   k_identity<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.V, N);
   CMX_HIP(hipGetLastError());
+  kt_begin(kt, KID_EIG_GEMM);
   CMX_HIP(launch_dgemm(st, false, false, n, n, n, C, ldc, B, ldb, w.T, ldb));   // T = C B
+  kt_end(kt);
+  kt_begin(kt, KID_EIG_GEMM);
   CMX_HIP(launch_dgemm(st, true, false, n, n, n, B, ldb, w.T, ldb, w.A, N));    // A = B^T T
+  kt_end(kt);
   double* part = w.evals;  // 3 n doubles of scratch during the sweeps (evals has 3N)
   int host_flags[2] = {1, 0};
   int sweeps = 0;
@@ -400,15 +405,21 @@ int eigen_solve(hipStream_t st, int n, const double* C, int ldc, double* B, int 
     if (host_flags[1]) return fail(-6, "eigensolver: non-finite covariance matrix");
     if (!host_flags[0] || sweeps >= max_sweeps) break;
     for (int r = 0; r < p - 1; ++r) {
+      kt_begin(kt, KID_JAC_PAIR);
       k_jac_pair<<<q, 256, 0, st>>>(w.A, N, p, r, w.sign, w.Q, 1);
+      kt_end(kt);
+      kt_begin(kt, KID_JAC_APPLY);
       k_jac_apply<<<apply_blocks, 256, 0, st>>>(w.A, w.V, N, p, r, w.Q);
+      kt_end(kt);
     }
     CMX_HIP(hipGetLastError());
     ++sweeps;
   }
   if (sweeps_out) *sweeps_out = sweeps;
   // B_new = B V (into T), then canonical order / signs into B, D, BD
+  kt_begin(kt, KID_EIG_GEMM);
   CMX_HIP(launch_dgemm(st, false, false, n, n, n, B, ldb, w.V, N, w.T, ldb));
+  kt_end(kt);
   k_eig_rank<<<ceil_div(n, 256), 256, 0, st>>>(w.A, N, n, w.perm, w.evals, sc);
   k_colsign<<<n, 256, 0, st>>>(w.T, ldb, n, w.sign);
   dim3 grid(ceil_div(n, 256), n);

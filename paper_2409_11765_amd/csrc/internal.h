@@ -40,6 +40,32 @@ struct StopParams {
   int hist_len;
 };
 
+// ---- per-kernel event timer ------------------------------------------------
+// When enabled, begin/end events are recorded around selected launches; the
+// host folds them into per-kernel totals after the generation.
+enum KernelId { KID_NORMALS = 0, KID_SAMPLE_GEMM, KID_FITNESS, KID_RANK, KID_SYRK, KID_EIG_GEMM,
+                KID_JAC_PAIR, KID_JAC_APPLY, KID_COUNT };
+struct KTimer {
+  static constexpr int kMax = 4096;
+  bool on = false;
+  int used = 0;
+  hipStream_t st = nullptr;
+  hipEvent_t ev[2 * kMax] = {};
+  int kid[kMax] = {};
+  double total_us[KID_COUNT] = {};
+  int64_t calls[KID_COUNT] = {};
+};
+inline void kt_begin(KTimer* t, int kid) {
+  if (!t || !t->on || t->used >= KTimer::kMax) return;
+  t->kid[t->used] = kid;
+  (void)hipEventRecord(t->ev[2 * t->used], t->st);
+}
+inline void kt_end(KTimer* t) {
+  if (!t || !t->on || t->used >= KTimer::kMax) return;
+  (void)hipEventRecord(t->ev[2 * t->used + 1], t->st);
+  ++t->used;
+}
+
 // ---- error plumbing -------------------------------------------------------
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
@@ -121,7 +147,7 @@ struct EigWork {
 };
 int eigen_solve(hipStream_t st, int n, const double* C, int ldc, double* B, int ldb, double* D,
                 void* BD, bool fp64_bd, int ldbd, EigWork& w, DevScalars* sc, int max_sweeps,
-                int* sweeps_out);
+                int* sweeps_out, KTimer* kt);
 
 // stop tests
 hipError_t launch_stop(hipStream_t st, const KParams& kp, const StopParams& sp, const double* m,
