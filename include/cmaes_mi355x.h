@@ -197,9 +197,8 @@ int cmaes_phase_times(const cmaes_t* h, double* out);
 #define CMAES_KERNEL_RANK 3        /* argsort of f                              */
 #define CMAES_KERNEL_SYRK 4        /* rank-mu SYRK + covariance epilogue        */
 #define CMAES_KERNEL_EIG_GEMM 5    /* float64 products of the eigensolver       */
-#define CMAES_KERNEL_JAC_PAIR 6    /* Jacobi pair diagonalisation               */
-#define CMAES_KERNEL_JAC_APPLY 7   /* Jacobi tile / eigenvector update          */
-#define CMAES_NUM_KERNELS 8
+#define CMAES_KERNEL_JACOBI 6      /* persistent block-Jacobi sweeps            */
+#define CMAES_NUM_KERNELS 7
 int cmaes_enable_kernel_timing(cmaes_t* h, int on);
 int cmaes_kernel_times(const cmaes_t* h, double* total_us, int64_t* calls);
 

@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": CMAES_FP64, "mixed": CMAES_MIXED, "mixed_bf16x3": CMAES_MI
 STOP_BITS = ["tolhistfun", "tolfun", "tolx", "noeffectaxis", "noeffectcoord", "conditioncov",
              "ftarget", "maxgen", "maxevals", "numeric"]
 NUM_PHASES = 6
-KERNELS = ["normals", "sample_gemm", "fitness", "rank", "syrk", "eig_gemm", "jac_pair", "jac_apply"]
+KERNELS = ["normals", "sample_gemm", "fitness", "rank", "syrk", "eig_gemm", "jacobi"]
 PHASES = ["sample", "fitness", "rank", "update", "covariance", "eigen"]
 
 

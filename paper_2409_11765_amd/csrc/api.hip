@@ -1,5 +1,6 @@
 // C ABI: handle life cycle, the generation pipeline and the IPOP restart loop
 // (Alg. 1 and Alg. 2 of the paper).  See include/cmaes_mi355x.h.
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -103,8 +104,8 @@ struct cmaes {
   bool timing = false;
   hipEvent_t ev[CMAES_NUM_PHASES + 1] = {};
   double phase_us[CMAES_NUM_PHASES] = {};
-  int last_sweeps = 0;
   KTimer kt;
+  bool eig_due = false;
 
   // float64 state
   DevScalars* sc = nullptr;
@@ -166,10 +167,17 @@ void free_all(cmaes* h) {
   dev_free(h->ew.V);
   dev_free(h->ew.Q);
   dev_free(h->ew.T);
-  dev_free(h->ew.flags);
+  dev_free(h->ew.A2);
+  dev_free(h->ew.Q2);
   dev_free(h->ew.evals);
   dev_free(h->ew.perm);
   dev_free(h->ew.sign);
+  dev_free(h->ew.part);
+  dev_free(h->ew.scale);
+  dev_free(h->ew.flags);
+  dev_free(h->ew.status);
+  if (h->ew.hflags) (void)hipHostFree(h->ew.hflags);
+  h->ew.hflags = nullptr;
   h->allocated = false;
 }
 
@@ -232,9 +240,18 @@ int alloc_fixed(cmaes* h) {
       (rc = dev_alloc(&h->Rt, e * nn)) || (rc = dev_alloc(&h->coef, e * ldn)) ||
       (rc = dev_alloc(&h->ew.A, 8ull * N * N)) || (rc = dev_alloc(&h->ew.V, 8ull * N * N)) ||
       (rc = dev_alloc(&h->ew.Q, 8ull * (N / 32) * 32 * 32)) || (rc = dev_alloc(&h->ew.T, 8 * nn)) ||
-      (rc = dev_alloc(&h->ew.flags, 16)) || (rc = dev_alloc(&h->ew.evals, 8ull * 3 * N)) ||
-      (rc = dev_alloc(&h->ew.perm, 4ull * N)) || (rc = dev_alloc(&h->ew.sign, 8ull * N)))
+      (rc = dev_alloc(&h->ew.A2, 8ull * N * N)) || (rc = dev_alloc(&h->ew.Q2, 8ull * (N / 32) * 32 * 32)) ||
+      (rc = dev_alloc(&h->ew.evals, 8ull * N)) || (rc = dev_alloc(&h->ew.perm, 4ull * N)) ||
+      (rc = dev_alloc(&h->ew.sign, 8ull * N)) || (rc = dev_alloc(&h->ew.scale, 16)) ||
+      (rc = dev_alloc(&h->ew.flags, 16)) || (rc = dev_alloc(&h->ew.status, 16)))
     return rc;
+  {
+    const int q = N / 32;
+    if ((rc = dev_alloc(&h->ew.part, 8ull * 3 * std::max(n, q * (q + 1) / 2)))) return rc;
+  }
+  void* hf = nullptr;
+  if (hipHostMalloc(&hf, 16, hipHostMallocDefault) != hipSuccess) return fail(CMAES_ENOMEM, "hipHostMalloc failed");
+  h->ew.hflags = static_cast<int*>(hf);
   return 0;
 }
 
@@ -362,7 +379,10 @@ int phase_fitness(cmaes* h) {
   return 0;
 }
 
-int phase_update(cmaes* h) {
+// ranking, recombination, paths / sigma and the covariance update; the
+// eigensolve (if due) is begun here and finished by eigen_drive or the
+// batch driver
+int phase_update_pre(cmaes* h) {
   const int n = h->n, lam = h->lam, ldn = h->ldn, mu = h->hp.kp.mu;
   rec(h, 2);
   kt_begin(&h->kt, KID_RANK);
@@ -385,20 +405,23 @@ int phase_update(cmaes* h) {
   h->gen += 1;
   h->evals += lam;
   h->total_evals += lam;
-  if (h->gen % h->hp.kp.kappa == 0) {
-    const int rc = eigen_solve(h->st, n, h->C, ldn, h->B, ldn, h->D, h->BD, h->fp64, ldn, h->ew, h->sc, 30,
-                               &h->last_sweeps, &h->kt);
-    if (rc == CMAES_ENUMERIC) {
-      // no usable decomposition: report it through the ConditionCov stop bit
-      const int32_t zero = 0;
-      CMX_HIP(hipMemcpyAsync(reinterpret_cast<char*>(h->sc) + offsetof(DevScalars, eig_ok), &zero, sizeof(zero),
-                             hipMemcpyHostToDevice, h->st));
-      CMX_HIP(hipStreamSynchronize(h->st));
-    } else if (rc != 0) {
-      return rc;
-    }
-  }
-  CMX_HIP(launch_stop(h->st, h->hp.kp, h->sp, h->m, h->C, ldn, h->B, ldn, h->D, h->pc, h->hist, h->sc));
+  h->eig_due = (h->gen % h->hp.kp.kappa == 0);
+  if (h->eig_due) return eigen_begin(h->st, n, h->C, ldn, h->B, ldn, h->ew, &h->kt);
+  return 0;
+}
+
+// one step of the eigensolve in flight (the stream must have been
+// synchronised since the last call); *done once the decomposition is final
+int eigen_advance(cmaes* h, bool* done) {
+  // a decomposition that does not converge within the sweep limit (or meets
+  // non-finite values) clears eig_ok on the device, which raises the
+  // ConditionCov stop bit
+  return eigen_step(h->st, h->n, h->B, h->ldn, h->D, h->BD, h->fp64, h->ldn, h->ew, h->sc, 40, &h->kt, done);
+}
+
+// stop tests, then fold the optional timers
+int phase_update_post(cmaes* h) {
+  CMX_HIP(launch_stop(h->st, h->hp.kp, h->sp, h->m, h->C, h->ldn, h->B, h->ldn, h->D, h->pc, h->hist, h->sc));
   rec(h, 6);
   if (h->kt.on && h->kt.used > 0) {
     CMX_HIP(hipEventSynchronize(h->kt.ev[2 * h->kt.used - 1]));
@@ -414,14 +437,23 @@ int phase_update(cmaes* h) {
     CMX_HIP(hipEventSynchronize(h->ev[6]));
     float ms = 0.f;
     // phases: sample | fitness | rank | update | covariance | eigen
-    const int a[CMAES_NUM_PHASES] = {0, 1, 2, 3, 4, 5};
-    const int b[CMAES_NUM_PHASES] = {1, 2, 3, 4, 5, 6};
     for (int i = 0; i < CMAES_NUM_PHASES; ++i) {
-      (void)hipEventElapsedTime(&ms, h->ev[a[i]], h->ev[b[i]]);
+      (void)hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]);
       h->phase_us[i] = 1000.0 * ms;
     }
   }
   return 0;
+}
+
+int phase_update(cmaes* h) {
+  if (int rc = phase_update_pre(h)) return rc;
+  if (h->eig_due) {
+    for (bool done = false; !done;) {
+      CMX_HIP(hipStreamSynchronize(h->st));
+      if (int rc = eigen_advance(h, &done)) return rc;
+    }
+  }
+  return phase_update_post(h);
 }
 
 int check(const cmaes* h) {
@@ -705,7 +737,7 @@ int cmaes_state(const cmaes_t* hc, cmaes_state_t* out) {
   out->f_best = s.f_best;
   out->stop = s.stop;
   out->kappa = h->hp.kp.kappa;
-  out->eig_sweeps = h->last_sweeps;
+  out->eig_sweeps = s.jac_sweeps;
   out->reserved = 0;
   auto vec = [&](double* dst, const double* src) -> int {
     if (dst) CMX_HIP(hipMemcpy(dst, src, 8ull * n, hipMemcpyDeviceToHost));

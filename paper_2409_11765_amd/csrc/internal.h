@@ -44,7 +44,7 @@ struct StopParams {
 // When enabled, begin/end events are recorded around selected launches; the
 // host folds them into per-kernel totals after the generation.
 enum KernelId { KID_NORMALS = 0, KID_SAMPLE_GEMM, KID_FITNESS, KID_RANK, KID_SYRK, KID_EIG_GEMM,
-                KID_JAC_PAIR, KID_JAC_APPLY, KID_COUNT };
+                KID_JACOBI, KID_COUNT };
 struct KTimer {
   static constexpr int kMax = 4096;
   bool on = false;
@@ -136,18 +136,31 @@ hipError_t launch_dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, c
 // eigensolver
 struct EigWork {
   int N;          // padded size (multiple of 32)
-  double* A;      // N*N
+  double* A;      // N*N, ping-pong with A2
+  double* A2;     // N*N
   double* V;      // N*N
-  double* Q;      // (N/32) * 32*32
+  double* Q;      // (N/32) * 32*32, ping-pong with Q2
+  double* Q2;
   double* T;      // n*n scratch
-  int* flags;     // [0] = significant rotation seen in this sweep
   double* evals;  // N
   int32_t* perm;  // N
   double* sign;   // N
+  double* part;   // 3 * max(n, tiles) partial sums
+  double* scale;  // max |a_ii|
+  int* flags;     // [0] more sweeps needed, [1] non-finite
+  int* status;    // [0] 1 converged, 2 sweep limit, 3 non-finite; [1] sweeps
+  int* hflags;    // pinned host copy of flags
+  // progress of the eigensolve in flight
+  double *Acur, *Anext, *Qcur, *Qnext;
+  int sweeps;
+  bool pending;
 };
-int eigen_solve(hipStream_t st, int n, const double* C, int ldc, double* B, int ldb, double* D,
-                void* BD, bool fp64_bd, int ldbd, EigWork& w, DevScalars* sc, int max_sweeps,
-                int* sweeps_out, KTimer* kt);
+// Queue the warm start and the first convergence test; the host then
+// synchronises the stream and calls eigen_step until it reports done (each
+// call queues one more sweep, or the finishing kernels).
+int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B, int ldb, EigWork& w, KTimer* kt);
+int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, bool fp64_bd, int ldbd, EigWork& w,
+               DevScalars* sc, int max_sweeps, KTimer* kt, bool* done);
 
 // stop tests
 hipError_t launch_stop(hipStream_t st, const KParams& kp, const StopParams& sp, const double* m,
