@@ -266,8 +266,7 @@ __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Ac
                                                    double* __restrict__ V, const double* __restrict__ Qcur,
                                                    double* __restrict__ Qnext, int N, int r,
                                                    const double* __restrict__ scale, double* __restrict__ tilepart) {
-  __shared__ double lds[6 * kS * kLD];
-  __shared__ double red[3][256];
+  __shared__ double lds[5 * kS * kLD];
   double* QA = lds;
   double* QB = lds + kS * kLD;
   double* X = lds + 2 * kS * kLD;
@@ -279,11 +278,9 @@ __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Ac
   int b = blockIdx.x;
   if (b < q) {
     // ---- pair solve of the next round, from recomputed round-r tiles:
-    // the three tiles (Pa,Pa), (Pb,Pb), (Pa,Pb) and both Q's are loaded at
-    // once, transformed, and the next pair's S assembled from them.
-    double* X1 = X;
-    double* X2 = S;
-    double* X3 = lds + 5 * kS * kLD;
+    // the tiles (Pa,Pa), (Pb,Pb), (Pa,Pb) and both Q's are fetched at once
+    // (the last two tiles wait in registers), transformed one after the
+    // other, and the next pair's S assembled from them.
     const bool wrap = (r + 1 == p - 1);
     const int rn = wrap ? 0 : r + 1;
     int In, Jn;
@@ -295,28 +292,22 @@ __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Ac
     const int pi = (In == Ia) ? 0 : kNB, pj = (Jn == Ib) ? 0 : kNB;
     const double* qa = Qcur + static_cast<int64_t>(Pa) * kS * kS;
     const double* qb = Qcur + static_cast<int64_t>(Pb) * kS * kS;
-    for (int idx = t; idx < kS * kS; idx += 256) {
-      const int rr = idx % kS, c = idx / kS;
+    constexpr int PER = kS * kS / 256;
+    double t2[PER], t3[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = t + 256 * k, rr = idx % kS, c = idx / kS;
       QA[rr * kLD + c] = qa[idx];
       QB[rr * kLD + c] = qb[idx];
-      X1[rr * kLD + c] = Acur[static_cast<int64_t>(gidx(Ia, Ja, c)) * N + gidx(Ia, Ja, rr)];
-      X2[rr * kLD + c] = Acur[static_cast<int64_t>(gidx(Ib, Jb, c)) * N + gidx(Ib, Jb, rr)];
-      X3[rr * kLD + c] = Acur[static_cast<int64_t>(gidx(Ib, Jb, c)) * N + gidx(Ia, Ja, rr)];
+      X[rr * kLD + c] = Acur[static_cast<int64_t>(gidx(Ia, Ja, c)) * N + gidx(Ia, Ja, rr)];
+      t2[k] = Acur[static_cast<int64_t>(gidx(Ib, Jb, c)) * N + gidx(Ib, Jb, rr)];
+      t3[k] = Acur[static_cast<int64_t>(gidx(Ib, Jb, c)) * N + gidx(Ia, Ja, rr)];
     }
     __syncthreads();
-    mm32<false>(X1, QA, W);
+    mm32<false>(X, QA, W);
     __syncthreads();
-    mm32<true>(QA, W, X1);  // X1 = Qa^T A[Pa,Pa] Qa
+    mm32<true>(QA, W, X);  // X = Qa^T A[Pa,Pa] Qa
     __syncthreads();
-    mm32<false>(X2, QB, W);
-    __syncthreads();
-    mm32<true>(QB, W, X2);  // X2 = Qb^T A[Pb,Pb] Qb
-    __syncthreads();
-    mm32<false>(X3, QB, W);
-    __syncthreads();
-    mm32<true>(QA, W, X3);  // X3 = Qa^T A[Pa,Pb] Qb
-    __syncthreads();
-    double* Sn = QA;  // the next pair's S (QA and QB are free now)
     if (Pa == Pb) {
       // both blocks of the next pair come from one round-r pair (p = 2)
       const int pjj = (Jn == Ia) ? 0 : kNB;
@@ -324,21 +315,49 @@ __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Ac
         const int rr = idx % kS, c = idx / kS;
         const int sr = rr < kNB ? pi + rr : pjj + rr - kNB;
         const int sc = c < kNB ? pi + c : pjj + c - kNB;
-        Sn[rr * kLD + c] = X1[sr * kLD + sc];
+        S[rr * kLD + c] = X[sr * kLD + sc];
       }
     } else {
       for (int idx = t; idx < kNB * kNB; idx += 256) {
         const int rr = idx % kNB, c = idx / kNB;
-        Sn[rr * kLD + c] = X1[(pi + rr) * kLD + pi + c];
-        Sn[(kNB + rr) * kLD + kNB + c] = X2[(pj + rr) * kLD + pj + c];
-        const double v = X3[(pi + rr) * kLD + pj + c];
-        Sn[rr * kLD + kNB + c] = v;
-        Sn[(kNB + c) * kLD + rr] = v;
+        S[rr * kLD + c] = X[(pi + rr) * kLD + pi + c];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = t + 256 * k;
+        X[(idx % kS) * kLD + idx / kS] = t2[k];
+      }
+      __syncthreads();
+      mm32<false>(X, QB, W);
+      __syncthreads();
+      mm32<true>(QB, W, X);  // X = Qb^T A[Pb,Pb] Qb
+      __syncthreads();
+      for (int idx = t; idx < kNB * kNB; idx += 256) {
+        const int rr = idx % kNB, c = idx / kNB;
+        S[(kNB + rr) * kLD + kNB + c] = X[(pj + rr) * kLD + pj + c];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = t + 256 * k;
+        X[(idx % kS) * kLD + idx / kS] = t3[k];
+      }
+      __syncthreads();
+      mm32<false>(X, QB, W);
+      __syncthreads();
+      mm32<true>(QA, W, X);  // X = Qa^T A[Pa,Pb] Qb
+      __syncthreads();
+      for (int idx = t; idx < kNB * kNB; idx += 256) {
+        const int rr = idx % kNB, c = idx / kNB;
+        const double v = X[(pi + rr) * kLD + pj + c];
+        S[rr * kLD + kNB + c] = v;
+        S[(kNB + c) * kLD + rr] = v;
       }
     }
     __syncthreads();
     __builtin_amdgcn_s_setprio(2);  // the pair solves are the round's critical path
-    rotate_pair(Sn, QB, X1, 2.2e-16 * (*scale), wrap, Qnext + static_cast<int64_t>(b) * kS * kS);
+    rotate_pair(S, X, W, 2.2e-16 * (*scale), wrap, Qnext + static_cast<int64_t>(b) * kS * kS);
     return;
   }
   b -= q;
@@ -373,22 +392,23 @@ __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Ac
       off *= 2.0;
       tot *= 2.0;
     }
-    red[0][t] = off;
-    red[1][t] = tot;
-    red[2][t] = dmax;
+    double* red = W;  // W is free after the transform: 3 x 256 partial sums
+    red[t] = off;
+    red[256 + t] = tot;
+    red[512 + t] = dmax;
     __syncthreads();
     for (int s2 = 128; s2 > 0; s2 >>= 1) {
       if (t < s2) {
-        red[0][t] += red[0][t + s2];
-        red[1][t] += red[1][t + s2];
-        red[2][t] = fmax(red[2][t], red[2][t + s2]);
+        red[t] += red[t + s2];
+        red[256 + t] += red[256 + t + s2];
+        red[512 + t] = fmax(red[512 + t], red[512 + t + s2]);
       }
       __syncthreads();
     }
     if (t == 0) {
-      tilepart[3 * b + 0] = red[0][0];
-      tilepart[3 * b + 1] = red[1][0];
-      tilepart[3 * b + 2] = red[2][0];
+      tilepart[3 * b + 0] = red[0];
+      tilepart[3 * b + 1] = red[256];
+      tilepart[3 * b + 2] = red[512];
     }
     return;
   }
