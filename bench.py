@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=10,
+                    help="generations of the concurrent-restart batch (10 descents, n=200); 0 = skip")
     return ap.parse_args()
 
 
@@ -123,6 +125,30 @@ def run_gpu(P, torch, n, lam, precision, steps, warmup, seed, R, xs):
         es.close()
     return {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "phases_us": phases, "state": st,
             "kernels": kt}
+
+
+def run_batch(P, torch, steps, warmup, seed):
+    """Concurrent restarts: 10 descents, n = 200, lambda_k = 19 * 2^k, rotated
+    Rastrigin, mixed precision; one batch generation advances every descent."""
+    import synth
+    K, n = 10, 200
+    lams = [19 * 2 ** k for k in range(K)]
+    seeds = [seed * 100 + k for k in range(K)]
+    with P.CMAESBatch([n] * K, lams, [2.0] * K, seeds, precision="mixed") as b:
+        for k in range(K):
+            R, xs = synth.problem(n, seeds[k])
+            b.set_objective(k, "rastrigin", R, xs)
+        for _ in range(warmup):
+            b.generation()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.generation()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    return {"workload": "10 concurrent descents, n=200, lambda_k=19*2^k (k=0..9), rotated Rastrigin, mixed",
+            "evals_per_s": sum(lams) * steps / el, "batch_gens_per_s": steps / el,
+            "ms_per_batch_generation": 1e3 * el / steps, "sum_lambda": sum(lams)}
 
 
 def cpu_baseline(n, lam, seed, R, xs, budget_s):
@@ -213,6 +239,8 @@ def main():
     roof["share_of_step"] = kt[dom_k]["total_us"] / (1e3 * mixed["ms_per_step"])
     out["roofline"] = roof
     out["kernels"] = {k: {**kt[k], "roofline": per_kernel.get(k)} for k in kt}
+    if a.batch_steps > 0:
+        out["batch"] = run_batch(P, torch, a.batch_steps, 3, a.seed)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, lam, a.seed, R, xs, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -180,6 +180,31 @@ int cmaes_state(const cmaes_t* h, cmaes_state_t* out);
  * handle.  Clears the stop bits and the f-history of the descent. */
 int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in);
 
+/* ---- batched concurrent descents (K-Distributed, Sec. 3.2.3) ------------
+ * count independent descents of possibly different n and lambda that step
+ * together: instance k is created like cmaes_create(n[k], lambda[k],
+ * sigma0[k], seed[k]) and runs on its own HIP stream.  One batch generation
+ * advances every instance by one generation; an instance whose stop tests
+ * fired is then restarted with the same lambda (fresh mean from its seed
+ * stream, restart index + 1), so the batch keeps its population sizes
+ * (restart-on-finish, Sec. 5).  Returns NULL on failure. */
+typedef struct cmaes_batch cmaes_batch_t;
+cmaes_batch_t* cmaes_batch_create(int count, const int* n, const int* lambda, const double* sigma0,
+                                  const uint64_t* seed);
+void cmaes_batch_destroy(cmaes_batch_t* b);
+/* Number of instances (or a negative error code). */
+int cmaes_batch_count(const cmaes_batch_t* b);
+/* Apply the options to every instance (the stream field is ignored). */
+int cmaes_batch_set_options(cmaes_batch_t* b, const cmaes_options_t* opt);
+/* Fused objective of instance k (as cmaes_set_objective). */
+int cmaes_batch_set_objective(cmaes_batch_t* b, int k, int kind, const double* R, const double* xstar);
+/* One generation of every instance, then restart-on-finish. */
+int cmaes_batch_generation(cmaes_batch_t* b);
+/* State of instance k (as cmaes_state). */
+int cmaes_batch_state(const cmaes_batch_t* b, int k, cmaes_state_t* out);
+/* Best f over all instances and all their descents, and its instance. */
+int cmaes_batch_best(const cmaes_batch_t* b, double* f_best, int* k_best);
+
 /* Device time of the phases of the last generation in microseconds, measured
  * with HIP events when timing is enabled (cmaes_enable_timing).  out holds
  * CMAES_NUM_PHASES doubles: sample, fitness, rank, update, covariance, eigen. */

@@ -5,8 +5,11 @@ package loads its in-tree HIP library on import and fails loudly if it is
 missing; nothing here computes a CMA-ES step on the host.
 """
 
-from .binding import (CMAES, CmaesError, CmaesOptions, KERNELS, OBJECTIVES, PHASES, PRECISIONS, STOP_BITS,  # noqa: F401
+from .binding import (CMAES, CMAESBatch, CmaesError, CmaesOptions, KERNELS, OBJECTIVES, PHASES, PRECISIONS, STOP_BITS,  # noqa: F401
                       cmaes_ask, cmaes_create, cmaes_default_options, cmaes_destroy, cmaes_enable_timing,
                       cmaes_generation, cmaes_generation_with_z, cmaes_get_options, cmaes_ipop_run,
                       cmaes_kernel_times, cmaes_enable_kernel_timing, cmaes_last_error, cmaes_phase_times, cmaes_restart_ipop, cmaes_set_objective,
-                      cmaes_set_options, cmaes_set_state, cmaes_state, cmaes_tell, library, LIB_PATH)
+                      cmaes_set_options, cmaes_set_state, cmaes_state, cmaes_tell, library, LIB_PATH,
+                      cmaes_batch_best, cmaes_batch_count, cmaes_batch_create, cmaes_batch_destroy,
+                      cmaes_batch_generation, cmaes_batch_set_objective, cmaes_batch_set_options,
+                      cmaes_batch_state)

@@ -83,6 +83,14 @@ def _load():
         "cmaes_enable_kernel_timing": (C.c_int, [H, C.c_int]),
         "cmaes_kernel_times": (C.c_int, [H, _PD, C.POINTER(C.c_int64)]),
         "cmaes_last_error": (C.c_char_p, []),
+        "cmaes_batch_create": (H, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _PD, C.POINTER(C.c_uint64)]),
+        "cmaes_batch_destroy": (None, [H]),
+        "cmaes_batch_count": (C.c_int, [H]),
+        "cmaes_batch_set_options": (C.c_int, [H, C.POINTER(CmaesOptions)]),
+        "cmaes_batch_set_objective": (C.c_int, [H, C.c_int, C.c_int, _PD, _PD]),
+        "cmaes_batch_generation": (C.c_int, [H]),
+        "cmaes_batch_state": (C.c_int, [H, C.c_int, C.POINTER(CmaesState)]),
+        "cmaes_batch_best": (C.c_int, [H, _PD, C.POINTER(C.c_int)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -96,7 +104,9 @@ EXPORTED = ["cmaes_default_options", "cmaes_create", "cmaes_destroy", "cmaes_set
             "cmaes_get_options", "cmaes_set_objective", "cmaes_generation", "cmaes_generation_with_z",
             "cmaes_ask", "cmaes_tell", "cmaes_restart_ipop", "cmaes_ipop_run", "cmaes_state",
             "cmaes_set_state", "cmaes_enable_timing", "cmaes_phase_times", "cmaes_enable_kernel_timing",
-            "cmaes_kernel_times", "cmaes_last_error"]
+            "cmaes_kernel_times", "cmaes_last_error", "cmaes_batch_create", "cmaes_batch_destroy",
+            "cmaes_batch_count", "cmaes_batch_set_options", "cmaes_batch_set_objective", "cmaes_batch_generation",
+            "cmaes_batch_state", "cmaes_batch_best"]
 
 
 def library():
@@ -188,9 +198,10 @@ def cmaes_ipop_run(h) -> int:
     return d.value
 
 
-def cmaes_state(h, arrays: bool = True) -> dict:
+def cmaes_state(h, arrays: bool = True, _fetch=None) -> dict:
+    fetch = _fetch or (lambda st: _lib.cmaes_state(h, C.byref(st)))
     s = CmaesState()
-    _check(_lib.cmaes_state(h, C.byref(s)))  # scalars first, to learn n and lambda
+    _check(fetch(s))  # scalars first, to learn n and lambda
     out = {"n": s.n, "lambda": s.lambda_, "mu": s.mu, "restart": s.restart, "gen": s.gen,
            "evals": s.evals, "total_evals": s.total_evals, "sigma": s.sigma, "f_best": s.f_best,
            "stop": s.stop, "kappa": s.kappa, "eig_sweeps": s.eig_sweeps}
@@ -204,7 +215,7 @@ def cmaes_state(h, arrays: bool = True) -> dict:
         for k, v in bufs.items():
             setattr(s, k, _dptr(v))
         s.order = order.ctypes.data_as(_PI)
-        _check(_lib.cmaes_state(h, C.byref(s)))
+        _check(fetch(s))
         out.update(bufs)
         out["order"] = order
         out["sigma"], out["f_best"], out["stop"] = s.sigma, s.f_best, s.stop
@@ -327,3 +338,89 @@ class CMAES:
 
     def kernel_times(self):
         return cmaes_kernel_times(self.h)
+
+
+def cmaes_batch_create(n, lam, sigma0, seed):
+    k = len(n)
+    arr_i = lambda v: (C.c_int * k)(*[int(x) for x in v])
+    b = _lib.cmaes_batch_create(k, arr_i(n), arr_i(lam), (C.c_double * k)(*[float(x) for x in sigma0]),
+                                (C.c_uint64 * k)(*[int(x) & 0xFFFFFFFFFFFFFFFF for x in seed]))
+    if not b:
+        raise CmaesError(CMAES_EINVAL, cmaes_last_error())
+    return b
+
+
+def cmaes_batch_destroy(b):
+    _lib.cmaes_batch_destroy(b)
+
+
+def cmaes_batch_count(b) -> int:
+    return _check(_lib.cmaes_batch_count(b), allow=tuple(range(1, 1 << 20)))
+
+
+def cmaes_batch_set_options(b, opt: CmaesOptions):
+    _check(_lib.cmaes_batch_set_options(b, C.byref(opt)))
+
+
+def cmaes_batch_set_objective(b, k, kind, n, R=None, xstar=None):
+    kk = OBJECTIVES[kind] if isinstance(kind, str) else int(kind)
+    Rf = _colmajor(R, (n, n)) if R is not None else None
+    xs = np.ascontiguousarray(xstar, dtype=np.float64) if xstar is not None else None
+    _check(_lib.cmaes_batch_set_objective(b, int(k), kk, _dptr(Rf), _dptr(xs)))
+
+
+def cmaes_batch_generation(b):
+    _check(_lib.cmaes_batch_generation(b))
+
+
+def cmaes_batch_state(b, k, arrays: bool = True) -> dict:
+    return cmaes_state(b, arrays, _fetch=lambda st: _lib.cmaes_batch_state(b, int(k), C.byref(st)))
+
+
+def cmaes_batch_best(b):
+    f = C.c_double(0.0)
+    k = C.c_int(-1)
+    _check(_lib.cmaes_batch_best(b, C.byref(f), C.byref(k)))
+    return f.value, k.value
+
+
+class CMAESBatch:
+    """Owning wrapper of a batch of concurrent descents."""
+
+    def __init__(self, n, lam, sigma0, seed, precision="mixed", **options):
+        self.b = cmaes_batch_create(n, lam, sigma0, seed)
+        self.n = list(n)
+        opt = cmaes_default_options()
+        opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        for k, v in options.items():
+            setattr(opt, k, v)
+        cmaes_batch_set_options(self.b, opt)
+
+    def set_objective(self, k, kind, R=None, xstar=None):
+        cmaes_batch_set_objective(self.b, k, kind, self.n[k], R, xstar)
+
+    def generation(self):
+        cmaes_batch_generation(self.b)
+
+    def state(self, k, arrays=True):
+        return cmaes_batch_state(self.b, k, arrays)
+
+    def best(self):
+        return cmaes_batch_best(self.b)
+
+    def close(self):
+        if self.b:
+            cmaes_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -834,3 +834,148 @@ int cmaes_phase_times(const cmaes_t* h, double* out) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched concurrent descents (K-Distributed, Sec. 3.2.3): every instance is a
+// full handle with its own stream, so the hardware interleaves the kernels of
+// all instances; a batch generation queues every instance up to its
+// eigensolve, then advances all sweeps in lockstep with one host
+// synchronisation per sweep for the whole batch.  An instance whose stop
+// tests fire is restarted with the same population size (restart-on-finish).
+
+struct cmaes_batch {
+  std::vector<cmaes*> inst;
+  std::vector<int32_t> restarts;
+};
+
+namespace {
+
+int restart_same_lambda(cmaes* h) {
+  CMX_HIP(hipStreamSynchronize(h->st));
+  h->restart += 1;
+  return init_descent(h, false);
+}
+
+int batch_check(const cmaes_batch* b, int k) {
+  if (!b) return fail(CMAES_EINVAL, "null batch");
+  if (k < 0 || k >= static_cast<int>(b->inst.size())) return fail(CMAES_EINVAL, "instance index out of range");
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+cmaes_batch_t* cmaes_batch_create(int count, const int* n, const int* lambda, const double* sigma0,
+                                  const uint64_t* seed) {
+  if (count < 1 || count > 1024 || !n || !lambda || !sigma0 || !seed) {
+    set_error("cmaes_batch_create: need 1..1024 instances and non-null size arrays");
+    return nullptr;
+  }
+  cmaes_batch* b = new (std::nothrow) cmaes_batch();
+  if (!b) {
+    set_error("host allocation failed");
+    return nullptr;
+  }
+  for (int k = 0; k < count; ++k) {
+    cmaes* h = cmaes_create(n[k], lambda[k], sigma0[k], seed[k]);
+    if (!h) {
+      const std::string why = g_err;
+      cmaes_batch_destroy(b);
+      set_error("instance " + std::to_string(k) + ": " + why);
+      return nullptr;
+    }
+    b->inst.push_back(h);
+    b->restarts.push_back(0);
+  }
+  return b;
+}
+
+void cmaes_batch_destroy(cmaes_batch_t* b) {
+  if (!b) return;
+  for (cmaes* h : b->inst) cmaes_destroy(h);
+  delete b;
+}
+
+int cmaes_batch_count(const cmaes_batch_t* b) {
+  if (!b) return fail(CMAES_EINVAL, "null batch");
+  return static_cast<int>(b->inst.size());
+}
+
+int cmaes_batch_set_options(cmaes_batch_t* b, const cmaes_options_t* opt) {
+  if (!b) return fail(CMAES_EINVAL, "null batch");
+  if (!opt) return fail(CMAES_EINVAL, "null options");
+  cmaes_options_t o = *opt;
+  for (cmaes* h : b->inst) {
+    o.stream = h->opt.stream;  // every instance keeps its own stream
+    if (int rc = cmaes_set_options(h, &o)) return rc;
+  }
+  return CMAES_OK;
+}
+
+int cmaes_batch_set_objective(cmaes_batch_t* b, int k, int kind, const double* R, const double* xstar) {
+  if (int rc = batch_check(b, k)) return rc;
+  return cmaes_set_objective(b->inst[k], kind, R, xstar);
+}
+
+int cmaes_batch_generation(cmaes_batch_t* b) {
+  if (!b) return fail(CMAES_EINVAL, "null batch");
+  for (cmaes* h : b->inst)
+    if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "every instance needs a fused objective");
+  for (cmaes* h : b->inst) {
+    if (int rc = ensure_ready(h)) return rc;
+    if (int rc = phase_sample(h, nullptr)) return rc;
+    if (int rc = phase_fitness(h)) return rc;
+    if (int rc = phase_update_pre(h)) return rc;
+  }
+  std::vector<cmaes*> pending;
+  for (cmaes* h : b->inst)
+    if (h->eig_due) pending.push_back(h);
+  while (!pending.empty()) {
+    for (cmaes* h : pending) CMX_HIP(hipStreamSynchronize(h->st));
+    std::vector<cmaes*> still;
+    for (cmaes* h : pending) {
+      bool done = false;
+      if (int rc = eigen_advance(h, &done)) return rc;
+      if (!done) still.push_back(h);
+    }
+    pending.swap(still);
+  }
+  for (cmaes* h : b->inst)
+    if (int rc = phase_update_post(h)) return rc;
+  // restart-on-finish with the same population size
+  for (size_t k = 0; k < b->inst.size(); ++k) {
+    cmaes* h = b->inst[k];
+    DevScalars s;
+    if (int rc = read_scalars(h, &s)) return rc;
+    if (s.stop) {
+      if (int rc = restart_same_lambda(h)) return rc;
+      b->restarts[k] += 1;
+    }
+  }
+  return CMAES_OK;
+}
+
+int cmaes_batch_state(const cmaes_batch_t* b, int k, cmaes_state_t* out) {
+  if (int rc = batch_check(b, k)) return rc;
+  return cmaes_state(b->inst[k], out);
+}
+
+int cmaes_batch_best(const cmaes_batch_t* b, double* f_best, int* k_best) {
+  if (!b) return fail(CMAES_EINVAL, "null batch");
+  double best = HUGE_VAL;
+  int arg = -1;
+  for (size_t k = 0; k < b->inst.size(); ++k) {
+    DevScalars s;
+    if (int rc = read_scalars(b->inst[k], &s)) return rc;
+    if (s.f_best < best) {
+      best = s.f_best;
+      arg = static_cast<int>(k);
+    }
+  }
+  if (f_best) *f_best = best;
+  if (k_best) *k_best = arg;
+  return CMAES_OK;
+}
+
+}  // extern "C"

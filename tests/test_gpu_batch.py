@@ -1,0 +1,82 @@
+"""GPU tests of the batched concurrent descents (K-Distributed, Sec. 3.2.3):
+a batch instance evolves bit-identically to the same descent run alone, stopped
+instances restart with the same population size, and the uneven-size batch of
+the concurrent-restart workload (n = 200, lambda_k = 19 * 2^k) runs."""
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_11765_amd as P
+    return P
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_instance_equals_solo_run(P, precision):
+    ns, lams, seeds = [10, 37, 64], [10, 20, 40], [5, 6, 7]
+    sig = [2.0, 1.5, 1.0]
+    gens = 6
+    with P.CMAESBatch(ns, lams, sig, seeds, precision=precision, eigen_interval=1) as b:
+        for k, n in enumerate(ns):
+            R, xs = synth.problem(n, 100 + k)
+            b.set_objective(k, "rastrigin", R, xs)
+        for _ in range(gens):
+            b.generation()
+        got = [b.state(k) for k in range(len(ns))]
+    for k, n in enumerate(ns):
+        R, xs = synth.problem(n, 100 + k)
+        with P.CMAES(n, lams[k], sig[k], seed=seeds[k], precision=precision, objective="rastrigin", R=R,
+                     xstar=xs, eigen_interval=1) as es:
+            for _ in range(gens):
+                es.generation()
+            want = es.state()
+        for key in ("m", "C", "B", "D", "p_sigma", "p_c", "f"):
+            assert np.array_equal(got[k][key], want[key]), (k, key)
+        assert got[k]["sigma"] == want["sigma"] and got[k]["gen"] == want["gen"] == gens
+
+
+def test_batch_restart_on_finish_keeps_lambda(P):
+    with P.CMAESBatch([12, 12], [8, 16], [2.0, 2.0], [1, 2], precision="fp64", max_gens=3) as b:
+        for k in range(2):
+            b.set_objective(k, "sphere")
+        for _ in range(4):
+            b.generation()
+        s = [b.state(k, arrays=False) for k in range(2)]
+        f, kb = b.best()
+    for k, lam in enumerate([8, 16]):
+        assert s[k]["lambda"] == lam
+        assert s[k]["restart"] == 1          # stopped after 3 generations, restarted once
+        assert s[k]["gen"] == 1              # one generation into the new descent
+        assert s[k]["total_evals"] == 4 * lam
+    assert kb in (0, 1) and f == min(s[0]["f_best"], s[1]["f_best"])
+
+
+def test_concurrent_restart_workload_runs(P):
+    """10 instances, n = 200, lambda_k = 19 * 2^k (k = 0..9), rotated Rastrigin
+    with per-instance seeds, mixed precision."""
+    K, n = 10, 200
+    lams = [19 * 2 ** k for k in range(K)]
+    seeds = [100 + k for k in range(K)]
+    with P.CMAESBatch([n] * K, lams, [2.0] * K, seeds, precision="mixed") as b:
+        for k in range(K):
+            R, xs = synth.problem(n, seeds[k])
+            b.set_objective(k, "rastrigin", R, xs)
+        for _ in range(3):
+            b.generation()
+        for k in range(K):
+            s = b.state(k)
+            assert s["lambda"] == lams[k] and s["total_evals"] == 3 * lams[k]
+            assert np.all(np.isfinite(s["m"])) and np.isfinite(s["sigma"])
+            C, B, D = s["C"], s["B"], s["D"]
+            assert np.max(np.abs(B.T @ B - np.eye(n))) <= 1e-12
+            if s["gen"] % s["kappa"] == 0:   # the decomposition ran in this generation
+                assert np.linalg.norm(B @ np.diag(D ** 2) @ B.T - C) <= 1e-12 * np.linalg.norm(C)
