@@ -357,7 +357,11 @@ int phase_sample(cmaes* h, const double* Zhost) {
     kt_end(&h->kt);
   }
   kt_begin(&h->kt, KID_SAMPLE_GEMM);
-  CMX_HIP(launch_sample_gemm(h->st, h->fp64, n, lam, h->BD, ldn, h->Z, ldn, h->Y, ldn));
+  if (h->opt.precision == CMAES_MIXED_BF16X3)
+    CMX_HIP(launch_sample_gemm_bf16x3(h->st, n, lam, static_cast<const float*>(h->BD), ldn,
+                                      static_cast<const float*>(h->Z), ldn, static_cast<float*>(h->Y), ldn));
+  else
+    CMX_HIP(launch_sample_gemm(h->st, h->fp64, n, lam, h->BD, ldn, h->Z, ldn, h->Y, ldn));
   kt_end(&h->kt);
   rec(h, 1);
   return 0;

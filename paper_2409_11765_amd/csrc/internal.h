@@ -98,6 +98,9 @@ struct FitnessArgs {
 };
 hipError_t launch_sample_gemm(hipStream_t st, bool fp64, int n, int lam, const void* BD, int ldbd,
                               const void* Z, int ldz, void* Y, int ldy);
+// y = (B D) z as bf16 x 3 split products with float32 accumulation
+hipError_t launch_sample_gemm_bf16x3(hipStream_t st, int n, int lam, const float* BD, int ldbd, const float* Z,
+                                     int ldz, float* Y, int ldy);
 hipError_t launch_fitness_gemm(hipStream_t st, bool fp64, int n, int lam, const void* R, int ldr,
                                const void* Y, int ldy, const FitnessArgs& fa, int* row_tiles);
 hipError_t launch_fitness_direct(hipStream_t st, bool fp64, int n, int lam, const void* Y, int ldy,

@@ -1,0 +1,58 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times: one generation from an injected state and injected z at
+n = 1000, lambda = 6144 (rotated Rastrigin; mixed and float64 paths) and at
+n = 2000, lambda = 4096 (rotated ellipsoid, bf16 x 3 sampling), against the
+FP64 oracle run on the whole population."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from helpers import TOL, one_generation, oracle_state, rank_agreement, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_11765_amd as P
+    return P
+
+
+CASES = [
+    (1000, 6144, "rastrigin", "mixed"),
+    (1000, 6144, "rastrigin", "fp64"),
+    (2000, 4096, "ellipsoid", "mixed_bf16x3"),
+    (257, 1030, "ellipsoid", "mixed_bf16x3"),
+    (37, 53, "rastrigin", "mixed_bf16x3"),
+]
+
+
+@pytest.mark.parametrize("n,lam,kind,precision", CASES)
+def test_full_size_generation(P, n, lam, kind, precision):
+    print(f"case n={n} lam={lam} {kind} {precision}", flush=True)
+    st = synth.random_state(n, lam, seed=n + lam, cond=1e3)
+    R, xs = synth.problem(n, seed=n)
+    Z = synth.normal_matrix(n, lam, seed=lam)
+    g, o, info = one_generation(P, st, Z, kind, R, xs, precision)
+    tol = 1e-12 if precision == "fp64" else TOL["mixed"]
+    if precision != "fp64":
+        # reduced-precision fitness can reorder near-ties (checked below with
+        # tau); the update arithmetic is compared for the device's ranking by
+        # driving the oracle with the device's fitness values
+        o = oracle_state(st)
+        O.generation(o, None, Z=Z, fvals=g["f"])
+    errs = {"m": rel(g["m"], o.m), "C": rel(g["C"], o.C), "sigma": abs(g["sigma"] - o.sigma) / o.sigma,
+            "p_sigma": rel(g["p_sigma"], o.ps), "p_c": rel(g["p_c"], o.pc)}
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v < tol, (k, v)
+    f_ref = info["f"]
+    ftol = 1e-12 if precision == "fp64" else 2e-5
+    assert np.max(np.abs(g["f"] - f_ref)) <= ftol * np.max(np.abs(f_ref))
+    tau = 1e-10 if precision == "fp64" else 1e-4
+    assert rank_agreement(f_ref, g["order"], info["order"], tau) == 0
