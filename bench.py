@@ -79,16 +79,31 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=10,
                     help="generations of the concurrent-restart batch (10 descents, n=200); 0 = skip")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default float32 GEMM tiles")
+    ap.add_argument("--tiles", default=None, help="force tiles: sample,fitness,syrk configuration indices")
     return ap.parse_args()
 
 
-def run_gpu(P, torch, n, lam, precision, steps, warmup, seed, R, xs):
+def run_gpu(P, torch, n, lam, precision, steps, warmup, seed, R, xs, tune=True, tiles=None):
     # a dedicated (default-priority) torch stream, handed to the library, so
     # the timing events below bracket exactly the library's work
     stream = torch.cuda.Stream()
     es = P.CMAES(n, lam, 2.0, seed=seed, precision=precision, objective="rastrigin", R=R, xstar=xs,
                  stream=stream.cuda_stream)
+    tiles_out = None
     try:
+        if precision != "fp64":
+            # the float32 GEMM tiles for this shape (untimed set-up)
+            if tiles is not None:
+                for site, cfg in zip(P.SITES, tiles):
+                    es.set_gemm_config(site, cfg)
+            elif tune:
+                es.autotune(reps=10)
+            tiles_out = {site: {"config": es.gemm_config(site),
+                                "tile": P.cmaes_gemm_config_info(es.gemm_config(site))} for site in P.SITES}
+            if hasattr(es, "last_tune_us"):
+                tiles_out["tune_us"] = {site: [round(float(v), 2) for v in row]
+                                        for site, row in zip(P.SITES, es.last_tune_us)}
         for _ in range(warmup):
             es.generation()
         torch.cuda.synchronize()
@@ -124,7 +139,7 @@ def run_gpu(P, torch, n, lam, precision, steps, warmup, seed, R, xs):
     finally:
         es.close()
     return {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "phases_us": phases, "state": st,
-            "kernels": kt}
+            "kernels": kt, "tiles": tiles_out}
 
 
 def run_batch(P, torch, steps, warmup, seed):
@@ -187,7 +202,9 @@ def main():
     n, lam = a.n, a.lam
     R, xs = synth.problem(n, a.seed)
     torch.cuda.set_device(0)
-    mixed = run_gpu(P, torch, n, lam, a.precision, a.steps, a.warmup, a.seed, R, xs)
+    tiles = [int(v) for v in a.tiles.split(",")] if a.tiles else None
+    mixed = run_gpu(P, torch, n, lam, a.precision, a.steps, a.warmup, a.seed, R, xs, tune=not a.no_tune,
+                    tiles=tiles)
     fp64 = None
     if not a.no_fp64:
         fp64 = run_gpu(P, torch, n, lam, "fp64", a.fp64_steps, 2, a.seed, R, xs)
@@ -239,6 +256,7 @@ def main():
     roof["share_of_step"] = kt[dom_k]["total_us"] / (1e3 * mixed["ms_per_step"])
     out["roofline"] = roof
     out["kernels"] = {k: {**kt[k], "roofline": per_kernel.get(k)} for k in kt}
+    out["gemm_tiles"] = mixed["tiles"]
     if a.batch_steps > 0:
         out["batch"] = run_batch(P, torch, a.batch_steps, 3, a.seed)
     if not a.no_cpu_baseline:

@@ -227,6 +227,40 @@ int cmaes_phase_times(const cmaes_t* h, double* out);
 int cmaes_enable_kernel_timing(cmaes_t* h, int on);
 int cmaes_kernel_times(const cmaes_t* h, double* total_us, int64_t* calls);
 
+/* ---- float32 GEMM tiles and their tuner (Sec. 3.1 GEMM reformulation) -----
+ * In CMAES_MIXED and CMAES_MIXED_BF16X3 the float32 MFMA products -- the
+ * sampling product (B D) Z of eq. (1), the rotated-objective product R Y whose
+ * epilogue reduces f, and the split-k rank-mu product of eq. (3) -- each run
+ * one of CMAES_NUM_GEMM_CONFIGS block tiles (BM x BN x BK).  The tile changes
+ * speed only: the sampling product is bit-identical for every tile; the
+ * fitness and covariance sums change by float32 rounding.  CMAES_FP64 and the
+ * bf16x3 sampling product have one tile and are not tuned.
+ *
+ * cmaes_gemm_config_info: the tile of configuration cfg (no device needed).
+ * cmaes_set_gemm_config / cmaes_get_gemm_config: the tile of call site `site`
+ *   (CMAES_SITE_*); CMAES_EINVAL for a tile the site cannot run (the
+ *   covariance site takes square tiles only).  Default: configuration 0.
+ * cmaes_autotune: times every configuration `reps` times at each tunable site
+ *   on the handle's current (n, lambda) and keeps the fastest.  us (NULL or
+ *   CMAES_NUM_SITES * cmaes_gemm_config_count() doubles, site-major) receives
+ *   the mean microseconds per launch, -1 where not timed; chosen (NULL or
+ *   CMAES_NUM_SITES) the selected configurations.  Leaves the search state
+ *   untouched (the covariance site is timed without its C update); refused
+ *   between ask and tell (CMAES_ESTATE).  Blocks until done.
+ * cmaes_device_arch: the current device's architecture name (e.g. "gfx950"),
+ *   NUL-terminated into buf of len bytes; the key of a tuning cache. */
+#define CMAES_SITE_SAMPLE 0
+#define CMAES_SITE_FITNESS 1
+#define CMAES_SITE_SYRK 2
+#define CMAES_NUM_SITES 3
+#define CMAES_NUM_GEMM_CONFIGS 7
+int cmaes_gemm_config_count(void);
+int cmaes_gemm_config_info(int cfg, int32_t* bm, int32_t* bn, int32_t* bk);
+int cmaes_set_gemm_config(cmaes_t* h, int site, int cfg);
+int cmaes_get_gemm_config(const cmaes_t* h, int site, int32_t* cfg);
+int cmaes_autotune(cmaes_t* h, int reps, double* us, int32_t* chosen);
+int cmaes_device_arch(char* buf, int len);
+
 /* Thread-local message for the last failing call (never NULL). */
 const char* cmaes_last_error(void);
 

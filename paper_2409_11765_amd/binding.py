@@ -12,10 +12,12 @@ ImportError (there is no fallback implementation).
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import numpy as np
 
+_PI32 = C.POINTER(C.c_int32)
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcmaes_mi355x.so")
 
@@ -83,6 +85,12 @@ def _load():
         "cmaes_enable_kernel_timing": (C.c_int, [H, C.c_int]),
         "cmaes_kernel_times": (C.c_int, [H, _PD, C.POINTER(C.c_int64)]),
         "cmaes_last_error": (C.c_char_p, []),
+        "cmaes_gemm_config_count": (C.c_int, []),
+        "cmaes_gemm_config_info": (C.c_int, [C.c_int, _PI32, _PI32, _PI32]),
+        "cmaes_set_gemm_config": (C.c_int, [H, C.c_int, C.c_int]),
+        "cmaes_get_gemm_config": (C.c_int, [H, C.c_int, _PI32]),
+        "cmaes_autotune": (C.c_int, [H, C.c_int, _PD, _PI32]),
+        "cmaes_device_arch": (C.c_int, [C.c_char_p, C.c_int]),
         "cmaes_batch_create": (H, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _PD, C.POINTER(C.c_uint64)]),
         "cmaes_batch_destroy": (None, [H]),
         "cmaes_batch_count": (C.c_int, [H]),
@@ -104,7 +112,9 @@ EXPORTED = ["cmaes_default_options", "cmaes_create", "cmaes_destroy", "cmaes_set
             "cmaes_get_options", "cmaes_set_objective", "cmaes_generation", "cmaes_generation_with_z",
             "cmaes_ask", "cmaes_tell", "cmaes_restart_ipop", "cmaes_ipop_run", "cmaes_state",
             "cmaes_set_state", "cmaes_enable_timing", "cmaes_phase_times", "cmaes_enable_kernel_timing",
-            "cmaes_kernel_times", "cmaes_last_error", "cmaes_batch_create", "cmaes_batch_destroy",
+            "cmaes_kernel_times", "cmaes_last_error", "cmaes_gemm_config_count", "cmaes_gemm_config_info",
+            "cmaes_set_gemm_config", "cmaes_get_gemm_config", "cmaes_autotune", "cmaes_device_arch",
+            "cmaes_batch_create", "cmaes_batch_destroy",
             "cmaes_batch_count", "cmaes_batch_set_options", "cmaes_batch_set_objective", "cmaes_batch_generation",
             "cmaes_batch_state", "cmaes_batch_best"]
 
@@ -264,6 +274,52 @@ def cmaes_kernel_times(h) -> dict:
             for k, t, c in zip(KERNELS, tot, cnt)}
 
 
+SITES = ["sample", "fitness", "syrk"]
+
+
+def cmaes_gemm_config_count() -> int:
+    return int(_lib.cmaes_gemm_config_count())
+
+
+def cmaes_gemm_config_info(cfg: int) -> tuple:
+    v = [C.c_int32() for _ in range(3)]
+    _check(_lib.cmaes_gemm_config_info(cfg, *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def _site(site):
+    return SITES.index(site) if isinstance(site, str) else int(site)
+
+
+def cmaes_set_gemm_config(h, site, cfg: int):
+    _check(_lib.cmaes_set_gemm_config(h, _site(site), int(cfg)))
+
+
+def cmaes_get_gemm_config(h, site) -> int:
+    v = C.c_int32()
+    _check(_lib.cmaes_get_gemm_config(h, _site(site), C.byref(v)))
+    return v.value
+
+
+def cmaes_autotune(h, reps: int = 10):
+    """Times every tile at each tunable site; returns (us[site][cfg], chosen[site])."""
+    nc = cmaes_gemm_config_count()
+    us = np.zeros(len(SITES) * nc)
+    chosen = (C.c_int32 * len(SITES))()
+    _check(_lib.cmaes_autotune(h, int(reps), _dptr(us), chosen))
+    return us.reshape(len(SITES), nc), list(chosen)
+
+
+def cmaes_device_arch() -> str:
+    buf = C.create_string_buffer(128)
+    _check(_lib.cmaes_device_arch(buf, len(buf)))
+    return buf.value.decode()
+
+
+def _tune_key(n, lam, precision):
+    return f"{cmaes_device_arch()}|n={n}|lam={lam}|precision={precision}"
+
+
 class CMAES:
     """Owning wrapper of one handle (one descent plus its IPOP restarts)."""
 
@@ -335,6 +391,40 @@ class CMAES:
 
     def enable_kernel_timing(self, on=True):
         cmaes_enable_kernel_timing(self.h, on)
+
+    def gemm_config(self, site):
+        return cmaes_get_gemm_config(self.h, site)
+
+    def set_gemm_config(self, site, cfg):
+        cmaes_set_gemm_config(self.h, site, cfg)
+
+    def autotune(self, reps=10, cache=None):
+        """Select the float32 GEMM tiles for the current (n, lambda).
+
+        With ``cache`` (a JSON file path) a previous choice for the same device
+        architecture, shape and precision is reused and new choices are added.
+        Returns {site: configuration}.
+        """
+        opt = cmaes_get_options(self.h)
+        key = _tune_key(self.n, self.lam, int(opt.precision))
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+        if key in table:
+            for site, cfg in table[key]["chosen"].items():
+                cmaes_set_gemm_config(self.h, site, cfg)
+            return dict(table[key]["chosen"])
+        us, chosen = cmaes_autotune(self.h, reps)
+        res = dict(zip(SITES, chosen))
+        if cache:
+            table[key] = {"chosen": res, "us": us.tolist()}
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        self.last_tune_us = us
+        return res
 
     def kernel_times(self):
         return cmaes_kernel_times(self.h)

@@ -24,6 +24,10 @@ int fail(int code, const std::string& msg) {
 
 using namespace cmx;
 
+static_assert(CMAES_NUM_GEMM_CONFIGS == kG32NumConfigs, "tile table and header disagree");
+static_assert(CMAES_NUM_SITES == G32_NUM_SITES && CMAES_SITE_SYRK == G32_SYRK, "GEMM sites and header disagree");
+static_assert(CMAES_NUM_KERNELS == KID_COUNT, "kernel ids and header disagree");
+
 namespace {
 
 // tutorial default parameters (positive weights), identical to the oracle's reading
@@ -106,6 +110,7 @@ struct cmaes {
   double phase_us[CMAES_NUM_PHASES] = {};
   KTimer kt;
   bool eig_due = false;
+  int gcfg[G32_NUM_SITES] = {0, 0, 0};  // float32 GEMM tile per call site
 
   // float64 state
   DevScalars* sc = nullptr;
@@ -213,7 +218,10 @@ int alloc_pop(cmaes* h) {
   {
     int ntl, splits, kspan;
     size_t we;
-    syrk_plan(h->fp64, n, mu, &ntl, &splits, &kspan, &we);
+    if (h->fp64)
+      syrk_plan(true, n, mu, &ntl, &splits, &kspan, &we);
+    else
+      we = syrk32_max_work(n, mu);
     if ((rc = dev_alloc(&h->syrk_work, e * we))) return rc;
   }
   h->cap_lam = lam;
@@ -360,8 +368,11 @@ int phase_sample(cmaes* h, const double* Zhost) {
   if (h->opt.precision == CMAES_MIXED_BF16X3)
     CMX_HIP(launch_sample_gemm_bf16x3(h->st, n, lam, static_cast<const float*>(h->BD), ldn,
                                       static_cast<const float*>(h->Z), ldn, static_cast<float*>(h->Y), ldn));
+  else if (h->fp64)
+    CMX_HIP(launch_sample_gemm(h->st, true, n, lam, h->BD, ldn, h->Z, ldn, h->Y, ldn));
   else
-    CMX_HIP(launch_sample_gemm(h->st, h->fp64, n, lam, h->BD, ldn, h->Z, ldn, h->Y, ldn));
+    CMX_HIP(g32_gemm(h->st, h->gcfg[G32_SAMPLE], G32_SAMPLE, n, lam, n, static_cast<const float*>(h->BD), ldn,
+                     static_cast<const float*>(h->Z), ldn, h->Y, ldn, nullptr));
   kt_end(&h->kt);
   rec(h, 1);
   return 0;
@@ -374,8 +385,13 @@ int phase_fitness(cmaes* h) {
   FitnessArgs fa{h->obj_kind, h->d, h->coef, h->sc, h->partial, lam};
   int tiles = 0;
   kt_begin(&h->kt, KID_FITNESS);
-  if (h->have_R)
-    CMX_HIP(launch_fitness_gemm(h->st, h->fp64, n, lam, h->Rt, ldn, h->Y, ldn, fa, &tiles));
+  if (h->have_R && !h->fp64) {
+    const G32FitArgs ga{h->obj_kind, h->d, static_cast<const float*>(h->coef), h->sc};
+    tiles = g32_row_tiles(h->gcfg[G32_FITNESS], n);
+    CMX_HIP(g32_gemm(h->st, h->gcfg[G32_FITNESS], G32_FITNESS, n, lam, n, static_cast<const float*>(h->Rt), ldn,
+                     static_cast<const float*>(h->Y), ldn, h->partial, lam, &ga));
+  } else if (h->have_R)
+    CMX_HIP(launch_fitness_gemm(h->st, true, n, lam, h->Rt, ldn, h->Y, ldn, fa, &tiles));
   else
     CMX_HIP(launch_fitness_direct(h->st, h->fp64, n, lam, h->Y, ldn, fa, &tiles));
   kt_end(&h->kt);
@@ -402,8 +418,12 @@ int phase_update_pre(cmaes* h) {
   CMX_HIP(launch_vec_update(h->st, h->hp.kp, nchb, h->part_bz, h->yw, h->m, h->ps, h->pc, h->sc));
   rec(h, 4);
   kt_begin(&h->kt, KID_SYRK);
-  CMX_HIP(launch_syrk_update(h->st, h->fp64, n, mu, h->Ysel, ldn, h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc,
-                             h->syrk_work));
+  if (h->fp64)
+    CMX_HIP(launch_syrk_update(h->st, true, n, mu, h->Ysel, ldn, h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc,
+                               h->syrk_work));
+  else
+    CMX_HIP(g32_syrk(h->st, h->gcfg[G32_SYRK], n, mu, static_cast<const float*>(h->Ysel), ldn,
+                     static_cast<float*>(h->syrk_work), h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc, false));
   kt_end(&h->kt);
   rec(h, 5);
   h->gen += 1;
@@ -834,6 +854,104 @@ int cmaes_phase_times(const cmaes_t* h, double* out) {
   if (int rc = check(h)) return rc;
   if (!out) return fail(CMAES_EINVAL, "null output");
   for (int i = 0; i < CMAES_NUM_PHASES; ++i) out[i] = h->phase_us[i];
+  return CMAES_OK;
+}
+
+int cmaes_gemm_config_count(void) { return kG32NumConfigs; }
+
+int cmaes_gemm_config_info(int cfg, int32_t* bm, int32_t* bn, int32_t* bk) {
+  if (cfg < 0 || cfg >= kG32NumConfigs) return fail(CMAES_EINVAL, "no such tile configuration");
+  if (bm) *bm = kG32Configs[cfg].bm;
+  if (bn) *bn = kG32Configs[cfg].bn;
+  if (bk) *bk = kG32Configs[cfg].bk;
+  return CMAES_OK;
+}
+
+int cmaes_set_gemm_config(cmaes_t* h, int site, int cfg) {
+  if (int rc = check(h)) return rc;
+  if (site < 0 || site >= G32_NUM_SITES) return fail(CMAES_EINVAL, "no such GEMM site");
+  if (!g32_config_valid(cfg, site)) return fail(CMAES_EINVAL, "tile configuration not available at this site");
+  h->gcfg[site] = cfg;
+  return CMAES_OK;
+}
+
+int cmaes_get_gemm_config(const cmaes_t* h, int site, int32_t* cfg) {
+  if (int rc = check(h)) return rc;
+  if (site < 0 || site >= G32_NUM_SITES || !cfg) return fail(CMAES_EINVAL, "bad site or null output");
+  *cfg = h->gcfg[site];
+  return CMAES_OK;
+}
+
+int cmaes_autotune(cmaes_t* h, int reps, double* us, int32_t* chosen) {
+  if (int rc = check(h)) return rc;
+  if (reps < 1) return fail(CMAES_EINVAL, "reps must be positive");
+  if (h->ask_pending) return fail(CMAES_ESTATE, "autotune between ask and tell");
+  if (int rc = ensure_ready(h)) return rc;
+  if (us)
+    for (int i = 0; i < G32_NUM_SITES * kG32NumConfigs; ++i) us[i] = -1.0;
+  if (!h->fp64) {
+    const int n = h->n, lam = h->lam, ldn = h->ldn, mu = h->hp.kp.mu;
+    // operands with the next generation's statistics: its own normals and the
+    // current B D; the next generation redraws Z and rewrites Y, Ysel
+    CMX_HIP(launch_normals(h->st, h->Z, false, ldn, n, lam, h->seed, static_cast<uint32_t>(h->restart), h->sc));
+    CMX_HIP(hipMemcpyAsync(h->Y, h->Z, 4ull * ldn * lam, hipMemcpyDeviceToDevice, h->st));
+    CMX_HIP(hipMemcpyAsync(h->Ysel, h->Z, 4ull * ldn * mu, hipMemcpyDeviceToDevice, h->st));
+    hipEvent_t e0, e1;
+    CMX_HIP(hipEventCreate(&e0));
+    CMX_HIP(hipEventCreate(&e1));
+    const G32FitArgs ga{h->obj_kind, h->d, static_cast<const float*>(h->coef), h->sc};
+    int rc = CMAES_OK;
+    for (int site = 0; site < G32_NUM_SITES && rc == CMAES_OK; ++site) {
+      if (site == G32_SAMPLE && h->opt.precision == CMAES_MIXED_BF16X3) continue;
+      if (site == G32_FITNESS && !(h->have_R && h->obj_kind != CMAES_OBJ_NONE)) continue;
+      double best = HUGE_VAL;
+      for (int c = 0; c < kG32NumConfigs && rc == CMAES_OK; ++c) {
+        if (!g32_config_valid(c, site)) continue;
+        auto launch = [&]() -> hipError_t {
+          if (site == G32_SAMPLE)
+            return g32_gemm(h->st, c, site, n, lam, n, static_cast<const float*>(h->BD), ldn,
+                            static_cast<const float*>(h->Z), ldn, h->Y, ldn, nullptr);
+          if (site == G32_FITNESS)
+            return g32_gemm(h->st, c, site, n, lam, n, static_cast<const float*>(h->Rt), ldn,
+                            static_cast<const float*>(h->Y), ldn, h->partial, lam, &ga);
+          return g32_syrk(h->st, c, n, mu, static_cast<const float*>(h->Ysel), ldn, static_cast<float*>(h->syrk_work),
+                          h->C, ldn, h->pc, 0.0, 0.0, h->sc, true);
+        };
+        hipError_t e = launch();  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, h->st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, h->st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          rc = fail(CMAES_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+          break;
+        }
+        const double t = 1e3 * ms / reps;
+        if (us) us[site * kG32NumConfigs + c] = t;
+        if (t < best) {
+          best = t;
+          h->gcfg[site] = c;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+  }
+  if (chosen)
+    for (int i = 0; i < G32_NUM_SITES; ++i) chosen[i] = h->gcfg[i];
+  return CMAES_OK;
+}
+
+int cmaes_device_arch(char* buf, int len) {
+  if (!buf || len < 1) return fail(CMAES_EINVAL, "null or empty buffer");
+  int dev = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess)
+    return fail(CMAES_EDEVICE, "no HIP device");
+  std::snprintf(buf, static_cast<size_t>(len), "%s", p.gcnArchName);
   return CMAES_OK;
 }
 

@@ -491,10 +491,6 @@ __global__ void __launch_bounds__(256) k_offnorm_final(const double* __restrict_
   }
 }
 
-__global__ void k_reset_status(int* status) {
-  if (threadIdx.x < 4) status[threadIdx.x] = 0;
-}
-
 __global__ void k_fill(double* __restrict__ A, int64_t count, double v) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < count) A[i] = v;

@@ -1,0 +1,420 @@
+// Tunable float32 MFMA GEMMs of the mixed-precision generation: the sampling
+// product Y = (B D) Z (eq. (1), Sec. 3.1 rewrite), the fitness product R Y with
+// the objective reduced in the epilogue, and the split-k rank-mu SYRK partials
+// (eq. (3)).  One kernel template, several block tiles; the tile is chosen
+// per call site by the autotuner (api.hip) from kG32Configs.
+//
+//  * v_mfma_f32_32x32x2_f32; 4 waves in a 2 x 2 grid, each owning a
+//    (BM/2) x (BN/2) sub-tile of 32 x 32 MFMA blocks;
+//  * operands staged k-major in LDS (m / n contiguous, conflict-free MFMA
+//    reads), double buffered, one barrier per k-tile; the next k-tile's global
+//    loads are in flight while the current one is multiplied;
+//  * XCD-aware tile order: consecutive workgroups are dispatched round-robin
+//    over the 8 XCDs, so workgroup w is given tile (w mod 8) * T/8 + w / 8 and
+//    each XCD walks a contiguous run of tiles that share their B columns in
+//    its own L2.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace cmx {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// bijection [0, T) -> [0, T): workgroup w on XCD (w mod 8) gets the j-th tile
+// of that XCD's contiguous range
+__device__ __forceinline__ int xcd_swizzle(int w, int T) {
+  const int x = w & 7, j = w >> 3;
+  const int q = T >> 3, r = T & 7;
+  return x * q + min(x, r) + j;
+}
+
+template <int BM, int BN, int BK, bool TB>
+struct G32 {
+  static constexpr int LDA = BM + 4, LDB = BN + 4;
+  static constexpr int TMB = BM / 64, TNB = BN / 64;  // 32x32 blocks per wave
+  static constexpr int A_V4 = BM * BK / 4 / 256;      // float4 loads per thread
+  static constexpr int B_V4 = BN * BK / 4 / 256;
+  static_assert(A_V4 >= 1 && B_V4 >= 1, "tile too small for 256 threads");
+  float4 ra[A_V4], rb[B_V4];
+
+  __device__ static float4 ld4(const float* __restrict__ P, int64_t off, bool full, int lim) {
+    if (full) return *reinterpret_cast<const float4*>(P + off);
+    float v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = c < lim ? P[off + c] : 0.0f;
+    return make_float4(v[0], v[1], v[2], v[3]);
+  }
+
+  // A: M x K column-major (m contiguous)
+  __device__ void load_a(const float* __restrict__ A, int lda, int M, int K, int m0, int k0) {
+    constexpr int PER_COL = BM / 4;
+#pragma unroll
+    for (int p = 0; p < A_V4; ++p) {
+      const int q = p * 256 + threadIdx.x;
+      const int m = m0 + (q % PER_COL) * 4, k = k0 + q / PER_COL;
+      const bool ok = k < K;
+      ra[p] = ld4(A, static_cast<int64_t>(k) * lda + m, ok && m + 4 <= M, ok ? M - m : 0);
+    }
+  }
+  __device__ void store_a(float* S) const {
+    constexpr int PER_COL = BM / 4;
+#pragma unroll
+    for (int p = 0; p < A_V4; ++p) {
+      const int q = p * 256 + threadIdx.x;
+      *reinterpret_cast<float4*>(&S[(q / PER_COL) * LDA + (q % PER_COL) * 4]) = ra[p];
+    }
+  }
+  // B: K x N column-major (k contiguous) when !TB, else element (k, n) at B[n + k ldb]
+  __device__ void load_b(const float* __restrict__ B, int ldb, int N, int K, int n0, int k0) {
+#pragma unroll
+    for (int p = 0; p < B_V4; ++p) {
+      const int q = p * 256 + threadIdx.x;
+      if constexpr (!TB) {
+        constexpr int PER_ROW = BK / 4;
+        const int k = k0 + (q % PER_ROW) * 4, n = n0 + q / PER_ROW;
+        const bool ok = n < N;
+        rb[p] = ld4(B, static_cast<int64_t>(n) * ldb + k, ok && k + 4 <= K, ok ? K - k : 0);
+      } else {
+        constexpr int PER_COL = BN / 4;
+        const int n = n0 + (q % PER_COL) * 4, k = k0 + q / PER_COL;
+        const bool ok = k < K;
+        rb[p] = ld4(B, static_cast<int64_t>(k) * ldb + n, ok && n + 4 <= N, ok ? N - n : 0);
+      }
+    }
+  }
+  __device__ void store_b(float* S) const {
+#pragma unroll
+    for (int p = 0; p < B_V4; ++p) {
+      const int q = p * 256 + threadIdx.x;
+      if constexpr (!TB) {
+        constexpr int PER_ROW = BK / 4;
+        const int k = (q % PER_ROW) * 4, n = q / PER_ROW;
+        S[(k + 0) * LDB + n] = rb[p].x;
+        S[(k + 1) * LDB + n] = rb[p].y;
+        S[(k + 2) * LDB + n] = rb[p].z;
+        S[(k + 3) * LDB + n] = rb[p].w;
+      } else {
+        constexpr int PER_COL = BN / 4;
+        *reinterpret_cast<float4*>(&S[(q / PER_COL) * LDB + (q % PER_COL) * 4]) = rb[p];
+      }
+    }
+  }
+
+  // acc += A[m0.., k-range] * B[k-range, n0..] for k in [0, K)
+  __device__ void mainloop(int M, int N, int K, const float* __restrict__ A, int lda, const float* __restrict__ B,
+                           int ldb, int m0, int n0, float* As, float* Bs, floatx16 (&acc)[TMB][TNB]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+#pragma unroll
+    for (int i = 0; i < TMB; ++i)
+#pragma unroll
+      for (int j = 0; j < TNB; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    const int nk = (K + BK - 1) / BK;
+    if (nk == 0) return;
+    load_a(A, lda, M, K, m0, 0);
+    load_b(B, ldb, N, K, n0, 0);
+    store_a(As);
+    store_b(Bs);
+    __syncthreads();
+    const int kidx = lane >> 5, midx = lane & 31;
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      const float* Ac = As + cur * BK * LDA;
+      const float* Bc = Bs + cur * BK * LDB;
+      if (kt + 1 < nk) {
+        load_a(A, lda, M, K, m0, (kt + 1) * BK);
+        load_b(B, ldb, N, K, n0, (kt + 1) * BK);
+      }
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        float a[TMB], b[TNB];
+#pragma unroll
+        for (int i = 0; i < TMB; ++i) a[i] = Ac[(kk + kidx) * LDA + wm * (BM / 2) + i * 32 + midx];
+#pragma unroll
+        for (int j = 0; j < TNB; ++j) b[j] = Bc[(kk + kidx) * LDB + wn * (BN / 2) + j * 32 + midx];
+#pragma unroll
+        for (int i = 0; i < TMB; ++i)
+#pragma unroll
+          for (int j = 0; j < TNB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      if (kt + 1 < nk) {
+        store_a(As + (cur ^ 1) * BK * LDA);
+        store_b(Bs + (cur ^ 1) * BK * LDB);
+      }
+      __syncthreads();
+    }
+  }
+};
+
+// row of accumulator element r held by lane l (column l % 32) of a 32x32 block
+__device__ __forceinline__ int acc_row(int r, int l) { return (r >> 2) * 8 + (l >> 5) * 4 + (r & 3); }
+
+template <int BM, int BN>
+struct Epi32Store {
+  float* Y;
+  int ldy;
+  __device__ void operator()(const floatx16 (&acc)[BM / 64][BN / 64], int M, int N, int m0, int n0, float*) const {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+#pragma unroll
+    for (int i = 0; i < BM / 64; ++i)
+#pragma unroll
+      for (int j = 0; j < BN / 64; ++j) {
+        const int col = n0 + wn * (BN / 2) + j * 32 + (lane & 31);
+        if (col >= N) continue;
+        const int rbase = m0 + wm * (BM / 2) + i * 32 + (lane >> 5) * 4;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int row = rbase + g * 8;
+          float* dst = Y + static_cast<int64_t>(col) * ldy + row;
+          if (row + 4 <= M) {
+            *reinterpret_cast<float4*>(dst) = make_float4(acc[i][j][4 * g], acc[i][j][4 * g + 1],
+                                                          acc[i][j][4 * g + 2], acc[i][j][4 * g + 3]);
+          } else {
+            for (int c = 0; c < 4 && row + c < M; ++c) dst[c] = acc[i][j][4 * g + c];
+          }
+        }
+      }
+  }
+};
+
+// objective term; Rastrigin via 10 - 10 cos(2 pi u) = 20 sin^2(pi u)
+__device__ __forceinline__ float obj_term(int kind, float u, float coef) {
+  if (kind == 3) {
+    const float s = sinpif(u);
+    return u * u + 20.0f * s * s;
+  }
+  if (kind == 2) return coef * u * u;
+  return u * u;
+}
+
+template <int BM, int BN>
+struct Epi32Fitness {
+  int kind;
+  const double* d;
+  const float* coef;
+  const DevScalars* sc;
+  float* partial;
+  int ldp;
+  __device__ void operator()(const floatx16 (&acc)[BM / 64][BN / 64], int M, int N, int m0, int n0,
+                             float* smem) const {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const float sigma = static_cast<float>(sc->sigma);
+    float s[BN / 64];
+#pragma unroll
+    for (int j = 0; j < BN / 64; ++j) {
+      float sum = 0.0f;
+#pragma unroll
+      for (int i = 0; i < BM / 64; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = m0 + wm * (BM / 2) + i * 32 + acc_row(r, lane);
+          if (row < M) {
+            const float u = static_cast<float>(d[row]) + sigma * acc[i][j][r];
+            sum += obj_term(kind, u, kind == 2 ? coef[row] : 1.0f);
+          }
+        }
+      sum += __shfl_xor(sum, 32);  // the other 4-row groups of the same column
+      s[j] = sum;
+    }
+    __syncthreads();
+    if (lane < 32) {
+#pragma unroll
+      for (int j = 0; j < BN / 64; ++j) smem[wm * BN + wn * (BN / 2) + j * 32 + lane] = s[j];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < BN; t += 256) {
+      const int col = n0 + t;
+      if (col < N) partial[static_cast<int64_t>(m0 / BM) * ldp + col] = smem[t] + smem[BN + t];
+    }
+  }
+};
+
+template <int BM, int BN, int BK, bool TB, class Epi>
+__global__ void __launch_bounds__(256) k_g32(int M, int N, int K, const float* __restrict__ A, int lda,
+                                             const float* __restrict__ B, int ldb, Epi epi) {
+  using G = G32<BM, BN, BK, TB>;
+  __shared__ float As[2 * BK * G::LDA];
+  __shared__ float Bs[2 * BK * G::LDB];
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  const int tile = xcd_swizzle(blockIdx.x, tiles_m * tiles_n);
+  const int m0 = (tile % tiles_m) * BM, n0 = (tile / tiles_m) * BN;
+  floatx16 acc[G::TMB][G::TNB];
+  G g;
+  g.mainloop(M, N, K, A, lda, B, ldb, m0, n0, As, Bs, acc);
+  epi(acc, M, N, m0, n0, As);
+}
+
+__device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
+  tm = static_cast<int>((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+  while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
+  while (tm * (tm + 1) / 2 > t) --tm;
+  tn = t - tm * (tm + 1) / 2;
+}
+
+// rank-mu SYRK partials: workgroup (tile t, split s) writes its lower tile's
+// partial product over k-range s into work[(s ntl + t) BM^2 ...]
+template <int BM, int BK>
+__global__ void __launch_bounds__(256) k_syrk32(int n, int K, int kspan, const float* __restrict__ Y, int ldy,
+                                                float* __restrict__ work, int ntl) {
+  using G = G32<BM, BM, BK, true>;
+  __shared__ float As[2 * BK * G::LDA];
+  __shared__ float Bs[2 * BK * G::LDB];
+  const int item = xcd_swizzle(blockIdx.x, static_cast<int>(gridDim.x));
+  const int t = item % ntl, s = item / ntl;
+  int tm, tn;
+  lower_tile(t, tm, tn);
+  const int k0 = s * kspan, k1 = min(K, k0 + kspan);
+  floatx16 acc[G::TMB][G::TMB];
+  const float* Yk = Y + static_cast<int64_t>(k0) * ldy;
+  G g;
+  g.mainloop(n, n, max(0, k1 - k0), Yk, ldy, Yk, ldy, tm * BM, tn * BM, As, Bs, acc);
+  // fragment-native layout: each lane stores its 16 accumulator values
+  // contiguously, so a wave writes one contiguous 4 KiB run per 32x32 block
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float* out = work + (static_cast<int64_t>(s) * ntl + t) * (BM * BM);
+#pragma unroll
+  for (int i = 0; i < G::TMB; ++i)
+#pragma unroll
+    for (int j = 0; j < G::TMB; ++j) {
+      float4* dst = reinterpret_cast<float4*>(out + ((((wave * G::TMB + i) * G::TMB + j) * 64 + lane) << 4));
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        dst[g] = make_float4(acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2], acc[i][j][4 * g + 3]);
+    }
+}
+
+// position of tile element (row, col) in the fragment-native layout above
+// (wave = wm + 2 wn owns rows wm*BM/2.., columns wn*BM/2..; lane and register
+// follow the 32x32 accumulator layout of acc_row)
+template <int BM>
+__device__ __forceinline__ int frag_index(int row, int col) {
+  constexpr int H = BM / 2, TB = BM / 64;
+  const int wave = row / H + 2 * (col / H);
+  const int i = (row % H) >> 5, j = (col % H) >> 5, rr = row & 31;
+  const int lane = ((rr >> 2) & 1) * 32 + (col & 31);
+  const int r = (rr >> 3) * 4 + (rr & 3);
+  return ((((wave * TB + i) * TB + j) * 64 + lane) << 4) + r;
+}
+
+// C <- a C + c1 pc pc^T + cmu * sum_s partial_s (lower triangle, mirrored),
+// partials summed in ascending split order
+template <int BM>
+__global__ void __launch_bounds__(256) k_syrk32_epi(int n, int ntl, int splits, const float* __restrict__ work,
+                                                    double* __restrict__ C, int ldc, const double* __restrict__ pc,
+                                                    double c1, double cmu, const DevScalars* __restrict__ sc) {
+  constexpr int TILE = BM * BM;
+  const int t = blockIdx.x / 16, part = blockIdx.x % 16;
+  int tm, tn;
+  lower_tile(t, tm, tn);
+  const double a = sc->c_coef;
+  for (int e = part * 256 + threadIdx.x; e < TILE; e += 16 * 256) {
+    const int rl = e % BM, cl = e / BM;
+    const int row = tm * BM + rl, col = tn * BM + cl;
+    if (row >= n || col >= n || row < col) continue;
+    const int fi = frag_index<BM>(rl, cl);
+    double acc = 0.0;
+    for (int s = 0; s < splits; ++s) acc += static_cast<double>(work[(static_cast<int64_t>(s) * ntl + t) * TILE + fi]);
+    const int64_t at = static_cast<int64_t>(col) * ldc + row;
+    const double v = a * C[at] + c1 * pc[row] * pc[col] + cmu * acc;
+    C[at] = v;
+    if (row != col) C[static_cast<int64_t>(row) * ldc + col] = v;
+  }
+}
+
+template <int BM, int BN, int BK>
+hipError_t launch_cfg(hipStream_t st, int site, int M, int N, int K, const float* A, int lda, const float* B, int ldb,
+                      void* out, int ldo, const G32FitArgs* fa) {
+  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  if (tiles == 0) return hipSuccess;
+  if (site == G32_SAMPLE) {
+    k_g32<BM, BN, BK, false, Epi32Store<BM, BN>><<<tiles, 256, 0, st>>>(
+        M, N, K, A, lda, B, ldb, Epi32Store<BM, BN>{static_cast<float*>(out), ldo});
+  } else {
+    Epi32Fitness<BM, BN> e{fa->kind, fa->d, fa->coef, fa->sc, static_cast<float*>(out), ldo};
+    k_g32<BM, BN, BK, false, Epi32Fitness<BM, BN>><<<tiles, 256, 0, st>>>(M, N, K, A, lda, B, ldb, e);
+  }
+  return hipGetLastError();
+}
+
+template <int BM, int BK>
+hipError_t launch_syrk_cfg(hipStream_t st, int n, int K, const float* Y, int ldy, float* work, double* C, int ldc,
+                           const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only) {
+  int ntl, splits, kspan;
+  size_t we;
+  syrk32_plan(BM, n, K, &ntl, &splits, &kspan, &we);
+  k_syrk32<BM, BK><<<ntl * splits, 256, 0, st>>>(n, K, kspan, Y, ldy, work, ntl);
+  if (!partial_only)
+    k_syrk32_epi<BM><<<ntl * 16, 256, 0, st>>>(n, ntl, splits, work, C, ldc, pc, c1, cmu, sc);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// block tiles (BM x BN x BK) the tuner chooses from; SYRK uses the square ones
+const G32Config kG32Configs[kG32NumConfigs] = {
+    {128, 128, 16}, {128, 64, 16}, {64, 128, 16}, {256, 128, 16}, {128, 128, 32}, {64, 64, 32}, {64, 64, 16},
+};
+
+void syrk32_plan(int bm, int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems) {
+  const int tm = ceil_div(n, bm);
+  *ntl = tm * (tm + 1) / 2;
+  int s = ceil_div(512, *ntl);
+  s = std::max(1, std::min(s, ceil_div(K, 64)));
+  *kspan = round_up(ceil_div(std::max(K, 1), s), 32);
+  *splits = ceil_div(std::max(K, 1), *kspan);
+  *work_elems = static_cast<size_t>(*splits) * (*ntl) * bm * bm;
+}
+
+size_t syrk32_max_work(int n, int K) {
+  size_t best = 0;
+  for (int c = 0; c < kG32NumConfigs; ++c) {
+    if (kG32Configs[c].bm != kG32Configs[c].bn) continue;
+    int ntl, splits, kspan;
+    size_t we;
+    syrk32_plan(kG32Configs[c].bm, n, K, &ntl, &splits, &kspan, &we);
+    best = std::max(best, we);
+  }
+  return best;
+}
+
+bool g32_config_valid(int cfg, int site) {
+  if (cfg < 0 || cfg >= kG32NumConfigs) return false;
+  if (site == G32_SYRK) return kG32Configs[cfg].bm == kG32Configs[cfg].bn;
+  return true;
+}
+
+int g32_row_tiles(int cfg, int M) { return ceil_div(M, kG32Configs[cfg].bm); }
+
+hipError_t g32_gemm(hipStream_t st, int cfg, int site, int M, int N, int K, const float* A, int lda, const float* B,
+                    int ldb, void* out, int ldo, const G32FitArgs* fa) {
+  switch (cfg) {
+    case 0: return launch_cfg<128, 128, 16>(st, site, M, N, K, A, lda, B, ldb, out, ldo, fa);
+    case 1: return launch_cfg<128, 64, 16>(st, site, M, N, K, A, lda, B, ldb, out, ldo, fa);
+    case 2: return launch_cfg<64, 128, 16>(st, site, M, N, K, A, lda, B, ldb, out, ldo, fa);
+    case 3: return launch_cfg<256, 128, 16>(st, site, M, N, K, A, lda, B, ldb, out, ldo, fa);
+    case 4: return launch_cfg<128, 128, 32>(st, site, M, N, K, A, lda, B, ldb, out, ldo, fa);
+    case 5: return launch_cfg<64, 64, 32>(st, site, M, N, K, A, lda, B, ldb, out, ldo, fa);
+    case 6: return launch_cfg<64, 64, 16>(st, site, M, N, K, A, lda, B, ldb, out, ldo, fa);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t g32_syrk(hipStream_t st, int cfg, int n, int K, const float* Y, int ldy, float* work, double* C, int ldc,
+                    const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only) {
+  switch (cfg) {
+    case 0: return launch_syrk_cfg<128, 16>(st, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only);
+    case 4: return launch_syrk_cfg<128, 32>(st, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only);
+    case 5: return launch_syrk_cfg<64, 32>(st, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only);
+    case 6: return launch_syrk_cfg<64, 16>(st, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace cmx

@@ -132,6 +132,32 @@ hipError_t launch_syrk_update(hipStream_t st, bool fp64, int n, int mu, const vo
                               double* C, int ldc, const double* pc, double c1, double cmu,
                               const DevScalars* sc, void* work);
 
+// ---- tunable float32 MFMA GEMMs (mixed precisions) -------------------------
+enum G32Site { G32_SAMPLE = 0, G32_FITNESS = 1, G32_SYRK = 2, G32_NUM_SITES = 3 };
+struct G32Config {
+  int bm, bn, bk;  // block tile
+};
+constexpr int kG32NumConfigs = 7;
+extern const G32Config kG32Configs[kG32NumConfigs];
+struct G32FitArgs {
+  int kind;               // cmaes_objective_t
+  const double* d;        // n: R (m - x*)
+  const float* coef;      // n: ellipsoid weights
+  const DevScalars* sc;   // sigma
+};
+bool g32_config_valid(int cfg, int site);
+int g32_row_tiles(int cfg, int M);
+// site G32_SAMPLE: out = A*B (float, ld ldo); G32_FITNESS: out = per-row-tile
+// partial objective sums of d + sigma A*B ([row_tiles][N] floats, ld ldo)
+hipError_t g32_gemm(hipStream_t st, int cfg, int site, int M, int N, int K, const float* A, int lda, const float* B,
+                    int ldb, void* out, int ldo, const G32FitArgs* fa);
+void syrk32_plan(int bm, int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems);
+size_t syrk32_max_work(int n, int K);
+// C <- a C + c1 pc pc^T + cmu Y Y^T; partial_only stops after the split-k
+// products (the tuner times that part alone, C is left untouched)
+hipError_t g32_syrk(hipStream_t st, int cfg, int n, int K, const float* Y, int ldy, float* work, double* C, int ldc,
+                    const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only);
+
 // generic FP64 GEMM: C = op(A) * op(B), column-major
 hipError_t launch_dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
                         int lda, const double* B, int ldb, double* C, int ldc);

@@ -24,12 +24,15 @@ def oracle_state(st: dict, sigma0=1.0, seed=1, kappa=0) -> O.State:
     return o
 
 
-def one_generation(P, st, Z, kind, R, xs, precision, kappa=0):
-    """Returns (gpu_state, oracle_state, oracle_info)."""
+def one_generation(P, st, Z, kind, R, xs, precision, kappa=0, configure=None):
+    """Returns (gpu_state, oracle_state, oracle_info); configure(es) runs on the
+    device handle before the generation."""
     n, lam = st["n"], st["lambda"]
     es = P.CMAES(n, lam, 1.0, seed=1, precision=precision, objective=kind, R=R, xstar=xs,
                  eigen_interval=kappa)
     try:
+        if configure is not None:
+            configure(es)
         es.set_state(st)
         es.generation_with_z(Z)
         g = es.state()

@@ -55,3 +55,19 @@ def test_default_options_and_errors_without_device():
     with pytest.raises(P.CmaesError):
         P.cmaes_create(5, 10, -1.0, 1)         # sigma0 <= 0
     assert isinstance(P.cmaes_last_error(), str)
+
+
+def test_gemm_tile_table_without_device():
+    import paper_2409_11765_amd as P
+    assert P.cmaes_gemm_config_count() == 7
+    tiles = [P.cmaes_gemm_config_info(c) for c in range(7)]
+    assert tiles[0] == (128, 128, 16)
+    for bm, bn, bk in tiles:
+        # 4 waves in a 2 x 2 grid of 32 x 32 MFMA blocks; float4 staging
+        assert bm % 64 == 0 and bn % 64 == 0 and bk in (16, 32)
+    assert len(set(tiles)) == 7
+    assert any(bm == bn for bm, bn, _ in tiles)
+    with pytest.raises(P.CmaesError):
+        P.cmaes_gemm_config_info(7)
+    with pytest.raises(P.CmaesError):
+        P.cmaes_gemm_config_info(-1)
