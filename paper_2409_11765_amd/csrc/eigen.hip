@@ -20,7 +20,9 @@
 //     wide, bandwidth bound update, so one launch per round does both: the
 //     R2 of round r (A ping-pongs between two buffers) and, in q extra
 //     workgroups, the R1 of round r+1, each of which recomputes the three
-//     round-r tiles its next pair needs instead of waiting for them.
+//     16 x 16 round-r blocks its next pair needs instead of waiting for them.
+//     Rotation angles are formed in float32 (they only set how far an entry
+//     is reduced); cosines and sines are float64 and orthogonal to rounding.
 //     Sweeps stop when the off-diagonal Frobenius norm of A falls below
 //     1e-13 of its total norm (summed per tile by the last round).
 //  3. B = B_old V, D = sqrt(diag A), then the pairs are canonicalised like the
@@ -42,40 +44,30 @@ constexpr double kOffTol = 1e-13;
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-// 1/x and 1/sqrt(x) from the hardware approximations (about 1e-7 relative)
-// refined by Newton steps: one step gives about 1e-14, two give full double
-// precision.
-__device__ __forceinline__ double rcp_nr1(double x) {
-  const double y = __builtin_amdgcn_rcp(x);
-  return y * fma(-x, y, 2.0);
-}
-__device__ __forceinline__ double rsq_nr1(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  return y * fma(-0.5 * x * y, y, 1.5);
-}
-__device__ __forceinline__ double rsq_nr2(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * fma(-0.5 * x * y, y, 1.5);
-  return y * fma(-0.5 * x * y, y, 1.5);
-}
-
-// Jacobi rotation J = [[c, s], [-s, c]] on (a, b) with (J^T S J)_ab = 0
-// (Golub & Van Loan, sym.schur2): t = sign(delta) 2 d / (|delta| + sqrt(delta^2 + 4 d^2))
-// with delta = S_bb - S_aa, d = S_ab; c = 1/sqrt(1 + t^2), s = t c; the
-// identity when |d| <= thr.  Branch free, so the callers' loads issue up front
-// and two rotations interleave.  t is accurate to about 1e-14 relative (it
-// only decides how well the entry is annihilated); c is refined to full
-// precision because c^2 (1 + t^2) = 1 is what keeps Q orthogonal.
-__device__ __forceinline__ void jacobi_rotation(double saa, double sbb, double d, double thr, double& c,
+// Jacobi rotation J = [[c, s], [-s, c]] on (a, b) that annihilates (J^T S J)_ab
+// up to the accuracy of t (Golub & Van Loan, sym.schur2): t = sign(delta) 2 d /
+// (|delta| + sqrt(delta^2 + 4 d^2)) with delta = S_bb - S_aa, d = S_ab;
+// c = 1/sqrt(1 + t^2), s = t c; the identity when |d| <= thr.
+// t only decides how far the entry is reduced, so it is formed in float32 from
+// the entries scaled by inv = 1/max|a_ii| (relative error ~1e-7: the entry
+// drops to ~1e-7 of itself and later rotations remove the rest).  c is then
+// refined to float64 precision from that t by two Newton steps, because
+// c^2 (1 + t^2) = 1 is what keeps each rotation, and so Q, orthogonal.
+// Branch free, so the callers' loads issue up front and two rotations
+// interleave.
+__device__ __forceinline__ void jacobi_rotation(double saa, double sbb, double d, double thr, double inv, double& c,
                                                 double& s) {
-  // |d| <= thr gives d' = 0 and hence t = 0; the floor on h2 keeps every
-  // intermediate finite, so no branch is needed
   const double dd = fabs(d) > thr ? d : 0.0;
-  const double delta = sbb - saa;
-  const double h2 = fmax(fma(delta, delta, 4.0 * dd * dd), 1e-280);
-  const double h = h2 * rsq_nr1(h2);
-  const double t = (delta >= 0.0 ? 2.0 : -2.0) * dd * rcp_nr1(fabs(delta) + h);
-  c = rsq_nr2(fma(t, t, 1.0));
+  const float df = static_cast<float>(dd * inv);
+  const float delta = static_cast<float>((sbb - saa) * inv);
+  const float h = __builtin_amdgcn_sqrtf(fmaf(delta, delta, 4.0f * df * df));
+  // |delta| + h >= 2 |df| > 0 whenever df != 0; the floor only guards 0 / 0
+  const float tf = (delta >= 0.0f ? 2.0f : -2.0f) * df * __builtin_amdgcn_rcpf(fmaxf(fabsf(delta) + h, 1e-30f));
+  const double t = static_cast<double>(tf);
+  const double x = fma(t, t, 1.0);
+  double y = static_cast<double>(__builtin_amdgcn_rsqf(fmaf(tf, tf, 1.0f)));
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  c = y * fma(-0.5 * x * y, y, 1.5);
   s = t * c;
 }
 
@@ -107,46 +99,24 @@ __device__ __forceinline__ int pair_of(int p, int r, int X) {
   return d <= p / 2 - 1 ? d : (p - 1) - d;
 }
 
-// 32x32x32 product on the float64 matrix cores: wave w (of 4) computes the
-// 16x16 block (w & 1, w >> 1) of  OUT = op(L) * R,  op(L) = L or L^T, all
-// operands in LDS with row stride kLD.
-template <bool LT>
-__device__ __forceinline__ void mm32(const double* Lm, const double* Rm, double* Out) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int bi = w & 1, bj = w >> 1;
-  const int li = lane & 15, lk = lane >> 4;
+// 16x16 output block of a product with inner dimension 32 on the float64
+// matrix cores (8 steps of v_mfma_f64_16x16x4f64).  Lane l supplies
+// A(i = l & 15, k = 4 s + (l >> 4)) in a[s] and B(k = 4 s + (l >> 4), j = l & 15)
+// in b[s]; the result holds OUT(row = (l >> 4) + 4 r, col = l & 15) in acc[r].
+__device__ __forceinline__ doublex4 mfma_k32(const double (&a)[8], const double (&b)[8]) {
   doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k0 = 0; k0 < kS; k0 += 4) {
-    const int k = k0 + lk;
-    const double a = LT ? Lm[k * kLD + bi * 16 + li] : Lm[(bi * 16 + li) * kLD + k];
-    const double b = Rm[k * kLD + bj * 16 + li];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) Out[(bi * 16 + lk + 4 * r) * kLD + bj * 16 + li] = acc[r];
+  for (int s = 0; s < 8; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+  return acc;
 }
 
-// load a column-major 32x32 Q (global) into LDS rows
+// 32x32 column-major matrix q (global) into LDS rows: Q[row * kLD + col]
 __device__ __forceinline__ void load_q(const double* __restrict__ q, double* Q) {
-  for (int idx = threadIdx.x; idx < kS * kS; idx += 256) Q[(idx % kS) * kLD + idx / kS] = q[idx];
-}
-
-// X <- Q1^T A[{P1 blocks}, {P2 blocks}] Q2 for round r (W is scratch); all in LDS
-__device__ void tile_transform(const double* __restrict__ A, int N, int p, int r, int P1, int P2,
-                               const double* Q1, const double* Q2, double* X, double* W) {
-  int I1, J1, I2, J2;
-  block_pair(p, r, P1, I1, J1);
-  block_pair(p, r, P2, I2, J2);
-  for (int idx = threadIdx.x; idx < kS * kS; idx += 256) {
-    const int rr = idx % kS, c = idx / kS;
-    X[rr * kLD + c] = A[static_cast<int64_t>(gidx(I2, J2, c)) * N + gidx(I1, J1, rr)];
+#pragma unroll
+  for (int k = 0; k < kS * kS / 256; ++k) {
+    const int idx = threadIdx.x + 256 * k;
+    Q[(idx % kS) * kLD + idx / kS] = q[idx];
   }
-  __syncthreads();
-  mm32<false>(X, Q2, W);  // W = X Q2
-  __syncthreads();
-  mm32<true>(Q1, W, X);   // X = Q1^T W
-  __syncthreads();
 }
 
 // Rotation x (0..15) of inner round r as branch-free index arithmetic (see
@@ -171,8 +141,8 @@ __device__ __forceinline__ void pair_idx(int r, int x, int& a, int& b) {
 // recomputes the two rotations it needs, updates its block of S into the
 // other buffer and rows r0, r1 of Q for rotation x.
 template <bool INTRA>
-__device__ __forceinline__ void inner_round(const double* S, double* Sn, double* Q, double thr, int rr, int x,
-                                            int y) {
+__device__ __forceinline__ void inner_round(const double* S, double* Sn, double* Q, double thr, double inv, int rr,
+                                            int x, int y) {
   int ax, bx, ay, by;
   pair_idx<INTRA>(rr, x, ax, bx);
   pair_idx<INTRA>(rr, y, ay, by);
@@ -184,17 +154,14 @@ __device__ __forceinline__ void inner_round(const double* S, double* Sn, double*
   const double q0a = Q[r0 * kLD + ax], q0b = Q[r0 * kLD + bx];
   const double q1a = Q[r1 * kLD + ax], q1b = Q[r1 * kLD + bx];
   double cx, sx, cy, sy;
-  jacobi_rotation(xaa, xbb, xab, thr, cx, sx);
-  jacobi_rotation(yaa, ybb, yab, thr, cy, sy);
+  jacobi_rotation(xaa, xbb, xab, thr, inv, cx, sx);
+  jacobi_rotation(yaa, ybb, yab, thr, inv, cy, sy);
   // S_xy <- J_x^T S_xy J_y,  J = [[c, s], [-s, c]] on (a, b)
   const double p00 = m00 * cy - m01 * sy, p01 = m00 * sy + m01 * cy;
   const double p10 = m10 * cy - m11 * sy, p11 = m10 * sy + m11 * cy;
+  // (for x == y, n01 = n10 is what remains of the annihilated entry)
   const double n00 = cx * p00 - sx * p10, n11 = sx * p01 + cx * p11;
-  double n01 = cx * p01 - sx * p11, n10 = sx * p00 + cx * p10;
-  if (x == y) {  // the annihilated entry is exactly zero
-    n01 = 0.0;
-    n10 = 0.0;
-  }
+  const double n01 = cx * p01 - sx * p11, n10 = sx * p00 + cx * p10;
   Sn[ax * kLD + ay] = n00;
   Sn[ax * kLD + by] = n01;
   Sn[bx * kLD + ay] = n10;
@@ -210,7 +177,7 @@ __device__ __forceinline__ void inner_round(const double* S, double* Sn, double*
 // outer round (optionally the 15 intra-block rounds, then the 16 cross
 // rounds), accumulated into Q (LDS) and written column-major to qout.  One
 // barrier per inner round.
-__device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, bool with_intra,
+__device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, double inv, bool with_intra,
                             double* __restrict__ qout) {
   const int t = threadIdx.x;
   for (int idx = t; idx < kS * kS; idx += 256) Q[(idx % kS) * kLD + idx / kS] = (idx % kS == idx / kS) ? 1.0 : 0.0;
@@ -220,7 +187,7 @@ __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, bool 
   __syncthreads();
   if (with_intra) {
     for (int rr = 0; rr < kNB - 1; ++rr) {
-      inner_round<true>(Sa, Sb, Q, thr, rr, x, y);
+      inner_round<true>(Sa, Sb, Q, thr, inv, rr, x, y);
       double* tmp = Sa;
       Sa = Sb;
       Sb = tmp;
@@ -228,7 +195,7 @@ __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, bool 
     }
   }
   for (int rr = 0; rr < kNB; ++rr) {
-    inner_round<false>(Sa, Sb, Q, thr, rr, x, y);
+    inner_round<false>(Sa, Sb, Q, thr, inv, rr, x, y);
     double* tmp = Sa;
     Sa = Sb;
     Sb = tmp;
@@ -254,33 +221,40 @@ __global__ void __launch_bounds__(256) k_jac_first(const double* __restrict__ A,
     S0[r * kLD + c] = A[static_cast<int64_t>(gidx(I, J, c)) * N + gidx(I, J, r)];
   }
   __syncthreads();
-  rotate_pair(S0, S1, Q, 2.2e-16 * (*scale), true, Qg + static_cast<int64_t>(P) * kS * kS);
+  const double sc = *scale;
+  rotate_pair(S0, S1, Q, 2.2e-16 * sc, sc > 0.0 ? 1.0 / sc : 0.0, true, Qg + static_cast<int64_t>(P) * kS * kS);
 }
 
 // One outer round r: workgroups [0, q) run the pair solves of the next round
 // (r + 1, or round 0 of the next sweep after the last round); workgroups
 // [q, q + q(q+1)/2) write the round-r lower tiles Q_P1^T A_cur Q_P2 of A into
-// A_next (mirrored) and their off-diagonal / total squared norms into
-// tilepart; the rest update 32-row pieces of V with V Q_P.
+// A_next (and their mirrors) and the tiles' off-diagonal / total squared norms
+// into tilepart; the rest update 32-row pieces of V with V Q_P.  MFMA operands
+// that come from A or V are loaded from global memory straight into the
+// fragment registers; only the Q's and cross-wave intermediates go through LDS.
+constexpr int kLU = kNB + 1;                           // row stride of the 32 x 16 stage-1 products
+constexpr int kRoundLds = 3 * kS * kLD + 3 * kS * kLU;  // doubles of LDS per workgroup
+
 __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Acur, double* __restrict__ Anext,
                                                    double* __restrict__ V, const double* __restrict__ Qcur,
                                                    double* __restrict__ Qnext, int N, int r,
                                                    const double* __restrict__ scale, double* __restrict__ tilepart) {
-  __shared__ double lds[5 * kS * kLD];
-  double* QA = lds;
-  double* QB = lds + kS * kLD;
-  double* X = lds + 2 * kS * kLD;
-  double* W = lds + 3 * kS * kLD;
-  double* S = lds + 4 * kS * kLD;
+  __shared__ double lds[kRoundLds];
   const int p = N / kNB, q = p / 2;
   const int ntiles = q * (q + 1) / 2;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   int b = blockIdx.x;
   if (b < q) {
-    // ---- pair solve of the next round, from recomputed round-r tiles:
-    // the tiles (Pa,Pa), (Pb,Pb), (Pa,Pb) and both Q's are fetched at once
-    // (the last two tiles wait in registers), transformed one after the
-    // other, and the next pair's S assembled from them.
+    // ---- pair solve of the next round.  Its 32 x 32 problem S is made of
+    // three 16 x 16 blocks of the round-r output, recomputed here from A_cur
+    // and the round-r Q's instead of waited for:
+    //   S11 = Qa[:, ca]^T Xa Qa[:, ca],  S22 = Qb[:, cb]^T Xb Qb[:, cb],
+    //   S12 = Qa[:, ca]^T Xab Qb[:, cb]
+    // (Xa, Xb, Xab: round-r tiles of A_cur; ca / cb: the 16 columns of the
+    // round-r pair that become the next pair's blocks).  Stage 1 forms the
+    // 32 x 16 products U = X Q[:, c] (6 MFMA blocks over the 4 waves),
+    // stage 2 the three 16 x 16 blocks.
     const bool wrap = (r + 1 == p - 1);
     const int rn = wrap ? 0 : r + 1;
     int In, Jn;
@@ -289,146 +263,183 @@ __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Ac
     int Ia, Ja, Ib, Jb;
     block_pair(p, r, Pa, Ia, Ja);
     block_pair(p, r, Pb, Ib, Jb);
-    const int pi = (In == Ia) ? 0 : kNB, pj = (Jn == Ib) ? 0 : kNB;
-    const double* qa = Qcur + static_cast<int64_t>(Pa) * kS * kS;
-    const double* qb = Qcur + static_cast<int64_t>(Pb) * kS * kS;
-    constexpr int PER = kS * kS / 256;
-    double t2[PER], t3[PER];
+    const bool same = (Pa == Pb);  // p = 2: both blocks from one round-r pair
+    const int ca = (In == Ia) ? 0 : kNB;
+    const int cb = same ? ((Jn == Ia) ? 0 : kNB) : ((Jn == Ib) ? 0 : kNB);
+    double* Qa = lds;
+    double* Qb = lds + kS * kLD;
+    double* S = lds + 2 * kS * kLD;
+    double* U = lds + 3 * kS * kLD;  // 3 x [32][kLU]
+    // stage-1 blocks: 2u + h = rows [16h, 16h + 16) of U_u; u = 0: Xa Qa[:, ca],
+    // 1: Xb Qb[:, cb], 2: Xab Qb[:, cb] (U_2 = U_1 when same)
+    const int nblk = same ? 4 : 6;
+    double fa[2][8];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int idx = t + 256 * k, rr = idx % kS, c = idx / kS;
-      QA[rr * kLD + c] = qa[idx];
-      QB[rr * kLD + c] = qb[idx];
-      X[rr * kLD + c] = Acur[static_cast<int64_t>(gidx(Ia, Ja, c)) * N + gidx(Ia, Ja, rr)];
-      t2[k] = Acur[static_cast<int64_t>(gidx(Ib, Jb, c)) * N + gidx(Ib, Jb, rr)];
-      t3[k] = Acur[static_cast<int64_t>(gidx(Ib, Jb, c)) * N + gidx(Ia, Ja, rr)];
+    for (int v = 0; v < 2; ++v) {
+      const int blk = w + 4 * v;
+      if (blk < nblk) {  // uniform per wave
+        const int u = blk >> 1, R = (blk & 1) * kNB;
+        const int rI = u == 1 ? Ib : Ia, rJ = u == 1 ? Jb : Ja;
+        const int cI = u == 0 ? Ia : Ib, cJ = u == 0 ? Ja : Jb;
+        const int row = gidx(rI, rJ, R + li);
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) fa[v][s2] = Acur[static_cast<int64_t>(gidx(cI, cJ, 4 * s2 + lk)) * N + row];
+      }
+    }
+    load_q(Qcur + static_cast<int64_t>(Pa) * kS * kS, Qa);
+    load_q(Qcur + static_cast<int64_t>(Pb) * kS * kS, Qb);
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int blk = w + 4 * v;
+      if (blk < nblk) {
+        const int u = blk >> 1, R = (blk & 1) * kNB;
+        const double* Qs = u == 0 ? Qa : Qb;
+        const int c = u == 0 ? ca : cb;
+        double bq[8];
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) bq[s2] = Qs[(4 * s2 + lk) * kLD + c + li];
+        const doublex4 acc = mfma_k32(fa[v], bq);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) U[u * kS * kLU + (R + lk + 4 * rr) * kLU + li] = acc[rr];
+      }
     }
     __syncthreads();
-    mm32<false>(X, QA, W);
-    __syncthreads();
-    mm32<true>(QA, W, X);  // X = Qa^T A[Pa,Pa] Qa
-    __syncthreads();
-    if (Pa == Pb) {
-      // both blocks of the next pair come from one round-r pair (p = 2)
-      const int pjj = (Jn == Ia) ? 0 : kNB;
-      for (int idx = t; idx < kS * kS; idx += 256) {
-        const int rr = idx % kS, c = idx / kS;
-        const int sr = rr < kNB ? pi + rr : pjj + rr - kNB;
-        const int sc = c < kNB ? pi + c : pjj + c - kNB;
-        S[rr * kLD + c] = X[sr * kLD + sc];
-      }
-    } else {
-      for (int idx = t; idx < kNB * kNB; idx += 256) {
-        const int rr = idx % kNB, c = idx / kNB;
-        S[rr * kLD + c] = X[(pi + rr) * kLD + pi + c];
-      }
-      __syncthreads();
+    if (w < 3) {
+      // wave 0: S11 = Qa[:, ca]^T U_0; 1: S22 = Qb[:, cb]^T U_1; 2: S12 = Qa[:, ca]^T U_2
+      const double* Ql = w == 1 ? Qb : Qa;
+      const int c = w == 1 ? cb : ca;
+      const int u = (w == 2 && same) ? 1 : w;
+      double aq[8], bu[8];
 #pragma unroll
-      for (int k = 0; k < PER; ++k) {
-        const int idx = t + 256 * k;
-        X[(idx % kS) * kLD + idx / kS] = t2[k];
+      for (int s2 = 0; s2 < 8; ++s2) {
+        aq[s2] = Ql[(4 * s2 + lk) * kLD + c + li];
+        bu[s2] = U[u * kS * kLU + (4 * s2 + lk) * kLU + li];
       }
-      __syncthreads();
-      mm32<false>(X, QB, W);
-      __syncthreads();
-      mm32<true>(QB, W, X);  // X = Qb^T A[Pb,Pb] Qb
-      __syncthreads();
-      for (int idx = t; idx < kNB * kNB; idx += 256) {
-        const int rr = idx % kNB, c = idx / kNB;
-        S[(kNB + rr) * kLD + kNB + c] = X[(pj + rr) * kLD + pj + c];
-      }
-      __syncthreads();
+      const doublex4 acc = mfma_k32(aq, bu);
+      const int ro = w == 1 ? kNB : 0, co = w == 0 ? 0 : kNB;
 #pragma unroll
-      for (int k = 0; k < PER; ++k) {
-        const int idx = t + 256 * k;
-        X[(idx % kS) * kLD + idx / kS] = t3[k];
-      }
-      __syncthreads();
-      mm32<false>(X, QB, W);
-      __syncthreads();
-      mm32<true>(QA, W, X);  // X = Qa^T A[Pa,Pb] Qb
-      __syncthreads();
-      for (int idx = t; idx < kNB * kNB; idx += 256) {
-        const int rr = idx % kNB, c = idx / kNB;
-        const double v = X[(pi + rr) * kLD + pj + c];
-        S[rr * kLD + kNB + c] = v;
-        S[(kNB + c) * kLD + rr] = v;
+      for (int rr = 0; rr < 4; ++rr) {
+        S[(ro + lk + 4 * rr) * kLD + co + li] = acc[rr];
+        if (w == 2) S[(kNB + li) * kLD + lk + 4 * rr] = acc[rr];
       }
     }
     __syncthreads();
     __builtin_amdgcn_s_setprio(2);  // the pair solves are the round's critical path
-    rotate_pair(S, X, W, 2.2e-16 * (*scale), wrap, Qnext + static_cast<int64_t>(b) * kS * kS);
+    const double sc = *scale;
+    rotate_pair(S, Qa, Qb, 2.2e-16 * sc, sc > 0.0 ? 1.0 / sc : 0.0, wrap,
+                Qnext + static_cast<int64_t>(b) * kS * kS);
     return;
   }
   b -= q;
   if (b < ntiles) {
-    // ---- round-r tile of A into A_next
+    // ---- round-r tile T = Q1^T X Q2 (X = A_cur[rows of pair P1, cols of pair P2])
+    // of A_next.  Stage 1: W = X Q2.  Stage 2 forms both T and T^T so that the
+    // tile and its mirror are each stored by 16-lane runs of consecutive rows.
     int P1 = static_cast<int>((sqrtf(8.0f * b + 1.0f) - 1.0f) * 0.5f);
     while ((P1 + 1) * (P1 + 2) / 2 <= b) ++P1;
     while (P1 * (P1 + 1) / 2 > b) --P1;
     const int P2 = b - P1 * (P1 + 1) / 2;
-    load_q(Qcur + static_cast<int64_t>(P1) * kS * kS, QA);
-    load_q(Qcur + static_cast<int64_t>(P2) * kS * kS, QB);
-    __syncthreads();
-    tile_transform(Acur, N, p, r, P1, P2, QA, QB, X, W);
     int I1, J1, I2, J2;
     block_pair(p, r, P1, I1, J1);
     block_pair(p, r, P2, I2, J2);
-    double off = 0.0, tot = 0.0, dmax = 0.0;
-    for (int idx = t; idx < kS * kS; idx += 256) {
-      const int rr = idx % kS, c = idx / kS;
-      const int gr = gidx(I1, J1, rr), gc = gidx(I2, J2, c);
-      const double v = X[rr * kLD + c];
-      Anext[static_cast<int64_t>(gc) * N + gr] = v;
-      tot += v * v;
-      if (gr != gc) off += v * v;
-      else dmax = fmax(dmax, fabs(v));
+    double* Q1 = lds;
+    double* Q2 = lds + kS * kLD;
+    double* W = lds + 2 * kS * kLD;
+    double* red = lds + 3 * kS * kLD;
+    const int bi = w & 1, bj = w >> 1;
+    double fx[8];
+    {
+      const int row = gidx(I1, J1, bi * kNB + li);
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) fx[s2] = Acur[static_cast<int64_t>(gidx(I2, J2, 4 * s2 + lk)) * N + row];
     }
-    if (P1 != P2) {
-      for (int idx = t; idx < kS * kS; idx += 256) {
-        const int c = idx % kS, rr = idx / kS;  // consecutive threads -> consecutive rows of the mirror
-        Anext[static_cast<int64_t>(gidx(I1, J1, rr)) * N + gidx(I2, J2, c)] = X[rr * kLD + c];
-      }
+    load_q(Qcur + static_cast<int64_t>(P1) * kS * kS, Q1);
+    load_q(Qcur + static_cast<int64_t>(P2) * kS * kS, Q2);
+    __syncthreads();
+    {
+      double bq[8];
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) bq[s2] = Q2[(4 * s2 + lk) * kLD + bj * kNB + li];
+      const doublex4 acc = mfma_k32(fx, bq);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) W[(bi * kNB + lk + 4 * rr) * kLD + bj * kNB + li] = acc[rr];
+    }
+    __syncthreads();
+    // M1 = T^T = W^T Q1 (block (bi, bj)): row j, col i -> A_next(gidx1(i), gidx2(j))
+    // M2 = T   = Q1^T W (block (bi, bj)): row i, col j -> A_next(gidx2(j), gidx1(i))
+    double a1[8], b1[8], a2[8], b2[8];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      const int k = 4 * s2 + lk;
+      a1[s2] = W[k * kLD + bi * kNB + li];
+      b1[s2] = Q1[k * kLD + bj * kNB + li];
+      a2[s2] = Q1[k * kLD + bi * kNB + li];
+      b2[s2] = W[k * kLD + bj * kNB + li];
+    }
+    const doublex4 m1 = mfma_k32(a1, b1);
+    const bool diag = (P1 == P2);
+    double off = 0.0, tot = 0.0, dmax = 0.0;
+    const int col = bj * kNB + li;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int row = bi * kNB + lk + 4 * rr;
+      const double v = m1[rr];
+      Anext[static_cast<int64_t>(gidx(I2, J2, row)) * N + gidx(I1, J1, col)] = v;
+      tot += v * v;
+      if (diag && row == col) dmax = fmax(dmax, fabs(v));
+      else off += v * v;
+    }
+    if (!diag) {
+      const doublex4 m2 = mfma_k32(a2, b2);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        Anext[static_cast<int64_t>(gidx(I1, J1, bi * kNB + lk + 4 * rr)) * N + gidx(I2, J2, col)] = m2[rr];
       off *= 2.0;
       tot *= 2.0;
     }
-    double* red = W;  // W is free after the transform: 3 x 256 partial sums
-    red[t] = off;
-    red[256 + t] = tot;
-    red[512 + t] = dmax;
-    __syncthreads();
-    for (int s2 = 128; s2 > 0; s2 >>= 1) {
-      if (t < s2) {
-        red[t] += red[t + s2];
-        red[256 + t] += red[256 + t + s2];
-        red[512 + t] = fmax(red[512 + t], red[512 + t + s2]);
-      }
-      __syncthreads();
+    // fixed-order reduction: butterfly within each wave, then the 4 waves in order
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      off += __shfl_xor(off, m);
+      tot += __shfl_xor(tot, m);
+      dmax = fmax(dmax, __shfl_xor(dmax, m));
     }
+    if (lane == 0) {
+      red[3 * w + 0] = off;
+      red[3 * w + 1] = tot;
+      red[3 * w + 2] = dmax;
+    }
+    __syncthreads();
     if (t == 0) {
-      tilepart[3 * b + 0] = red[0];
-      tilepart[3 * b + 1] = red[256];
-      tilepart[3 * b + 2] = red[512];
+      tilepart[3 * b + 0] = ((red[0] + red[3]) + red[6]) + red[9];
+      tilepart[3 * b + 1] = ((red[1] + red[4]) + red[7]) + red[10];
+      tilepart[3 * b + 2] = fmax(fmax(red[2], red[5]), fmax(red[8], red[11]));
     }
     return;
   }
   b -= ntiles;
-  // ---- V piece: rows [32 rc, 32 rc + 32) of the columns of pair P
+  // ---- V piece: rows [32 rc, 32 rc + 32) of the columns of pair P, V <- V Q_P.
+  // Computed as M = Q_P^T X^T (X = the piece) so that each wave's block is
+  // stored by runs of consecutive rows; every wave has consumed its loads
+  // before the barrier, after which the piece is overwritten in place.
   const int P = b % q, rc = b / q;
   int I, J;
   block_pair(p, r, P, I, J);
-  load_q(Qcur + static_cast<int64_t>(P) * kS * kS, QA);
-  for (int idx = t; idx < kS * kS; idx += 256) {
-    const int rr = idx % kS, c = idx / kS;
-    X[rr * kLD + c] = V[static_cast<int64_t>(gidx(I, J, c)) * N + rc * kS + rr];
+  const double* qg = Qcur + static_cast<int64_t>(P) * kS * kS;
+  const int bm = w & 1, bn = w >> 1;
+  double aq[8], bx[8];
+#pragma unroll
+  for (int s2 = 0; s2 < 8; ++s2) {
+    const int k = 4 * s2 + lk;
+    aq[s2] = qg[k + kS * (bm * kNB + li)];                                     // Q(k, j)
+    bx[s2] = V[static_cast<int64_t>(gidx(I, J, k)) * N + rc * kS + bn * kNB + li];  // X(i, k)
   }
+  const doublex4 acc = mfma_k32(aq, bx);
   __syncthreads();
-  mm32<false>(X, QA, W);
-  __syncthreads();
-  for (int idx = t; idx < kS * kS; idx += 256) {
-    const int rr = idx % kS, c = idx / kS;
-    V[static_cast<int64_t>(gidx(I, J, c)) * N + rc * kS + rr] = W[rr * kLD + c];
-  }
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+    V[static_cast<int64_t>(gidx(I, J, bm * kNB + lk + 4 * rr)) * N + rc * kS + bn * kNB + li] = acc[rr];
 }
 
 // off-diagonal / total squared norms and max |diagonal| of A, per column
