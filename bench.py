@@ -80,6 +80,10 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10,
                     help="generations of the concurrent-restart batch (10 descents, n=200); 0 = skip")
     ap.add_argument("--no-tune", action="store_true", help="keep the default float32 GEMM tiles")
+    ap.add_argument("--ablation", action="store_true",
+                    help="instead of the headline line: per-phase mixed-vs-FP64 table over n and K")
+    ap.add_argument("--asktell", action="store_true",
+                    help="instead of the headline line: host ask/tell throughput with added evaluation cost")
     ap.add_argument("--tiles", default=None, help="force tiles: sample,fitness,syrk configuration indices")
     return ap.parse_args()
 
@@ -189,6 +193,107 @@ def cpu_baseline(n, lam, seed, R, xs, budget_s):
             "gens_per_s": gens / el}
 
 
+def default_lambda(n):
+    return 4 + int(np.floor(3.0 * np.log(n)))
+
+
+def run_ablation(P, torch, seed, gens=9, warmup=2):
+    """Per-phase device time, mixed vs FP64, for n in {10, 40, 200, 1000} and
+    K in {1, 2^8} (lambda = K * default lambda), rotated Rastrigin."""
+    import synth
+    rows = []
+    for n in (10, 40, 200, 1000):
+        R, xs = synth.problem(n, seed)
+        for K in (1, 256):
+            lam = K * default_lambda(n)
+            row = {"n": n, "K": K, "lambda": lam}
+            for prec in ("fp64", "mixed"):
+                stream = torch.cuda.Stream()
+                with P.CMAES(n, lam, 2.0, seed=seed, precision=prec, objective="rastrigin", R=R, xstar=xs,
+                             stream=stream.cuda_stream) as es:
+                    if prec != "fp64":
+                        es.autotune(reps=3)
+                    for _ in range(warmup):
+                        es.generation()
+                    es.enable_timing(True)
+                    acc = {k: 0.0 for k in P.PHASES}
+                    for _ in range(gens):
+                        es.generation()
+                        for k, v in es.phase_times().items():
+                            acc[k] += v / gens
+                    es.enable_timing(False)
+                    es.enable_graphs(True)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(gens):
+                        es.generation()
+                    torch.cuda.synchronize()
+                    wall = (time.perf_counter() - t0) / gens
+                row[prec] = {"phases_us": {k: round(v, 1) for k, v in acc.items()},
+                             "device_us": round(sum(acc.values()), 1), "wall_us": round(1e6 * wall, 1)}
+            row["mixed_speedup"] = {k: (row["fp64"]["phases_us"][k] / row["mixed"]["phases_us"][k]
+                                        if row["mixed"]["phases_us"][k] > 0 else None) for k in P.PHASES}
+            row["mixed_speedup_total"] = row["fp64"]["wall_us"] / row["mixed"]["wall_us"]
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+    return rows
+
+
+def run_asktell(P, torch, seed, n=200, lam=4864, gens=6, delays_ms=(0, 1, 10, 100)):
+    """Host blackbox path: ask -> (host evaluation + added delay) -> tell, the
+    paper's granularity axis (each generation's lambda evaluations run in
+    parallel and cost the added delay once).  Serial: one descent.
+    Overlapped: two descents in two host threads, so the device update of one
+    overlaps the host evaluation of the other."""
+    import threading
+    import synth
+    xs = synth.optimum(n, seed)
+
+    def evaluate(X, delay):
+        # shifted sphere on the host (the blackbox), plus the added cost
+        D = X - xs[:, None]
+        f = np.einsum("ij,ij->j", D, D)
+        if delay > 0:
+            time.sleep(delay)
+        return f
+
+    def descent(es, delay, count, out, idx):
+        t0 = time.perf_counter()
+        for _ in range(count):
+            X = es.ask()
+            es.tell(evaluate(X, delay))
+        out[idx] = time.perf_counter() - t0
+
+    res = []
+    for d in delays_ms:
+        delay = d / 1000.0
+        handles = [P.CMAES(n, lam, 2.0, seed=seed + i, precision="mixed") for i in range(2)]
+        try:
+            for es in handles:
+                es.autotune(reps=3)
+                X = es.ask()
+                es.tell(evaluate(X, 0.0))
+            out = [0.0, 0.0]
+            descent(handles[0], delay, gens, out, 0)
+            serial = gens / out[0]
+            ths = [threading.Thread(target=descent, args=(handles[i], delay, gens, out, i)) for i in range(2)]
+            t0 = time.perf_counter()
+            for t in ths:
+                t.start()
+            for t in ths:
+                t.join()
+            both = 2 * gens / (time.perf_counter() - t0)
+        finally:
+            for es in handles:
+                es.close()
+        res.append({"delay_ms": d, "serial_gens_per_s": serial, "serial_evals_per_s": serial * lam,
+                    "two_descents_gens_per_s": both, "two_descents_evals_per_s": both * lam,
+                    "overlap_gain": both / serial})
+        print(json.dumps(res[-1]), file=sys.stderr, flush=True)
+    return {"workload": f"n={n}, lambda={lam} (K=2^8), mixed; host-side shifted sphere (NumPy) + added delay "
+                        f"per generation", "rows": res}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -202,6 +307,12 @@ def main():
     n, lam = a.n, a.lam
     R, xs = synth.problem(n, a.seed)
     torch.cuda.set_device(0)
+    if a.ablation:
+        print(json.dumps({"ablation": run_ablation(P, torch, a.seed)}), flush=True)
+        return
+    if a.asktell:
+        print(json.dumps({"asktell": run_asktell(P, torch, a.seed)}), flush=True)
+        return
     tiles = [int(v) for v in a.tiles.split(",")] if a.tiles else None
     mixed = run_gpu(P, torch, n, lam, a.precision, a.steps, a.warmup, a.seed, R, xs, tune=not a.no_tune,
                     tiles=tiles)

@@ -199,6 +199,8 @@ int cmaes_batch_set_options(cmaes_batch_t* b, const cmaes_options_t* opt);
 /* Fused objective of instance k (as cmaes_set_objective). */
 int cmaes_batch_set_objective(cmaes_batch_t* b, int k, int kind, const double* R, const double* xstar);
 /* One generation of every instance, then restart-on-finish. */
+/* Graph replay for every instance of the batch (see cmaes_enable_graphs). */
+int cmaes_batch_enable_graphs(cmaes_batch_t* b, int on);
 int cmaes_batch_generation(cmaes_batch_t* b);
 /* State of instance k (as cmaes_state). */
 int cmaes_batch_state(const cmaes_batch_t* b, int k, cmaes_state_t* out);
@@ -224,6 +226,17 @@ int cmaes_phase_times(const cmaes_t* h, double* out);
 #define CMAES_KERNEL_EIG_GEMM 5    /* float64 products of the eigensolver       */
 #define CMAES_KERNEL_JACOBI 6      /* persistent block-Jacobi sweeps            */
 #define CMAES_NUM_KERNELS 7
+/* Graph replay of the generation (Sec. 3.1 pipeline as one captured unit).
+ * cmaes_generation (and the batch generation) queue the fixed part of a
+ * generation -- sampling, fitness, ranking, recombination, paths, the
+ * covariance update and the eigensolve set-up -- as one hipGraph, captured on
+ * first use and replayed while the handle's shapes, stream, objective,
+ * options and GEMM tiles are unchanged (any change re-captures).  The
+ * data-dependent sweeps of the eigensolve and the stop tests stay eager.
+ * Results are bit-identical with graphs on or off.  Default on; graphs are
+ * not used while phase or kernel timing is enabled, with caller-supplied z,
+ * or on the legacy null stream. */
+int cmaes_enable_graphs(cmaes_t* h, int on);
 int cmaes_enable_kernel_timing(cmaes_t* h, int on);
 int cmaes_kernel_times(const cmaes_t* h, double* total_us, int64_t* calls);
 

@@ -83,6 +83,8 @@ def _load():
         "cmaes_enable_timing": (C.c_int, [H, C.c_int]),
         "cmaes_phase_times": (C.c_int, [H, _PD]),
         "cmaes_enable_kernel_timing": (C.c_int, [H, C.c_int]),
+        "cmaes_enable_graphs": (C.c_int, [H, C.c_int]),
+        "cmaes_batch_enable_graphs": (C.c_int, [H, C.c_int]),
         "cmaes_kernel_times": (C.c_int, [H, _PD, C.POINTER(C.c_int64)]),
         "cmaes_last_error": (C.c_char_p, []),
         "cmaes_gemm_config_count": (C.c_int, []),
@@ -112,6 +114,7 @@ EXPORTED = ["cmaes_default_options", "cmaes_create", "cmaes_destroy", "cmaes_set
             "cmaes_get_options", "cmaes_set_objective", "cmaes_generation", "cmaes_generation_with_z",
             "cmaes_ask", "cmaes_tell", "cmaes_restart_ipop", "cmaes_ipop_run", "cmaes_state",
             "cmaes_set_state", "cmaes_enable_timing", "cmaes_phase_times", "cmaes_enable_kernel_timing",
+            "cmaes_enable_graphs", "cmaes_batch_enable_graphs",
             "cmaes_kernel_times", "cmaes_last_error", "cmaes_gemm_config_count", "cmaes_gemm_config_info",
             "cmaes_set_gemm_config", "cmaes_get_gemm_config", "cmaes_autotune", "cmaes_device_arch",
             "cmaes_batch_create", "cmaes_batch_destroy",
@@ -262,6 +265,14 @@ def cmaes_phase_times(h) -> dict:
     return dict(zip(PHASES, out.tolist()))
 
 
+def cmaes_enable_graphs(h, on: bool = True):
+    _check(_lib.cmaes_enable_graphs(h, 1 if on else 0))
+
+
+def cmaes_batch_enable_graphs(b, on: bool = True):
+    _check(_lib.cmaes_batch_enable_graphs(b, 1 if on else 0))
+
+
 def cmaes_enable_kernel_timing(h, on: bool = True):
     _check(_lib.cmaes_enable_kernel_timing(h, 1 if on else 0))
 
@@ -389,6 +400,9 @@ class CMAES:
     def phase_times(self):
         return cmaes_phase_times(self.h)
 
+    def enable_graphs(self, on=True):
+        cmaes_enable_graphs(self.h, on)
+
     def enable_kernel_timing(self, on=True):
         cmaes_enable_kernel_timing(self.h, on)
 
@@ -488,6 +502,9 @@ class CMAESBatch:
 
     def set_objective(self, k, kind, R=None, xstar=None):
         cmaes_batch_set_objective(self.b, k, kind, self.n[k], R, xstar)
+
+    def enable_graphs(self, on=True):
+        cmaes_batch_enable_graphs(self.b, on)
 
     def generation(self):
         cmaes_batch_generation(self.b)

@@ -111,6 +111,12 @@ struct cmaes {
   KTimer kt;
   bool eig_due = false;
   int gcfg[G32_NUM_SITES] = {0, 0, 0};  // float32 GEMM tile per call site
+  // captured front of a generation (sampling .. eigensolve set-up), one per
+  // value of eig_due, valid while gkey matches (see front_key)
+  bool graphs = true;
+  uint64_t epoch = 1;
+  hipGraphExec_t gx[2] = {nullptr, nullptr};
+  uint64_t gkey[2] = {0, 0};
 
   // float64 state
   DevScalars* sc = nullptr;
@@ -148,7 +154,18 @@ void free_pop_buffers(cmaes* h) {
   h->cap_lam = h->cap_mu = h->hist_cap = 0;
 }
 
+void drop_graphs(cmaes* h) {
+  if ((h->gx[0] || h->gx[1]) && h->st) (void)hipStreamSynchronize(h->st);  // no replay in flight
+  for (int i = 0; i < 2; ++i) {
+    if (h->gx[i]) (void)hipGraphExecDestroy(h->gx[i]);
+    h->gx[i] = nullptr;
+    h->gkey[i] = 0;
+  }
+  h->epoch += 1;
+}
+
 void free_all(cmaes* h) {
+  drop_graphs(h);
   free_pop_buffers(h);
   dev_free(h->sc);
   dev_free(h->m);
@@ -204,6 +221,7 @@ void refresh_stop_params(cmaes* h) {
 int alloc_pop(cmaes* h) {
   const int n = h->n, ldn = h->ldn, lam = h->lam, mu = h->hp.kp.mu;
   if (lam <= h->cap_lam && mu <= h->cap_mu && hist_len_for(n, lam) <= h->hist_cap) return 0;
+  drop_graphs(h);
   free_pop_buffers(h);
   const size_t e = esz(h);
   int rc = 0;
@@ -426,12 +444,17 @@ int phase_update_pre(cmaes* h) {
                      static_cast<float*>(h->syrk_work), h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc, false));
   kt_end(&h->kt);
   rec(h, 5);
-  h->gen += 1;
-  h->evals += lam;
-  h->total_evals += lam;
-  h->eig_due = (h->gen % h->hp.kp.kappa == 0);
   if (h->eig_due) return eigen_begin(h->st, n, h->C, ldn, h->B, ldn, h->ew, &h->kt);
   return 0;
+}
+
+// host-side counters of the generation just queued; eig_due must be set
+// (due_next) before its launches are queued
+bool due_next(const cmaes* h) { return (h->gen + 1) % h->hp.kp.kappa == 0; }
+void advance_counters(cmaes* h) {
+  h->gen += 1;
+  h->evals += h->lam;
+  h->total_evals += h->lam;
 }
 
 // one step of the eigensolve in flight (the stream must have been
@@ -470,7 +493,9 @@ int phase_update_post(cmaes* h) {
 }
 
 int phase_update(cmaes* h) {
+  h->eig_due = due_next(h);
   if (int rc = phase_update_pre(h)) return rc;
+  advance_counters(h);
   if (h->eig_due) {
     for (bool done = false; !done;) {
       CMX_HIP(hipStreamSynchronize(h->st));
@@ -482,6 +507,62 @@ int phase_update(cmaes* h) {
 
 int check(const cmaes* h) {
   if (!h) return fail(CMAES_EINVAL, "null handle");
+  return 0;
+}
+
+// everything a captured front depends on besides device memory contents:
+// buffer addresses (epoch), launch shapes and the host-side kernel arguments
+uint64_t front_key(const cmaes* h, bool due) {
+  uint64_t k = h->epoch;
+  auto mix = [&k](uint64_t v) { k = (k ^ v) * 0x100000001B3ull + 0x9E3779B97F4A7C15ull; };
+  mix(static_cast<uint64_t>(h->lam));
+  mix(static_cast<uint64_t>(h->restart));
+  mix(reinterpret_cast<uintptr_t>(h->st));
+  mix(static_cast<uint64_t>(h->obj_kind) | (h->have_R ? 16u : 0u) | (h->have_xstar ? 32u : 0u));
+  mix(static_cast<uint64_t>(h->opt.precision));
+  for (int i = 0; i < G32_NUM_SITES; ++i) mix(static_cast<uint64_t>(h->gcfg[i]));
+  mix(due ? 1u : 0u);
+  return k | 1u;  // never 0 (0 marks an empty slot)
+}
+
+// the launches of a generation up to the eigensolve set-up, eagerly or by
+// replaying a captured graph; then the host counters
+int front(cmaes* h) {
+  h->eig_due = due_next(h);
+  const bool can_graph = h->graphs && h->st != nullptr && !h->timing && !h->kt.on;
+  if (!can_graph) {
+    if (int rc = phase_sample(h, nullptr)) return rc;
+    if (int rc = phase_fitness(h)) return rc;
+    if (int rc = phase_update_pre(h)) return rc;
+    advance_counters(h);
+    return 0;
+  }
+  const int slot = h->eig_due ? 1 : 0;
+  const uint64_t key = front_key(h, h->eig_due);
+  if (h->gx[slot] == nullptr || h->gkey[slot] != key) {
+    if (h->gx[slot]) (void)hipGraphExecDestroy(h->gx[slot]);
+    h->gx[slot] = nullptr;
+    h->gkey[slot] = 0;
+    CMX_HIP(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+    int rc = phase_sample(h, nullptr);
+    if (!rc) rc = phase_fitness(h);
+    if (!rc) rc = phase_update_pre(h);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(h->st, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ce != hipSuccess) return fail(CMAES_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+    const hipError_t ie = hipGraphInstantiate(&h->gx[slot], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(CMAES_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    h->gkey[slot] = key;
+  } else if (h->eig_due) {
+    eigen_begin_host(h->ew);
+  }
+  CMX_HIP(hipGraphLaunch(h->gx[slot], h->st));
+  advance_counters(h);
   return 0;
 }
 
@@ -581,6 +662,7 @@ void cmaes_destroy(cmaes_t* h) {
 }
 
 int cmaes_set_options(cmaes_t* h, const cmaes_options_t* o) {
+  if (h) drop_graphs(h);
   if (int rc = check(h)) return rc;
   if (!o) return fail(CMAES_EINVAL, "null options");
   if (o->precision < CMAES_FP64 || o->precision > CMAES_MIXED_BF16X3)
@@ -626,6 +708,7 @@ int cmaes_get_options(const cmaes_t* h, cmaes_options_t* o) {
 
 int cmaes_set_objective(cmaes_t* h, int kind, const double* R, const double* xstar) {
   if (int rc = check(h)) return rc;
+  drop_graphs(h);
   if (kind < CMAES_OBJ_NONE || kind > CMAES_OBJ_RASTRIGIN) return fail(CMAES_EINVAL, "unknown objective");
   const size_t n = static_cast<size_t>(h->n);
   h->have_R = R != nullptr;
@@ -643,9 +726,14 @@ int cmaes_generation(cmaes_t* h) {
   if (int rc = check(h)) return rc;
   if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "no fused objective set (use ask/tell)");
   if (int rc = ensure_ready(h)) return rc;
-  if (int rc = phase_sample(h, nullptr)) return rc;
-  if (int rc = phase_fitness(h)) return rc;
-  return phase_update(h);
+  if (int rc = front(h)) return rc;
+  if (h->eig_due) {
+    for (bool done = false; !done;) {
+      CMX_HIP(hipStreamSynchronize(h->st));
+      if (int rc = eigen_advance(h, &done)) return rc;
+    }
+  }
+  return phase_update_post(h);
 }
 
 int cmaes_generation_with_z(cmaes_t* h, const double* Z) {
@@ -822,6 +910,13 @@ int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in) {
 int cmaes_enable_timing(cmaes_t* h, int on) {
   if (int rc = check(h)) return rc;
   h->timing = on != 0;
+  return CMAES_OK;
+}
+
+int cmaes_enable_graphs(cmaes_t* h, int on) {
+  if (int rc = check(h)) return rc;
+  h->graphs = on != 0;
+  drop_graphs(h);
   return CMAES_OK;
 }
 
@@ -1035,6 +1130,13 @@ int cmaes_batch_set_options(cmaes_batch_t* b, const cmaes_options_t* opt) {
   return CMAES_OK;
 }
 
+int cmaes_batch_enable_graphs(cmaes_batch_t* b, int on) {
+  if (!b) return fail(CMAES_EINVAL, "null batch");
+  for (cmaes* h : b->inst)
+    if (int rc = cmaes_enable_graphs(h, on)) return rc;
+  return CMAES_OK;
+}
+
 int cmaes_batch_set_objective(cmaes_batch_t* b, int k, int kind, const double* R, const double* xstar) {
   if (int rc = batch_check(b, k)) return rc;
   return cmaes_set_objective(b->inst[k], kind, R, xstar);
@@ -1046,9 +1148,7 @@ int cmaes_batch_generation(cmaes_batch_t* b) {
     if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "every instance needs a fused objective");
   for (cmaes* h : b->inst) {
     if (int rc = ensure_ready(h)) return rc;
-    if (int rc = phase_sample(h, nullptr)) return rc;
-    if (int rc = phase_fitness(h)) return rc;
-    if (int rc = phase_update_pre(h)) return rc;
+    if (int rc = front(h)) return rc;
   }
   std::vector<cmaes*> pending;
   for (cmaes* h : b->inst)

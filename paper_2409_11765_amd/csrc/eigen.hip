@@ -595,15 +595,20 @@ __global__ void __launch_bounds__(256) k_permute(const double* __restrict__ Bn, 
 // synchronisation per sweep (the convergence flag is the only value the
 // host needs between sweeps; it lands in pinned host memory).
 
-int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B, int ldb, EigWork& w,
-                KTimer* kt) {
-  const int N = w.N;
-  const int64_t NN = static_cast<int64_t>(N) * N;
+void eigen_begin_host(EigWork& w) {
   w.Acur = w.A;
   w.Anext = w.A2;
   w.Qcur = w.Q;
   w.Qnext = w.Q2;
   w.sweeps = 0;
+  w.pending = true;
+}
+
+int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B, int ldb, EigWork& w,
+                KTimer* kt) {
+  const int N = w.N;
+  const int64_t NN = static_cast<int64_t>(N) * N;
+  eigen_begin_host(w);
   k_fill<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.Acur, NN, 0.0);
   k_fill<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.Anext, NN, 0.0);
   k_identity<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.V, N);

@@ -188,6 +188,8 @@ struct EigWork {
 // synchronises the stream and calls eigen_step until it reports done (each
 // call queues one more sweep, or the finishing kernels).
 int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B, int ldb, EigWork& w, KTimer* kt);
+// the host-side part of eigen_begin alone (after replaying its launches from a graph)
+void eigen_begin_host(EigWork& w);
 int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, bool fp64_bd, int ldbd, EigWork& w,
                DevScalars* sc, int max_sweeps, KTimer* kt, bool* done);
 

@@ -41,6 +41,13 @@ __global__ void __launch_bounds__(256) k_rank_count(const double* __restrict__ f
   if (i < lam && cnt) atomicAdd(&rank[i], cnt);
 }
 
+// zero fill by a kernel, so the sequence stays free of memset nodes when a
+// generation is captured into a graph
+__global__ void k_zero_i32(int32_t* __restrict__ p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
 __global__ void k_scatter_order(const int32_t* __restrict__ rank, int lam, int32_t* __restrict__ order) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < lam) order[rank[i]] = i;
@@ -285,11 +292,9 @@ __global__ void k_convert(const double* __restrict__ s, int lds, T* __restrict__
 }  // namespace
 
 hipError_t launch_rank(hipStream_t st, const double* f, int lam, int32_t* order) {
-  // order[] doubles as the count array: zero it, count, then scatter into
-  // the upper half of a temporary... keep it simple: counts live in order+lam.
+  // the rank counters live in order[lam, 2 lam)
   int32_t* rank = order + lam;
-  hipError_t e = hipMemsetAsync(rank, 0, sizeof(int32_t) * lam, st);
-  if (e != hipSuccess) return e;
+  k_zero_i32<<<ceil_div(lam, 256), 256, 0, st>>>(rank, lam);
   const int splits = max(1, min(16, lam / 512));
   const int span = ceil_div(lam, splits);
   dim3 grid(ceil_div(lam, 256), splits);
