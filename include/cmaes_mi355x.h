@@ -274,6 +274,39 @@ int cmaes_get_gemm_config(const cmaes_t* h, int site, int32_t* cfg);
 int cmaes_autotune(cmaes_t* h, int reps, double* us, int32_t* chosen);
 int cmaes_device_arch(char* buf, int len);
 
+/* ---- K-Replicated strategy (Sec. 3.2.2, Alg. 3) on one GPU ---------------
+ * A binary tree of descents over one GPU's evaluation slots: k_max leaf
+ * descents (lambda_start each, own seeds) start together; when both children
+ * of a node have finished (any stop test), the node's descent starts with
+ * twice their population size (an IPOP restart of the left child's handle;
+ * the right child's handle is released), until the root descent
+ * (lambda_start * k_max) finishes.  Every generation steps all running
+ * descents in lockstep (fronts queued on per-descent streams, eigensolve
+ * sweeps advanced together).  The run is done when the root finishes or the
+ * best f found falls below f_target.
+ *
+ * cmaes_krep_create: k_max a power of two in [1, 1024]; lambda_start <= 0
+ *   picks the default population size for n; NULL on failure.
+ * cmaes_krep_set_options: applied to every descent (their streams are their
+ *   own; k_max raised to the tree's); cmaes_krep_set_objective likewise.
+ * cmaes_krep_generation: one lockstep generation, then the merges; a no-op
+ *   once done.  cmaes_krep_run: generations until done or the limit.
+ * cmaes_krep_status: running / finished descents, largest running lambda,
+ *   lockstep generations, evaluations over all descents, best f, done. */
+typedef struct cmaes_krep cmaes_krep_t;
+typedef struct {
+  int32_t running, finished, lambda_max_running, done;
+  int64_t lockstep_generations, total_evals;
+  double f_best;
+} cmaes_krep_status_t;
+cmaes_krep_t* cmaes_krep_create(int n, int lambda_start, int k_max, double sigma0, uint64_t seed);
+void cmaes_krep_destroy(cmaes_krep_t* r);
+int cmaes_krep_set_options(cmaes_krep_t* r, const cmaes_options_t* opt);
+int cmaes_krep_set_objective(cmaes_krep_t* r, int kind, const double* R, const double* xstar);
+int cmaes_krep_generation(cmaes_krep_t* r);
+int cmaes_krep_run(cmaes_krep_t* r, int64_t max_lockstep_generations);
+int cmaes_krep_status(const cmaes_krep_t* r, cmaes_krep_status_t* out);
+
 /* Thread-local message for the last failing call (never NULL). */
 const char* cmaes_last_error(void);
 

@@ -59,6 +59,12 @@ class CmaesState(C.Structure):
                 ("x_best", _PD), ("f", _PD), ("order", _PI)]
 
 
+class KrepStatus(C.Structure):
+    _fields_ = [("running", C.c_int32), ("finished", C.c_int32), ("lambda_max_running", C.c_int32),
+                ("done", C.c_int32), ("lockstep_generations", C.c_int64), ("total_evals", C.c_int64),
+                ("f_best", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
@@ -101,6 +107,13 @@ def _load():
         "cmaes_batch_generation": (C.c_int, [H]),
         "cmaes_batch_state": (C.c_int, [H, C.c_int, C.POINTER(CmaesState)]),
         "cmaes_batch_best": (C.c_int, [H, _PD, C.POINTER(C.c_int)]),
+        "cmaes_krep_create": (H, [C.c_int, C.c_int, C.c_int, C.c_double, C.c_uint64]),
+        "cmaes_krep_destroy": (None, [H]),
+        "cmaes_krep_set_options": (C.c_int, [H, C.POINTER(CmaesOptions)]),
+        "cmaes_krep_set_objective": (C.c_int, [H, C.c_int, _PD, _PD]),
+        "cmaes_krep_generation": (C.c_int, [H]),
+        "cmaes_krep_run": (C.c_int, [H, C.c_int64]),
+        "cmaes_krep_status": (C.c_int, [H, C.POINTER(KrepStatus)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -119,7 +132,9 @@ EXPORTED = ["cmaes_default_options", "cmaes_create", "cmaes_destroy", "cmaes_set
             "cmaes_set_gemm_config", "cmaes_get_gemm_config", "cmaes_autotune", "cmaes_device_arch",
             "cmaes_batch_create", "cmaes_batch_destroy",
             "cmaes_batch_count", "cmaes_batch_set_options", "cmaes_batch_set_objective", "cmaes_batch_generation",
-            "cmaes_batch_state", "cmaes_batch_best"]
+            "cmaes_batch_state", "cmaes_batch_best", "cmaes_krep_create", "cmaes_krep_destroy",
+            "cmaes_krep_set_options", "cmaes_krep_set_objective", "cmaes_krep_generation", "cmaes_krep_run",
+            "cmaes_krep_status"]
 
 
 def library():
@@ -519,6 +534,86 @@ class CMAESBatch:
         if self.b:
             cmaes_batch_destroy(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+# ---- K-Replicated (Alg. 3) -------------------------------------------------
+
+def cmaes_krep_create(n, lambda_start, k_max, sigma0, seed):
+    r = _lib.cmaes_krep_create(int(n), int(lambda_start), int(k_max), float(sigma0), int(seed))
+    if not r:
+        raise CmaesError(CMAES_EINVAL, cmaes_last_error())
+    return r
+
+
+def cmaes_krep_destroy(r):
+    _lib.cmaes_krep_destroy(r)
+
+
+def cmaes_krep_set_options(r, opt: CmaesOptions):
+    _check(_lib.cmaes_krep_set_options(r, C.byref(opt)))
+
+
+def cmaes_krep_set_objective(r, kind, n, R=None, xstar=None):
+    k = OBJECTIVES[kind] if isinstance(kind, str) else int(kind)
+    Rm = _colmajor(R, (n, n)) if R is not None else None
+    xs = np.ascontiguousarray(xstar, dtype=np.float64) if xstar is not None else None
+    _check(_lib.cmaes_krep_set_objective(r, k, _dptr(Rm), _dptr(xs)))
+
+
+def cmaes_krep_generation(r):
+    _check(_lib.cmaes_krep_generation(r))
+
+
+def cmaes_krep_run(r, max_lockstep_generations):
+    _check(_lib.cmaes_krep_run(r, int(max_lockstep_generations)))
+
+
+def cmaes_krep_status(r) -> dict:
+    s = KrepStatus()
+    _check(_lib.cmaes_krep_status(r, C.byref(s)))
+    return {k: getattr(s, k) for k, _ in KrepStatus._fields_}
+
+
+class KReplicated:
+    """Owning wrapper of a K-Replicated run (binary tree of descents)."""
+
+    def __init__(self, n, lambda_start=0, k_max=4, sigma0=2.0, seed=0, precision="mixed", objective=None,
+                 R=None, xstar=None, **options):
+        self.n = n
+        self.r = cmaes_krep_create(n, lambda_start, k_max, sigma0, seed)
+        opt = cmaes_default_options()
+        opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        for k, v in options.items():
+            setattr(opt, k, v)
+        cmaes_krep_set_options(self.r, opt)
+        if objective is not None:
+            cmaes_krep_set_objective(self.r, objective, n, R, xstar)
+
+    def generation(self):
+        cmaes_krep_generation(self.r)
+
+    def run(self, max_lockstep_generations):
+        cmaes_krep_run(self.r, max_lockstep_generations)
+
+    def status(self):
+        return cmaes_krep_status(self.r)
+
+    def close(self):
+        if self.r:
+            cmaes_krep_destroy(self.r)
+            self.r = None
 
     def __del__(self):
         try:

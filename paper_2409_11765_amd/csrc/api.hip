@@ -1073,6 +1073,34 @@ int restart_same_lambda(cmaes* h) {
   return init_descent(h, false);
 }
 
+// one generation of every handle: all fronts queued first (each on its own
+// stream), then the eigensolve sweeps of all handles advanced in lockstep with
+// one host synchronisation per sweep for the whole set, then the stop tests
+int lockstep_generation(const std::vector<cmaes*>& hs) {
+  for (cmaes* h : hs)
+    if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "every instance needs a fused objective");
+  for (cmaes* h : hs) {
+    if (int rc = ensure_ready(h)) return rc;
+    if (int rc = front(h)) return rc;
+  }
+  std::vector<cmaes*> pending;
+  for (cmaes* h : hs)
+    if (h->eig_due) pending.push_back(h);
+  while (!pending.empty()) {
+    for (cmaes* h : pending) CMX_HIP(hipStreamSynchronize(h->st));
+    std::vector<cmaes*> still;
+    for (cmaes* h : pending) {
+      bool done = false;
+      if (int rc = eigen_advance(h, &done)) return rc;
+      if (!done) still.push_back(h);
+    }
+    pending.swap(still);
+  }
+  for (cmaes* h : hs)
+    if (int rc = phase_update_post(h)) return rc;
+  return 0;
+}
+
 int batch_check(const cmaes_batch* b, int k) {
   if (!b) return fail(CMAES_EINVAL, "null batch");
   if (k < 0 || k >= static_cast<int>(b->inst.size())) return fail(CMAES_EINVAL, "instance index out of range");
@@ -1144,27 +1172,7 @@ int cmaes_batch_set_objective(cmaes_batch_t* b, int k, int kind, const double* R
 
 int cmaes_batch_generation(cmaes_batch_t* b) {
   if (!b) return fail(CMAES_EINVAL, "null batch");
-  for (cmaes* h : b->inst)
-    if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "every instance needs a fused objective");
-  for (cmaes* h : b->inst) {
-    if (int rc = ensure_ready(h)) return rc;
-    if (int rc = front(h)) return rc;
-  }
-  std::vector<cmaes*> pending;
-  for (cmaes* h : b->inst)
-    if (h->eig_due) pending.push_back(h);
-  while (!pending.empty()) {
-    for (cmaes* h : pending) CMX_HIP(hipStreamSynchronize(h->st));
-    std::vector<cmaes*> still;
-    for (cmaes* h : pending) {
-      bool done = false;
-      if (int rc = eigen_advance(h, &done)) return rc;
-      if (!done) still.push_back(h);
-    }
-    pending.swap(still);
-  }
-  for (cmaes* h : b->inst)
-    if (int rc = phase_update_post(h)) return rc;
+  if (int rc = lockstep_generation(b->inst)) return rc;
   // restart-on-finish with the same population size
   for (size_t k = 0; k < b->inst.size(); ++k) {
     cmaes* h = b->inst[k];
@@ -1197,6 +1205,224 @@ int cmaes_batch_best(const cmaes_batch_t* b, double* f_best, int* k_best) {
   }
   if (f_best) *f_best = best;
   if (k_best) *k_best = arg;
+  return CMAES_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// K-Replicated strategy (Sec. 3.2.2, Alg. 3) on one GPU.  The resources that
+// the paper splits into communicator halves are here the evaluation slots of
+// one lockstep generation: k_max descents with lambda_start each start at
+// once (the leaves of a binary tree); whenever both children of a tree node
+// have finished, the node's descent starts with twice their population size
+// (it takes over the left child's handle through an IPOP restart, the right
+// child's handle is released), so the number of evaluations per lockstep
+// generation stays k_max * lambda_start while descents run, until the root
+// descent (lambda_start * k_max) finishes.  Every leaf has its own seed; a
+// parent continues its left child's counter-based stream at the next restart
+// index.
+
+struct cmaes_krep {
+  int n = 0, lam0 = 0, k_max = 1, levels = 0;
+  cmaes_options_t opt{};
+  bool have_opt = false;
+  int obj_kind = CMAES_OBJ_NONE;
+  std::vector<double> R, xstar;
+  bool have_R = false, have_xstar = false;
+  // node (level l, index j) is slot (2^(levels-l) - 1) + j of the arrays below
+  std::vector<cmaes*> handle;      // running or finished-but-unmerged descent, else null
+  std::vector<uint8_t> finished;   // descent of the node has finished
+  std::vector<int32_t> gens;       // generations run by the node's descent
+  int64_t released_evals = 0;      // evaluations of released handles
+  double released_best = HUGE_VAL; // best f of released handles
+  int64_t lockstep_gens = 0;
+  bool done = false;
+};
+
+namespace {
+
+int krep_slot(const cmaes_krep* r, int level, int j) { return ((1 << (r->levels - level)) - 1) + j; }
+
+int krep_apply(cmaes_krep* r, cmaes* h) {
+  if (r->have_opt) {
+    cmaes_options_t o = r->opt;
+    o.stream = nullptr;  // every descent on its own stream
+    o.k_max = std::max(o.k_max, r->k_max);
+    if (int rc = cmaes_set_options(h, &o)) return rc;
+  } else {
+    cmaes_options_t o;
+    cmaes_get_options(h, &o);
+    o.k_max = std::max(o.k_max, r->k_max);
+    if (int rc = cmaes_set_options(h, &o)) return rc;
+  }
+  if (r->obj_kind != CMAES_OBJ_NONE)
+    return cmaes_set_objective(h, r->obj_kind, r->have_R ? r->R.data() : nullptr,
+                               r->have_xstar ? r->xstar.data() : nullptr);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+cmaes_krep_t* cmaes_krep_create(int n, int lambda_start, int k_max, double sigma0, uint64_t seed) {
+  if (n < 1 || k_max < 1 || k_max > 1024 || (k_max & (k_max - 1)) != 0) {
+    set_error("cmaes_krep_create: n >= 1 and k_max a power of two in [1, 1024]");
+    return nullptr;
+  }
+  cmaes_krep* r = new (std::nothrow) cmaes_krep();
+  if (!r) {
+    set_error("host allocation failed");
+    return nullptr;
+  }
+  r->n = n;
+  r->k_max = k_max;
+  while ((1 << r->levels) < k_max) ++r->levels;
+  const int nodes = 2 * k_max - 1;
+  r->handle.assign(nodes, nullptr);
+  r->finished.assign(nodes, 0);
+  r->gens.assign(nodes, 0);
+  for (int j = 0; j < k_max; ++j) {
+    // distinct leaf seeds: the run's seed mixed with the leaf index
+    const uint64_t s = seed * 0x9E3779B97F4A7C15ull + static_cast<uint64_t>(j) * 0xBF58476D1CE4E5B9ull + 1;
+    cmaes* h = cmaes_create(n, lambda_start, sigma0, s);
+    if (!h) {
+      const std::string why = g_err;
+      cmaes_krep_destroy(r);
+      set_error("leaf " + std::to_string(j) + ": " + why);
+      return nullptr;
+    }
+    r->handle[krep_slot(r, 0, j)] = h;
+    r->lam0 = h->lam;
+    if (krep_apply(r, h)) {
+      const std::string why = g_err;
+      cmaes_krep_destroy(r);
+      set_error("leaf " + std::to_string(j) + ": " + why);
+      return nullptr;
+    }
+  }
+  return r;
+}
+
+void cmaes_krep_destroy(cmaes_krep_t* r) {
+  if (!r) return;
+  for (cmaes* h : r->handle) cmaes_destroy(h);
+  delete r;
+}
+
+int cmaes_krep_set_options(cmaes_krep_t* r, const cmaes_options_t* o) {
+  if (!r || !o) return fail(CMAES_EINVAL, "null argument");
+  r->opt = *o;
+  r->have_opt = true;
+  for (cmaes* h : r->handle)
+    if (h)
+      if (int rc = krep_apply(r, h)) return rc;
+  return CMAES_OK;
+}
+
+int cmaes_krep_set_objective(cmaes_krep_t* r, int kind, const double* R, const double* xstar) {
+  if (!r) return fail(CMAES_EINVAL, "null argument");
+  if (kind < CMAES_OBJ_NONE || kind > CMAES_OBJ_RASTRIGIN) return fail(CMAES_EINVAL, "unknown objective");
+  const size_t n = static_cast<size_t>(r->n);
+  r->obj_kind = kind;
+  r->have_R = R != nullptr;
+  r->have_xstar = xstar != nullptr;
+  r->R.assign(R ? R : R, R ? R + n * n : R);
+  r->xstar.assign(xstar ? xstar : xstar, xstar ? xstar + n : xstar);
+  for (cmaes* h : r->handle)
+    if (h)
+      if (int rc = cmaes_set_objective(h, kind, R, xstar)) return rc;
+  return CMAES_OK;
+}
+
+int cmaes_krep_generation(cmaes_krep_t* r) {
+  if (!r) return fail(CMAES_EINVAL, "null argument");
+  if (r->done) return CMAES_OK;
+  std::vector<cmaes*> run;
+  std::vector<int> slot;
+  for (int l = 0; l <= r->levels; ++l)
+    for (int j = 0; j < (r->k_max >> l); ++j) {
+      const int s = krep_slot(r, l, j);
+      if (r->handle[s] && !r->finished[s]) {
+        run.push_back(r->handle[s]);
+        slot.push_back(s);
+      }
+    }
+  if (int rc = lockstep_generation(run)) return rc;
+  r->lockstep_gens += 1;
+  double best = r->released_best;
+  for (size_t i = 0; i < run.size(); ++i) {
+    DevScalars sc;
+    if (int rc = read_scalars(run[i], &sc)) return rc;
+    r->gens[slot[i]] += 1;
+    if (sc.stop) r->finished[slot[i]] = 1;
+  }
+  for (cmaes* h : r->handle)
+    if (h) {
+      DevScalars sc;
+      if (int rc = read_scalars(h, &sc)) return rc;
+      best = std::min(best, sc.f_best);
+    }
+  // merge finished sibling pairs into their parent (Alg. 3: the control flows
+  // back to the parent communicator once both halves are done)
+  for (int l = 1; l <= r->levels; ++l)
+    for (int j = 0; j < (r->k_max >> l); ++j) {
+      const int p = krep_slot(r, l, j), a = krep_slot(r, l - 1, 2 * j), b = krep_slot(r, l - 1, 2 * j + 1);
+      if (r->handle[p] || r->finished[p] || !r->finished[a] || !r->finished[b]) continue;
+      cmaes* hb = r->handle[b];
+      if (hb) {
+        DevScalars sb;
+        if (int rc = read_scalars(hb, &sb)) return rc;
+        r->released_best = std::min(r->released_best, sb.f_best);
+        r->released_evals += hb->total_evals;
+        r->handle[b] = nullptr;
+        cmaes_destroy(hb);
+      }
+      cmaes* ha = r->handle[a];
+      r->handle[a] = nullptr;
+      r->handle[p] = ha;
+      if (int rc = cmaes_restart_ipop(ha)) return rc;
+    }
+  const int root = krep_slot(r, r->levels, 0);
+  const bool target = r->have_opt ? best < r->opt.f_target : best < 1e-8;
+  r->done = r->finished[root] || target;
+  return CMAES_OK;
+}
+
+int cmaes_krep_status(const cmaes_krep_t* r, cmaes_krep_status_t* out) {
+  if (!r || !out) return fail(CMAES_EINVAL, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  double best = r->released_best;
+  int64_t evals = r->released_evals;
+  int32_t lmax = 0;
+  for (int l = 0; l <= r->levels; ++l)
+    for (int j = 0; j < (r->k_max >> l); ++j) {
+      const int s = krep_slot(r, l, j);
+      if (r->finished[s]) out->finished += 1;
+      cmaes* h = r->handle[s];
+      if (!h) continue;
+      if (!r->finished[s]) {
+        out->running += 1;
+        lmax = std::max(lmax, h->lam);
+      }
+      DevScalars sc;
+      if (int rc = read_scalars(const_cast<cmaes*>(h), &sc)) return rc;
+      best = std::min(best, sc.f_best);
+      evals += h->total_evals;
+    }
+  out->lambda_max_running = lmax;
+  out->done = r->done ? 1 : 0;
+  out->lockstep_generations = r->lockstep_gens;
+  out->total_evals = evals;
+  out->f_best = best;
+  return CMAES_OK;
+}
+
+int cmaes_krep_run(cmaes_krep_t* r, int64_t max_lockstep_generations) {
+  if (!r) return fail(CMAES_EINVAL, "null argument");
+  for (int64_t g = 0; !r->done && g < max_lockstep_generations; ++g)
+    if (int rc = cmaes_krep_generation(r)) return rc;
   return CMAES_OK;
 }
 

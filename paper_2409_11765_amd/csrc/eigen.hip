@@ -28,6 +28,8 @@
 //  3. B = B_old V, D = sqrt(diag A), then the pairs are canonicalised like the
 //     oracle: ascending eigenvalues, each column's largest-magnitude entry
 //     positive.  B D is also written in the sampling precision.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <vector>
 
@@ -649,9 +651,12 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
     }
     const int round_blocks = q + ntiles + (N / kS) * q;
     for (int r = 0; r < p - 1; ++r) {
-      kt_begin(kt, KID_JACOBI);
-      k_jac_round<<<round_blocks, 256, 0, st>>>(w.Acur, w.Anext, w.V, w.Qcur, w.Qnext, N, r, w.scale, w.part);
-      kt_end(kt);
+      hipEvent_t t0, t1;
+      if (kt_ext(kt, KID_JACOBI, &t0, &t1))
+        hipExtLaunchKernelGGL(k_jac_round, dim3(round_blocks), dim3(256), 0, st, t0, t1, 0, w.Acur, w.Anext, w.V,
+                              w.Qcur, w.Qnext, N, r, w.scale, w.part);
+      else
+        k_jac_round<<<round_blocks, 256, 0, st>>>(w.Acur, w.Anext, w.V, w.Qcur, w.Qnext, N, r, w.scale, w.part);
       std::swap(w.Acur, w.Anext);
       std::swap(w.Qcur, w.Qnext);
     }

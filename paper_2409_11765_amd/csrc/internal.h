@@ -66,6 +66,18 @@ inline void kt_end(KTimer* t) {
   ++t->used;
 }
 
+// Event pair for a launch that records its own start and end timestamps
+// (hipExtLaunchKernelGGL), so the measured duration is the kernel's alone,
+// without the marker packets of kt_begin / kt_end.  False when not timing.
+inline bool kt_ext(KTimer* t, int kid, hipEvent_t* start, hipEvent_t* stop) {
+  if (!t || !t->on || t->used >= KTimer::kMax) return false;
+  t->kid[t->used] = kid;
+  *start = t->ev[2 * t->used];
+  *stop = t->ev[2 * t->used + 1];
+  ++t->used;
+  return true;
+}
+
 // ---- error plumbing -------------------------------------------------------
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);

@@ -71,3 +71,9 @@ def test_gemm_tile_table_without_device():
         P.cmaes_gemm_config_info(7)
     with pytest.raises(P.CmaesError):
         P.cmaes_gemm_config_info(-1)
+
+
+def test_krep_status_layout():
+    import paper_2409_11765_amd.binding as B
+    assert ctypes.sizeof(B.KrepStatus) == 4 * 4 + 8 * 3
+    assert B.KrepStatus.lockstep_generations.offset == 16

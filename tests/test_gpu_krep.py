@@ -1,0 +1,69 @@
+"""K-Replicated strategy (Alg. 3) on one GPU: the tree of descents must merge
+finished sibling pairs into a descent of twice their population size, keep
+the number of evaluations per lockstep generation at k_max * lambda_start,
+finish at the root, be deterministic, and reach the target on the sphere."""
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_11765_amd as P
+    return P
+
+
+def test_tree_merges_and_constant_slots(P):
+    n, lam0, kmax, G = 10, 6, 4, 15
+    xs = synth.optimum(n, 3)
+    with P.KReplicated(n, lam0, kmax, 2.0, seed=9, precision="mixed", objective="sphere", xstar=xs,
+                       max_gens=G, f_target=-1.0) as r:
+        st = r.status()
+        assert st["running"] == kmax and st["finished"] == 0
+        expect = [(kmax, lam0), (kmax // 2, 2 * lam0), (1, 4 * lam0)]
+        evals = 0
+        for level, (running, lam) in enumerate(expect):
+            for g in range(G):
+                st = r.status()
+                assert st["running"] == running and st["lambda_max_running"] == lam, (level, g, st)
+                r.generation()
+                evals += running * lam
+            st = r.status()
+            assert st["total_evals"] == evals
+        assert running * lam == kmax * lam0
+        st = r.status()
+        assert st["done"] == 1 and st["running"] == 0 and st["finished"] == 2 * kmax - 1
+        assert st["lockstep_generations"] == 3 * G
+        assert st["total_evals"] == 3 * G * kmax * lam0
+        r.generation()  # no-op once done
+        assert r.status()["lockstep_generations"] == 3 * G
+
+
+def test_deterministic(P):
+    n = 12
+    R, xs = synth.problem(n, 5)
+    out = []
+    for _ in range(2):
+        with P.KReplicated(n, 0, 4, 2.0, seed=77, precision="mixed", objective="rastrigin", R=R, xstar=xs,
+                           max_gens=25, f_target=-1.0) as r:
+            r.run(40)
+            out.append(r.status())
+    assert out[0] == out[1]
+    assert np.isfinite(out[0]["f_best"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reaches_target_on_sphere(P, precision):
+    n = 10
+    xs = synth.optimum(n, 1)
+    with P.KReplicated(n, 0, 8, 2.0, seed=1, precision=precision, objective="sphere", xstar=xs) as r:
+        r.run(3000)
+        st = r.status()
+    assert st["done"] == 1 and st["f_best"] < 1e-8, st
