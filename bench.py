@@ -101,6 +101,9 @@ def parse():
                          "traffic, for scaling HBM counters)")
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the headline line: per-phase mixed-vs-FP64 table over n and K")
+    ap.add_argument("--ert", action="store_true",
+                    help="instead of the headline line: ERT / ECDF of IPOP, K-Distributed and K-Replicated on "
+                         "synthetic functions")
     ap.add_argument("--asktell", action="store_true",
                     help="instead of the headline line: host ask/tell throughput with added evaluation cost")
     ap.add_argument("--tiles", default=None, help="force tiles: sample,fitness,syrk configuration indices")
@@ -313,6 +316,98 @@ def run_asktell(P, torch, seed, n=200, lam=4864, gens=6, delays_ms=(0, 1, 10, 10
                         f"per generation", "rows": res}
 
 
+TARGETS = [1e2, 10 ** 1.5, 1e1, 10 ** 0.5, 1e0, 1e-2, 1e-4, 1e-6, 1e-8]
+
+
+def _trace_run(step, budget_s):
+    """Run `step()` (one lockstep generation, returning (total_evals, f_best,
+    finished)) until finished, the last target is hit or the budget is spent;
+    return the first (seconds, evals) at which each target was hit, and the
+    run's total (seconds, evals)."""
+    hits = [None] * len(TARGETS)
+    t0 = time.perf_counter()
+    evals, el = 0, 0.0
+    while True:
+        evals, fbest, finished = step()
+        el = time.perf_counter() - t0
+        for i, tg in enumerate(TARGETS):
+            if hits[i] is None and fbest <= tg:
+                hits[i] = (el, evals)
+        if finished or hits[-1] is not None or el > budget_s:
+            return hits, (el, evals)
+
+
+def run_ert(P, torch, seeds=(1, 2, 3), dims=(10, 40), budget_s=3.0, kmax=64, lam0=12):
+    """ERT and ECDF over the paper's nine targets (Sec. 4.3.1) for sequential
+    IPOP-CMA-ES, K-Distributed (one descent per K = 1..K_max, restart on
+    finish) and K-Replicated (Alg. 3), on the synthetic functions; f* = 0, so
+    the quality is the best f found.  Time is wall-clock seconds on one GPU."""
+    import synth
+    funcs = ["sphere", "ellipsoid", "rastrigin"]
+    levels = int(np.log2(kmax)) + 1
+    rows, ecdf_pts = [], {}
+    for n in dims:
+        for fn in funcs:
+            per_algo = {"ipop": [], "kdist": [], "krep": []}
+            for seed in seeds:
+                R, xs = synth.problem(n, seed)
+                Rm = None if fn == "sphere" else R
+                # sequential IPOP: lambda doubles at every stop until K_max
+                es = P.CMAES(n, lam0, 2.0, seed=seed, precision="mixed", objective=fn, R=Rm, xstar=xs,
+                             k_max=kmax)
+
+                def step_ipop():
+                    es.generation()
+                    st = es.state(arrays=False)
+                    done = False
+                    if st["stop"] and not st["f_best"] <= TARGETS[-1]:
+                        try:
+                            es.restart_ipop()
+                        except P.CmaesError:
+                            done = True
+                    return st["total_evals"], st["f_best"], done or st["f_best"] <= TARGETS[-1]
+                per_algo["ipop"].append(_trace_run(step_ipop, budget_s))
+                es.close()
+                # K-Distributed: all K at once, each restarting with its own lambda
+                b = P.CMAESBatch([n] * levels, [lam0 * 2 ** k for k in range(levels)], [2.0] * levels,
+                                 [seed * 100 + k for k in range(levels)], precision="mixed")
+                for k in range(levels):
+                    b.set_objective(k, fn, Rm, xs)
+
+                def step_kdist():
+                    b.generation()
+                    fbest, _ = b.best()
+                    ev = sum(b.state(k, arrays=False)["total_evals"] for k in range(levels))
+                    return ev, fbest, fbest <= TARGETS[-1]
+                per_algo["kdist"].append(_trace_run(step_kdist, budget_s))
+                b.close()
+                # K-Replicated: binary tree of descents over kmax * lam0 slots
+                r = P.KReplicated(n, lam0, kmax, 2.0, seed=seed, precision="mixed", objective=fn, R=Rm, xstar=xs)
+
+                def step_krep():
+                    r.generation()
+                    st = r.status()
+                    return st["total_evals"], st["f_best"], bool(st["done"])
+                per_algo["krep"].append(_trace_run(step_krep, budget_s))
+                r.close()
+            for algo, runs in per_algo.items():
+                for i, tg in enumerate(TARGETS):
+                    succ = [h[i] for h, _ in runs if h[i] is not None]
+                    tot_s = sum((h[i][0] if h[i] is not None else tot[0]) for h, tot in runs)
+                    tot_e = sum((h[i][1] if h[i] is not None else tot[1]) for h, tot in runs)
+                    rows.append({"n": n, "f": fn, "algo": algo, "target": tg, "successes": len(succ),
+                                 "runs": len(runs), "ert_s": tot_s / len(succ) if succ else None,
+                                 "ert_evals": tot_e / len(succ) if succ else None})
+                ecdf_pts.setdefault((n, algo), []).extend(
+                    h[i][0] if h[i] is not None else float("inf") for h, _ in runs for i in range(len(TARGETS)))
+            print(json.dumps({"n": n, "f": fn, "done": True}), file=sys.stderr, flush=True)
+    grid = [0.003, 0.01, 0.03, 0.1, 0.3, 1.0, budget_s]
+    ecdf = [{"n": n, "algo": algo, "t_s": grid,
+             "fraction": [float(np.mean(np.asarray(v) <= t)) for t in grid]} for (n, algo), v in ecdf_pts.items()]
+    return {"targets": TARGETS, "seeds": list(seeds), "budget_s": budget_s, "k_max": kmax, "lambda_start": lam0,
+            "ert": rows, "ecdf": ecdf}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -337,6 +432,9 @@ def main():
         return
     if a.asktell:
         print(json.dumps({"asktell": run_asktell(P, torch, a.seed)}), flush=True)
+        return
+    if a.ert:
+        print(json.dumps({"ert": run_ert(P, torch)}), flush=True)
         return
     tiles = [int(v) for v in a.tiles.split(",")] if a.tiles else None
     mixed = run_gpu(P, torch, n, lam, a.precision, a.steps, a.warmup, a.seed, R, xs, tune=not a.no_tune,
