@@ -234,6 +234,16 @@ __global__ void __launch_bounds__(256) k_jac_first(const double* __restrict__ A,
 // into tilepart; the rest update 32-row pieces of V with V Q_P.  MFMA operands
 // that come from A or V are loaded from global memory straight into the
 // fragment registers; only the Q's and cross-wave intermediates go through LDS.
+// Stores of the round's outputs (A_next, V) as relaxed device-scope atomic
+// stores: they are written through the XCD's L2 (cache policy sc1), so a round
+// leaves no dirty L2 lines behind and the end-of-kernel cache flush before the
+// next dependent launch has almost nothing to write back.  The values and
+// their order are those of plain stores; the next launch reads them after the
+// kernel boundary.
+__device__ __forceinline__ void store_through(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int kLU = kNB + 1;                           // row stride of the 32 x 16 stage-1 products
 constexpr int kRoundLds = 3 * kS * kLD + 3 * kS * kLU;  // doubles of LDS per workgroup
 
@@ -387,7 +397,7 @@ __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Ac
     for (int rr = 0; rr < 4; ++rr) {
       const int row = bi * kNB + lk + 4 * rr;
       const double v = m1[rr];
-      Anext[static_cast<int64_t>(gidx(I2, J2, row)) * N + gidx(I1, J1, col)] = v;
+      store_through(&Anext[static_cast<int64_t>(gidx(I2, J2, row)) * N + gidx(I1, J1, col)], v);
       tot += v * v;
       if (diag && row == col) dmax = fmax(dmax, fabs(v));
       else off += v * v;
@@ -396,7 +406,8 @@ __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Ac
       const doublex4 m2 = mfma_k32(a2, b2);
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
-        Anext[static_cast<int64_t>(gidx(I1, J1, bi * kNB + lk + 4 * rr)) * N + gidx(I2, J2, col)] = m2[rr];
+        store_through(&Anext[static_cast<int64_t>(gidx(I1, J1, bi * kNB + lk + 4 * rr)) * N + gidx(I2, J2, col)],
+                      m2[rr]);
       off *= 2.0;
       tot *= 2.0;
     }
@@ -441,7 +452,7 @@ __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Ac
   __syncthreads();
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr)
-    V[static_cast<int64_t>(gidx(I, J, bm * kNB + lk + 4 * rr)) * N + rc * kS + bn * kNB + li] = acc[rr];
+    store_through(&V[static_cast<int64_t>(gidx(I, J, bm * kNB + lk + 4 * rr)) * N + rc * kS + bn * kNB + li], acc[rr]);
 }
 
 // off-diagonal / total squared norms and max |diagonal| of A, per column
