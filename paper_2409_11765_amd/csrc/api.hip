@@ -155,7 +155,9 @@ void free_pop_buffers(cmaes* h) {
 }
 
 void drop_graphs(cmaes* h) {
-  if ((h->gx[0] || h->gx[1]) && h->st) (void)hipStreamSynchronize(h->st);  // no replay in flight
+  if ((h->gx[0] || h->gx[1] || h->ew.gx[0] || h->ew.gx[1] || h->ew.gx[2]) && h->st)
+    (void)hipStreamSynchronize(h->st);  // no replay in flight
+  eigen_drop_graphs(h->ew);
   for (int i = 0; i < 2; ++i) {
     if (h->gx[i]) (void)hipGraphExecDestroy(h->gx[i]);
     h->gx[i] = nullptr;
@@ -463,7 +465,8 @@ int eigen_advance(cmaes* h, bool* done) {
   // a decomposition that does not converge within the sweep limit (or meets
   // non-finite values) clears eig_ok on the device, which raises the
   // ConditionCov stop bit
-  return eigen_step(h->st, h->n, h->B, h->ldn, h->D, h->BD, h->fp64, h->ldn, h->ew, h->sc, 40, &h->kt, done);
+  return eigen_step(h->st, h->n, h->B, h->ldn, h->D, h->BD, h->fp64, h->ldn, h->ew, h->sc, 40, &h->kt,
+                    h->graphs && h->st != nullptr && !h->timing, done);
 }
 
 // stop tests, then fold the optional timers

@@ -647,34 +647,74 @@ __global__ void k_set_status(int* status, int code, int sweeps) {
   }
 }
 
+void eigen_drop_graphs(EigWork& w) {
+  for (auto& g : w.gx) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  w.gstream = nullptr;
+}
+
 int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, bool fp64_bd, int ldbd, EigWork& w,
-               DevScalars* sc, int max_sweeps, KTimer* kt, bool* done) {
+               DevScalars* sc, int max_sweeps, KTimer* kt, bool use_graph, bool* done) {
   *done = false;
   const int N = w.N;
   const int p = N / kNB, q = p / 2;
   const int ntiles = q * (q + 1) / 2;
   const bool more = w.hflags[0] && !w.hflags[1];
   if (more && w.sweeps < max_sweeps) {
-    if (w.sweeps == 0) {
-      kt_begin(kt, KID_JACOBI);
-      k_jac_first<<<q, 256, 0, st>>>(w.Acur, N, p, w.scale, w.Qcur);
-      kt_end(kt);
-    }
     const int round_blocks = q + ntiles + (N / kS) * q;
+    // one sweep's launches; with from_graph they are replayed from a graph
+    // captured for this starting buffer (sweeps alternate between the two A
+    // and Q buffers because a sweep has an odd number p - 1 of rounds)
+    auto queue_sweep = [&](double* a0, double* a1, double* q0, double* q1, bool first) -> hipError_t {
+      if (first) {
+        kt_begin(kt, KID_JACOBI);
+        k_jac_first<<<q, 256, 0, st>>>(a0, N, p, w.scale, q0);
+        kt_end(kt);
+      }
+      for (int r = 0; r < p - 1; ++r) {
+        hipEvent_t t0, t1;
+        if (kt_ext(kt, KID_JACOBI, &t0, &t1))
+          hipExtLaunchKernelGGL(k_jac_round, dim3(round_blocks), dim3(256), 0, st, t0, t1, 0, a0, a1, w.V, q0, q1,
+                                N, r, w.scale, w.part);
+        else
+          k_jac_round<<<round_blocks, 256, 0, st>>>(a0, a1, w.V, q0, q1, N, r, w.scale, w.part);
+        std::swap(a0, a1);
+        std::swap(q0, q1);
+      }
+      k_offnorm_final<<<1, 256, 0, st>>>(w.part, ntiles, w.flags, w.scale);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = hipMemcpyAsync(w.hflags, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+      return e;
+    };
+    const bool first = (w.sweeps == 0);
+    if (use_graph && !(kt && kt->on)) {
+      const int slot = first ? 2 : (w.Acur == w.A ? 0 : 1);
+      if (w.gx[slot] == nullptr || w.gstream != st) {
+        if (w.gstream != st) eigen_drop_graphs(w);
+        CMX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const hipError_t qe = queue_sweep(w.Acur, w.Anext, w.Qcur, w.Qnext, first);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(st, &g);
+        if (qe != hipSuccess || ce != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          return fail(-3, std::string("sweep capture: ") + hipGetErrorString(qe != hipSuccess ? qe : ce));
+        }
+        const hipError_t ie = hipGraphInstantiate(&w.gx[slot], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return fail(-3, std::string("sweep graph: ") + hipGetErrorString(ie));
+        w.gstream = st;
+      }
+      CMX_HIP(hipGraphLaunch(w.gx[slot], st));
+    } else {
+      CMX_HIP(queue_sweep(w.Acur, w.Anext, w.Qcur, w.Qnext, first));
+    }
     for (int r = 0; r < p - 1; ++r) {
-      hipEvent_t t0, t1;
-      if (kt_ext(kt, KID_JACOBI, &t0, &t1))
-        hipExtLaunchKernelGGL(k_jac_round, dim3(round_blocks), dim3(256), 0, st, t0, t1, 0, w.Acur, w.Anext, w.V,
-                              w.Qcur, w.Qnext, N, r, w.scale, w.part);
-      else
-        k_jac_round<<<round_blocks, 256, 0, st>>>(w.Acur, w.Anext, w.V, w.Qcur, w.Qnext, N, r, w.scale, w.part);
       std::swap(w.Acur, w.Anext);
       std::swap(w.Qcur, w.Qnext);
     }
     ++w.sweeps;
-    k_offnorm_final<<<1, 256, 0, st>>>(w.part, ntiles, w.flags, w.scale);
-    CMX_HIP(hipGetLastError());
-    CMX_HIP(hipMemcpyAsync(w.hflags, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     return 0;
   }
   // converged (1), sweep limit (2) or non-finite (3): finish

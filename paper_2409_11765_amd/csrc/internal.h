@@ -195,6 +195,9 @@ struct EigWork {
   double *Acur, *Anext, *Qcur, *Qnext;
   int sweeps;
   bool pending;
+  // captured sweeps: [0] starting from A, [1] from A2, [2] the first sweep
+  hipGraphExec_t gx[3];
+  hipStream_t gstream;
 };
 // Queue the warm start and the first convergence test; the host then
 // synchronises the stream and calls eigen_step until it reports done (each
@@ -203,7 +206,9 @@ int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B
 // the host-side part of eigen_begin alone (after replaying its launches from a graph)
 void eigen_begin_host(EigWork& w);
 int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, bool fp64_bd, int ldbd, EigWork& w,
-               DevScalars* sc, int max_sweeps, KTimer* kt, bool* done);
+               DevScalars* sc, int max_sweeps, KTimer* kt, bool use_graph, bool* done);
+// release the captured sweep graphs (the stream or the buffers change)
+void eigen_drop_graphs(EigWork& w);
 
 // stop tests
 hipError_t launch_stop(hipStream_t st, const KParams& kp, const StopParams& sp, const double* m,
