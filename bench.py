@@ -83,12 +83,12 @@ METRIC = "evals/s + gens/s at n=1000, λ=6144 (mixed vs FP64); % of MFMA/HBM pea
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=1000)
     ap.add_argument("--lam", type=int, default=6144)
     ap.add_argument("--precision", default="mixed")
-    ap.add_argument("--fp64-steps", type=int, default=10)
+    ap.add_argument("--fp64-steps", type=int, default=50)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
