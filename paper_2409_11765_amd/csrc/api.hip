@@ -239,7 +239,7 @@ int alloc_pop(cmaes* h) {
     int ntl, splits, kspan;
     size_t we;
     if (h->fp64)
-      syrk_plan(true, n, mu, &ntl, &splits, &kspan, &we);
+      syrk_plan_f64(n, mu, &ntl, &splits, &kspan, &we);
     else
       we = syrk32_max_work(n, mu);
     if ((rc = dev_alloc(&h->syrk_work, e * we))) return rc;
@@ -389,7 +389,8 @@ int phase_sample(cmaes* h, const double* Zhost) {
     CMX_HIP(launch_sample_gemm_bf16x3(h->st, n, lam, static_cast<const float*>(h->BD), ldn,
                                       static_cast<const float*>(h->Z), ldn, static_cast<float*>(h->Y), ldn));
   else if (h->fp64)
-    CMX_HIP(launch_sample_gemm(h->st, true, n, lam, h->BD, ldn, h->Z, ldn, h->Y, ldn));
+    CMX_HIP(launch_sample_gemm_f64(h->st, n, lam, static_cast<const double*>(h->BD), ldn,
+                                   static_cast<const double*>(h->Z), ldn, static_cast<double*>(h->Y), ldn));
   else
     CMX_HIP(g32_gemm(h->st, h->gcfg[G32_SAMPLE], G32_SAMPLE, n, lam, n, static_cast<const float*>(h->BD), ldn,
                      static_cast<const float*>(h->Z), ldn, h->Y, ldn, nullptr));
@@ -411,7 +412,8 @@ int phase_fitness(cmaes* h) {
     CMX_HIP(g32_gemm(h->st, h->gcfg[G32_FITNESS], G32_FITNESS, n, lam, n, static_cast<const float*>(h->Rt), ldn,
                      static_cast<const float*>(h->Y), ldn, h->partial, lam, &ga));
   } else if (h->have_R)
-    CMX_HIP(launch_fitness_gemm(h->st, true, n, lam, h->Rt, ldn, h->Y, ldn, fa, &tiles));
+    CMX_HIP(launch_fitness_gemm_f64(h->st, n, lam, static_cast<const double*>(h->Rt), ldn,
+                                    static_cast<const double*>(h->Y), ldn, fa, &tiles));
   else
     CMX_HIP(launch_fitness_direct(h->st, h->fp64, n, lam, h->Y, ldn, fa, &tiles));
   kt_end(&h->kt);
@@ -439,8 +441,8 @@ int phase_update_pre(cmaes* h) {
   rec(h, 4);
   kt_begin(&h->kt, KID_SYRK);
   if (h->fp64)
-    CMX_HIP(launch_syrk_update(h->st, true, n, mu, h->Ysel, ldn, h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc,
-                               h->syrk_work));
+    CMX_HIP(launch_syrk_update_f64(h->st, n, mu, static_cast<const double*>(h->Ysel), ldn, h->C, ldn, h->pc,
+                                   h->hp.kp.c1, h->hp.kp.cmu, h->sc, static_cast<double*>(h->syrk_work)));
   else
     CMX_HIP(g32_syrk(h->st, h->gcfg[G32_SYRK], n, mu, static_cast<const float*>(h->Ysel), ldn,
                      static_cast<float*>(h->syrk_work), h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc, false));

@@ -31,22 +31,12 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct Cfg;
+// float: only the direct (unrotated) fitness reduction of the mixed paths uses
+// this tile shape; their GEMMs live in the tunable float32 kernels.
 template <>
 struct Cfg<float> {
-  static constexpr int BM = 128, BN = 128, BK = 16;
-  static constexpr int MB = 32;  // MFMA block edge
-  static constexpr int KS = 2;   // MFMA k per instruction
-  static constexpr int WM = 64, WN = 64;
-  static constexpr int VEC = 4;  // elements per 16-byte load
-  static constexpr int NACC = 16;
-  static constexpr int PAD = 4;
+  static constexpr int BM = 128, BN = 128;
   using acc_t = floatx16;
-  using vec_t = float4;
-  __device__ static acc_t mfma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-  }
-  // row of accumulator element r held by lane l (column = l % 32)
-  __device__ static int acc_row(int r, int l) { return (r >> 2) * 8 + (l >> 5) * 4 + (r & 3); }
 };
 template <>
 struct Cfg<double> {
@@ -541,31 +531,17 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, const 
 
 }  // namespace
 
-hipError_t launch_sample_gemm(hipStream_t st, bool fp64, int n, int lam, const void* BD, int ldbd,
-                              const void* Z, int ldz, void* Y, int ldy) {
-  if (fp64)
-    return run_gemm<double, false, false>(st, n, lam, n, static_cast<const double*>(BD), ldbd,
-                                          static_cast<const double*>(Z), ldz,
-                                          EpiStore<double>{static_cast<double*>(Y), ldy});
-  return run_gemm<float, false, false>(st, n, lam, n, static_cast<const float*>(BD), ldbd,
-                                       static_cast<const float*>(Z), ldz,
-                                       EpiStore<float>{static_cast<float*>(Y), ldy});
+hipError_t launch_sample_gemm_f64(hipStream_t st, int n, int lam, const double* BD, int ldbd, const double* Z,
+                                  int ldz, double* Y, int ldy) {
+  return run_gemm<double, false, false>(st, n, lam, n, BD, ldbd, Z, ldz, EpiStore<double>{Y, ldy});
 }
 
-hipError_t launch_fitness_gemm(hipStream_t st, bool fp64, int n, int lam, const void* R, int ldr,
-                               const void* Y, int ldy, const FitnessArgs& fa, int* row_tiles) {
-  if (fp64) {
-    *row_tiles = ceil_div(n, Cfg<double>::BM);
-    EpiFitness<double> e{fa.kind, fa.d, static_cast<const double*>(fa.coef), fa.sc,
-                         static_cast<double*>(fa.partial), fa.ld_partial};
-    return run_gemm<double, false, false>(st, n, lam, n, static_cast<const double*>(R), ldr,
-                                          static_cast<const double*>(Y), ldy, e);
-  }
-  *row_tiles = ceil_div(n, Cfg<float>::BM);
-  EpiFitness<float> e{fa.kind, fa.d, static_cast<const float*>(fa.coef), fa.sc,
-                      static_cast<float*>(fa.partial), fa.ld_partial};
-  return run_gemm<float, false, false>(st, n, lam, n, static_cast<const float*>(R), ldr,
-                                       static_cast<const float*>(Y), ldy, e);
+hipError_t launch_fitness_gemm_f64(hipStream_t st, int n, int lam, const double* R, int ldr, const double* Y, int ldy,
+                                   const FitnessArgs& fa, int* row_tiles) {
+  *row_tiles = ceil_div(n, Cfg<double>::BM);
+  EpiFitness<double> e{fa.kind, fa.d, static_cast<const double*>(fa.coef), fa.sc,
+                       static_cast<double*>(fa.partial), fa.ld_partial};
+  return run_gemm<double, false, false>(st, n, lam, n, R, ldr, Y, ldy, e);
 }
 
 hipError_t launch_fitness_direct(hipStream_t st, bool fp64, int n, int lam, const void* Y, int ldy,
@@ -602,9 +578,9 @@ hipError_t launch_fitness_reduce(hipStream_t st, bool fp64, int kind, int n, int
   return hipGetLastError();
 }
 
-void syrk_plan(bool fp64, int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems) {
-  const int bm = fp64 ? Cfg<double>::BM : Cfg<float>::BM;
-  const int bk = Cfg<float>::BK;
+void syrk_plan_f64(int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems) {
+  const int bm = Cfg<double>::BM;
+  const int bk = Cfg<double>::BK;
   const int tm = ceil_div(n, bm);
   *ntl = tm * (tm + 1) / 2;
   int s = ceil_div(512, *ntl);
@@ -623,23 +599,13 @@ hipError_t launch_sample_gemm_bf16x3(hipStream_t st, int n, int lam, const float
   return hipGetLastError();
 }
 
-hipError_t launch_syrk_update(hipStream_t st, bool fp64, int n, int mu, const void* Ysel, int ldsel,
-                              double* C, int ldc, const double* pc, double c1, double cmu,
-                              const DevScalars* sc, void* work) {
+hipError_t launch_syrk_update_f64(hipStream_t st, int n, int mu, const double* Ysel, int ldsel, double* C, int ldc,
+                                  const double* pc, double c1, double cmu, const DevScalars* sc, double* work) {
   int ntl, splits, kspan;
   size_t we;
-  syrk_plan(fp64, n, mu, &ntl, &splits, &kspan, &we);
-  if (fp64) {
-    k_syrk_part<double><<<ntl * splits, 256, 0, st>>>(n, mu, kspan, static_cast<const double*>(Ysel), ldsel,
-                                                      static_cast<double*>(work), ntl);
-    k_syrk_epi<double><<<ntl * 16, 256, 0, st>>>(n, ntl, splits, static_cast<const double*>(work), C, ldc, pc, c1,
-                                                 cmu, sc);
-  } else {
-    k_syrk_part<float><<<ntl * splits, 256, 0, st>>>(n, mu, kspan, static_cast<const float*>(Ysel), ldsel,
-                                                     static_cast<float*>(work), ntl);
-    k_syrk_epi<float><<<ntl * 16, 256, 0, st>>>(n, ntl, splits, static_cast<const float*>(work), C, ldc, pc, c1,
-                                                cmu, sc);
-  }
+  syrk_plan_f64(n, mu, &ntl, &splits, &kspan, &we);
+  k_syrk_part<double><<<ntl * splits, 256, 0, st>>>(n, mu, kspan, Ysel, ldsel, work, ntl);
+  k_syrk_epi<double><<<ntl * 16, 256, 0, st>>>(n, ntl, splits, work, C, ldc, pc, c1, cmu, sc);
   return hipGetLastError();
 }
 

@@ -98,8 +98,9 @@ hipError_t launch_normals(hipStream_t st, void* Z, bool fp64, int ldz, int n, in
 hipError_t launch_init_mean(hipStream_t st, double* m, int n, double lo, double hi,
                             uint64_t seed, uint32_t restart);
 
-// sampling GEMM Y = BD * Z (store), fitness GEMM on R*Y (or on Y when R is
-// absent) writing per-row-tile partial sums of the objective terms.
+// FP64 path: sampling GEMM Y = BD * Z, fitness GEMM on R*Y writing per-row-tile
+// partial sums of the objective terms; without R (either precision) the
+// objective is reduced from Y directly.
 struct FitnessArgs {
   int kind;                 // cmaes_objective_t
   const double* d;          // n: R (m - x*) (or m - x*)
@@ -108,13 +109,13 @@ struct FitnessArgs {
   void* partial;            // [row_tiles][lam] partial sums, element type = T
   int ld_partial;
 };
-hipError_t launch_sample_gemm(hipStream_t st, bool fp64, int n, int lam, const void* BD, int ldbd,
-                              const void* Z, int ldz, void* Y, int ldy);
+hipError_t launch_sample_gemm_f64(hipStream_t st, int n, int lam, const double* BD, int ldbd, const double* Z,
+                                  int ldz, double* Y, int ldy);
 // y = (B D) z as bf16 x 3 split products with float32 accumulation
 hipError_t launch_sample_gemm_bf16x3(hipStream_t st, int n, int lam, const float* BD, int ldbd, const float* Z,
                                      int ldz, float* Y, int ldy);
-hipError_t launch_fitness_gemm(hipStream_t st, bool fp64, int n, int lam, const void* R, int ldr,
-                               const void* Y, int ldy, const FitnessArgs& fa, int* row_tiles);
+hipError_t launch_fitness_gemm_f64(hipStream_t st, int n, int lam, const double* R, int ldr, const double* Y, int ldy,
+                                   const FitnessArgs& fa, int* row_tiles);
 hipError_t launch_fitness_direct(hipStream_t st, bool fp64, int n, int lam, const void* Y, int ldy,
                                  const FitnessArgs& fa, int* row_tiles);
 hipError_t launch_fitness_reduce(hipStream_t st, bool fp64, int kind, int n, int lam,
@@ -138,11 +139,11 @@ hipError_t launch_best(hipStream_t st, bool fp64, int n, int lam, const double* 
                        const int32_t* order, const void* Y, int ldy, const double* m,
                        double* x_best, double* hist, int hist_len, DevScalars* sc);
 
-// covariance update C <- a C + c1 pc pc^T + cmu Ysel Ysel^T (lower tiles + mirror)
-void syrk_plan(bool fp64, int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems);
-hipError_t launch_syrk_update(hipStream_t st, bool fp64, int n, int mu, const void* Ysel, int ldsel,
-                              double* C, int ldc, const double* pc, double c1, double cmu,
-                              const DevScalars* sc, void* work);
+// FP64 path covariance update C <- a C + c1 pc pc^T + cmu Ysel Ysel^T (lower
+// tiles + mirror); the mixed paths use g32_syrk
+void syrk_plan_f64(int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems);
+hipError_t launch_syrk_update_f64(hipStream_t st, int n, int mu, const double* Ysel, int ldsel, double* C, int ldc,
+                                  const double* pc, double c1, double cmu, const DevScalars* sc, double* work);
 
 // ---- tunable float32 MFMA GEMMs (mixed precisions) -------------------------
 enum G32Site { G32_SAMPLE = 0, G32_FITNESS = 1, G32_SYRK = 2, G32_NUM_SITES = 3 };
