@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
 
 
-def kernel_work(n, lam, precision, sweeps):
+def kernel_work(n, lam, precision, sweeps, syrk_cfg=None):
     """Algorithmic work per launch of each timed kernel:
     (amount, unit, peak, bound)."""
     mu = lam // 2
@@ -39,7 +39,15 @@ def kernel_work(n, lam, precision, sweeps):
     # all of V in and out, in float64; its arithmetic intensity (~4.7 flop/B)
     # is below the float64 ridge, so it is priced against HBM
     jac = 8.0 * ((q * (q + 1) // 2) * 32 * 32 + 3 * N * N)
-    return {
+    # the mixed covariance epilogue reads each split's float32 partial of every
+    # lower 32 x 32 block (4 KiB), the lower triangle of C, and writes all of C
+    epi = None
+    if f32 and syrk_cfg is not None:
+        import paper_2409_11765_amd as P
+        _, _, splits = P.cmaes_syrk_plan(syrk_cfg, n, mu)
+        nb = (n + 31) // 32
+        epi = 4096.0 * splits * (nb * (nb + 1) // 2) + 8.0 * (n * (n + 1) // 2 + n * n)
+    work = {
         "normals": (esz * n * lam, "GB/s", PEAK["hbm_gbs"], "hbm"),
         "sample_gemm": (2.0 * n * n * lam, "TFLOP/s", mm, "mfma"),
         "fitness": (2.0 * n * n * lam, "TFLOP/s", mm, "mfma"),
@@ -48,6 +56,9 @@ def kernel_work(n, lam, precision, sweeps):
         "jacobi": (jac, "GB/s", PEAK["hbm_gbs"], "hbm"),
         "rank": (float(lam) * lam, "Gcmp/s", None, "alu"),
     }
+    if epi is not None:
+        work["syrk_epi"] = (epi, "GB/s", PEAK["hbm_gbs"], "hbm")
+    return work
 
 
 def roofline_entry(name, kt, work):
@@ -482,8 +493,9 @@ def main():
                        "gens_per_s": 1e3 / fp64["ms_per_step"], "phases_us": fp64["phases_us"]}
         out["mixed_over_fp64"] = fp64["ms_per_step"] / mixed["ms_per_step"]
     kt = mixed["kernels"]
-    work = kernel_work(n, lam, a.precision, mixed["state"]["eig_sweeps"])
-    per_kernel = {k: roofline_entry(k, kt, work) for k in kt if kt[k]["calls"]}
+    syrk_cfg = mixed["tiles"]["syrk"]["config"] if mixed["tiles"] else None
+    work = kernel_work(n, lam, a.precision, mixed["state"]["eig_sweeps"], syrk_cfg)
+    per_kernel = {k: roofline_entry(k, kt, work) for k in kt if kt[k]["calls"] and k in work}
     dom_k = max((k for k in kt if kt[k]["calls"]), key=lambda k: kt[k]["total_us"])
     roof = dict(per_kernel[dom_k])
     roof["traffic"] = measured_traffic(dom_k)

@@ -222,10 +222,12 @@ int cmaes_phase_times(const cmaes_t* h, double* out);
 #define CMAES_KERNEL_SAMPLE_GEMM 1 /* Y = B D Z                                 */
 #define CMAES_KERNEL_FITNESS 2     /* R Y with the objective epilogue           */
 #define CMAES_KERNEL_RANK 3        /* argsort of f                              */
-#define CMAES_KERNEL_SYRK 4        /* rank-mu SYRK + covariance epilogue        */
+#define CMAES_KERNEL_SYRK 4        /* rank-mu SYRK (mixed: split-k products;    */
+                                   /* float64: products + covariance epilogue)  */
 #define CMAES_KERNEL_EIG_GEMM 5    /* float64 products of the eigensolver       */
-#define CMAES_KERNEL_JACOBI 6      /* persistent block-Jacobi sweeps            */
-#define CMAES_NUM_KERNELS 7
+#define CMAES_KERNEL_JACOBI 6      /* block-Jacobi rounds of the eigensolve     */
+#define CMAES_KERNEL_SYRK_EPI 7    /* mixed: split-k sum + covariance epilogue  */
+#define CMAES_NUM_KERNELS 8
 /* Graph replay of the generation (Sec. 3.1 pipeline as one captured unit).
  * cmaes_generation (and the batch generation) queue the fixed part of a
  * generation -- sampling, fitness, ranking, recombination, paths, the
@@ -258,8 +260,9 @@ int cmaes_kernel_times(const cmaes_t* h, double* total_us, int64_t* calls);
  *   CMAES_NUM_SITES * cmaes_gemm_config_count() doubles, site-major) receives
  *   the mean microseconds per launch, -1 where not timed; chosen (NULL or
  *   CMAES_NUM_SITES) the selected configurations.  Leaves the search state
- *   untouched (the covariance site is timed without its C update); refused
- *   between ask and tell (CMAES_ESTATE).  Blocks until done.
+ *   untouched (the covariance site, split-k products plus epilogue, updates
+ *   a scratch matrix instead of C); refused between ask and tell
+ *   (CMAES_ESTATE).  Blocks until done.
  * cmaes_device_arch: the current device's architecture name (e.g. "gfx950"),
  *   NUL-terminated into buf of len bytes; the key of a tuning cache. */
 #define CMAES_SITE_SAMPLE 0
@@ -273,6 +276,13 @@ int cmaes_set_gemm_config(cmaes_t* h, int site, int cfg);
 int cmaes_get_gemm_config(const cmaes_t* h, int site, int32_t* cfg);
 int cmaes_autotune(cmaes_t* h, int reps, double* us, int32_t* chosen);
 int cmaes_device_arch(char* buf, int len);
+/* Split-k plan of the mixed-precision rank-mu SYRK (eq. (3)) with tile
+ * configuration cfg (a square one) on n x n with K = mu selected columns, host
+ * only: the lower tiles, the k-range per split (a multiple of 32) and the
+ * split count.  The products write splits * tiles * bm * bm float32 partial
+ * sums that the covariance epilogue reads back.  CMAES_EINVAL for a
+ * non-square cfg or n, K < 1. */
+int cmaes_syrk_plan(int cfg, int n, int K, int32_t* tiles, int32_t* kspan, int32_t* splits);
 
 /* ---- K-Replicated strategy (Sec. 3.2.2, Alg. 3) on one GPU ---------------
  * A binary tree of descents over one GPU's evaluation slots: k_max leaf

@@ -12,7 +12,7 @@ from .binding import (CMAES, CMAESBatch, CmaesError, CmaesOptions, KERNELS, OBJE
                       cmaes_set_options, cmaes_set_state, cmaes_state, cmaes_tell, library, LIB_PATH,
                       cmaes_batch_best, cmaes_batch_count, cmaes_batch_create, cmaes_batch_destroy,
                       cmaes_batch_generation, cmaes_batch_set_objective, cmaes_batch_set_options,
-                      cmaes_batch_state, SITES, cmaes_autotune, cmaes_device_arch, cmaes_gemm_config_count,
+                      cmaes_batch_state, SITES, cmaes_autotune, cmaes_device_arch, cmaes_syrk_plan, cmaes_gemm_config_count,
                       cmaes_gemm_config_info, cmaes_get_gemm_config, cmaes_set_gemm_config,
                       cmaes_enable_graphs, cmaes_batch_enable_graphs, KReplicated, cmaes_krep_create,
                       cmaes_krep_destroy, cmaes_krep_generation, cmaes_krep_run, cmaes_krep_set_objective,

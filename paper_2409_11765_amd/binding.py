@@ -29,7 +29,7 @@ PRECISIONS = {"fp64": CMAES_FP64, "mixed": CMAES_MIXED, "mixed_bf16x3": CMAES_MI
 STOP_BITS = ["tolhistfun", "tolfun", "tolx", "noeffectaxis", "noeffectcoord", "conditioncov",
              "ftarget", "maxgen", "maxevals", "numeric"]
 NUM_PHASES = 6
-KERNELS = ["normals", "sample_gemm", "fitness", "rank", "syrk", "eig_gemm", "jacobi"]
+KERNELS = ["normals", "sample_gemm", "fitness", "rank", "syrk", "eig_gemm", "jacobi", "syrk_epi"]
 PHASES = ["sample", "fitness", "rank", "update", "covariance", "eigen"]
 
 
@@ -99,6 +99,7 @@ def _load():
         "cmaes_get_gemm_config": (C.c_int, [H, C.c_int, _PI32]),
         "cmaes_autotune": (C.c_int, [H, C.c_int, _PD, _PI32]),
         "cmaes_device_arch": (C.c_int, [C.c_char_p, C.c_int]),
+        "cmaes_syrk_plan": (C.c_int, [C.c_int, C.c_int, C.c_int, _PI32, _PI32, _PI32]),
         "cmaes_batch_create": (H, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _PD, C.POINTER(C.c_uint64)]),
         "cmaes_batch_destroy": (None, [H]),
         "cmaes_batch_count": (C.c_int, [H]),
@@ -130,7 +131,7 @@ EXPORTED = ["cmaes_default_options", "cmaes_create", "cmaes_destroy", "cmaes_set
             "cmaes_enable_graphs", "cmaes_batch_enable_graphs",
             "cmaes_kernel_times", "cmaes_last_error", "cmaes_gemm_config_count", "cmaes_gemm_config_info",
             "cmaes_set_gemm_config", "cmaes_get_gemm_config", "cmaes_autotune", "cmaes_device_arch",
-            "cmaes_batch_create", "cmaes_batch_destroy",
+            "cmaes_syrk_plan", "cmaes_batch_create", "cmaes_batch_destroy",
             "cmaes_batch_count", "cmaes_batch_set_options", "cmaes_batch_set_objective", "cmaes_batch_generation",
             "cmaes_batch_state", "cmaes_batch_best", "cmaes_krep_create", "cmaes_krep_destroy",
             "cmaes_krep_set_options", "cmaes_krep_set_objective", "cmaes_krep_generation", "cmaes_krep_run",
@@ -340,6 +341,14 @@ def cmaes_device_arch() -> str:
     buf = C.create_string_buffer(128)
     _check(_lib.cmaes_device_arch(buf, len(buf)))
     return buf.value.decode()
+
+
+def cmaes_syrk_plan(cfg: int, n: int, K: int):
+    """(tiles, kspan, splits) of the mixed-precision split-k SYRK with tile
+    configuration cfg (host only)."""
+    t, ks, sp = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(_lib.cmaes_syrk_plan(int(cfg), int(n), int(K), C.byref(t), C.byref(ks), C.byref(sp)))
+    return t.value, ks.value, sp.value
 
 
 def _tune_key(n, lam, precision):

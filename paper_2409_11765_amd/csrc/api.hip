@@ -439,14 +439,16 @@ int phase_update_pre(cmaes* h) {
   CMX_HIP(launch_matvec(h->st, n, h->B, ldn, h->zw, h->part_bz, &nchb));
   CMX_HIP(launch_vec_update(h->st, h->hp.kp, nchb, h->part_bz, h->yw, h->m, h->ps, h->pc, h->sc));
   rec(h, 4);
-  kt_begin(&h->kt, KID_SYRK);
-  if (h->fp64)
+  if (h->fp64) {
+    kt_begin(&h->kt, KID_SYRK);
     CMX_HIP(launch_syrk_update_f64(h->st, n, mu, static_cast<const double*>(h->Ysel), ldn, h->C, ldn, h->pc,
                                    h->hp.kp.c1, h->hp.kp.cmu, h->sc, static_cast<double*>(h->syrk_work)));
-  else
+    kt_end(&h->kt);
+  } else {
     CMX_HIP(g32_syrk(h->st, h->gcfg[G32_SYRK], n, mu, static_cast<const float*>(h->Ysel), ldn,
-                     static_cast<float*>(h->syrk_work), h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc, false));
-  kt_end(&h->kt);
+                     static_cast<float*>(h->syrk_work), h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc, false,
+                     &h->kt));
+  }
   rec(h, 5);
   if (h->eig_due) return eigen_begin(h->st, n, h->C, ldn, h->B, ldn, h->ew, &h->kt);
   return 0;
@@ -1000,7 +1002,10 @@ int cmaes_autotune(cmaes_t* h, int reps, double* us, int32_t* chosen) {
     CMX_HIP(hipEventCreate(&e0));
     CMX_HIP(hipEventCreate(&e1));
     const G32FitArgs ga{h->obj_kind, h->d, static_cast<const float*>(h->coef), h->sc};
-    int rc = CMAES_OK;
+    // the covariance site is timed with its epilogue, which then updates this
+    // scratch matrix instead of C (tiles differ in how many partials it sums)
+    double* cscratch = nullptr;
+    int rc = dev_alloc(&cscratch, 8ull * ldn * n);
     for (int site = 0; site < G32_NUM_SITES && rc == CMAES_OK; ++site) {
       if (site == G32_SAMPLE && h->opt.precision == CMAES_MIXED_BF16X3) continue;
       if (site == G32_FITNESS && !(h->have_R && h->obj_kind != CMAES_OBJ_NONE)) continue;
@@ -1015,7 +1020,7 @@ int cmaes_autotune(cmaes_t* h, int reps, double* us, int32_t* chosen) {
             return g32_gemm(h->st, c, site, n, lam, n, static_cast<const float*>(h->Rt), ldn,
                             static_cast<const float*>(h->Y), ldn, h->partial, lam, &ga);
           return g32_syrk(h->st, c, n, mu, static_cast<const float*>(h->Ysel), ldn, static_cast<float*>(h->syrk_work),
-                          h->C, ldn, h->pc, 0.0, 0.0, h->sc, true);
+                          cscratch, ldn, h->pc, 0.0, 0.0, h->sc, false, nullptr);
         };
         hipError_t e = launch();  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, h->st);
@@ -1038,6 +1043,8 @@ int cmaes_autotune(cmaes_t* h, int reps, double* us, int32_t* chosen) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(h->st);
+    dev_free(cscratch);
     if (rc) return rc;
   }
   if (chosen)
@@ -1052,6 +1059,18 @@ int cmaes_device_arch(char* buf, int len) {
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess)
     return fail(CMAES_EDEVICE, "no HIP device");
   std::snprintf(buf, static_cast<size_t>(len), "%s", p.gcnArchName);
+  return CMAES_OK;
+}
+
+int cmaes_syrk_plan(int cfg, int n, int K, int32_t* tiles, int32_t* kspan, int32_t* splits) {
+  if (!g32_config_valid(cfg, G32_SYRK) || n < 1 || K < 1)
+    return fail(CMAES_EINVAL, "cfg must be a square tile configuration, n and K >= 1");
+  int ntl = 0, sp = 0, ks = 0;
+  size_t we = 0;
+  syrk32_plan(cfg, n, K, &ntl, &sp, &ks, &we);
+  if (tiles) *tiles = ntl;
+  if (kspan) *kspan = ks;
+  if (splits) *splits = sp;
   return CMAES_OK;
 }
 

@@ -31,13 +31,22 @@ __device__ __forceinline__ int xcd_swizzle(int w, int T) {
   return x * q + min(x, r) + j;
 }
 
-template <int BM, int BN, int BK, bool TB>
+// NT threads: 4 waves per k-group, KG = NT / 256 k-groups.  With KG = 2 the
+// waves 4-7 multiply the second half of every k-tile into accumulators of
+// their own (the caller folds the two groups).
+template <int BM, int BN, int BK, bool TB, int NT = 256>
 struct G32 {
-  static constexpr int LDA = BM + 4, LDB = BN + 4;
+  // B staged k-major from k-contiguous columns (!TB) is written one float per
+  // k: a row stride of BN + 2 words puts the 4 k-rows a half-wave writes on
+  // disjoint banks (BN + 4 would fold rows 0 and 2 together); float4 staging
+  // (TB, and A) needs a stride that keeps 16-byte alignment
+  static constexpr int LDA = BM + 4, LDB = TB ? BN + 4 : BN + 2;
   static constexpr int TMB = BM / 64, TNB = BN / 64;  // 32x32 blocks per wave
-  static constexpr int A_V4 = BM * BK / 4 / 256;      // float4 loads per thread
-  static constexpr int B_V4 = BN * BK / 4 / 256;
-  static_assert(A_V4 >= 1 && B_V4 >= 1, "tile too small for 256 threads");
+  static constexpr int KG = NT / 256;
+  static constexpr int A_V4 = BM * BK / 4 / NT;       // float4 loads per thread
+  static constexpr int B_V4 = BN * BK / 4 / NT;
+  static_assert(A_V4 >= 1 && B_V4 >= 1, "tile too small for the thread count");
+  static_assert(BK % (2 * KG) == 0, "k-tile must split evenly over the k-groups");
   float4 ra[A_V4], rb[B_V4];
 
   __device__ static float4 ld4(const float* __restrict__ P, int64_t off, bool full, int lim) {
@@ -53,7 +62,7 @@ struct G32 {
     constexpr int PER_COL = BM / 4;
 #pragma unroll
     for (int p = 0; p < A_V4; ++p) {
-      const int q = p * 256 + threadIdx.x;
+      const int q = p * NT + threadIdx.x;
       const int m = m0 + (q % PER_COL) * 4, k = k0 + q / PER_COL;
       const bool ok = k < K;
       ra[p] = ld4(A, static_cast<int64_t>(k) * lda + m, ok && m + 4 <= M, ok ? M - m : 0);
@@ -63,7 +72,7 @@ struct G32 {
     constexpr int PER_COL = BM / 4;
 #pragma unroll
     for (int p = 0; p < A_V4; ++p) {
-      const int q = p * 256 + threadIdx.x;
+      const int q = p * NT + threadIdx.x;
       *reinterpret_cast<float4*>(&S[(q / PER_COL) * LDA + (q % PER_COL) * 4]) = ra[p];
     }
   }
@@ -71,7 +80,7 @@ struct G32 {
   __device__ void load_b(const float* __restrict__ B, int ldb, int N, int K, int n0, int k0) {
 #pragma unroll
     for (int p = 0; p < B_V4; ++p) {
-      const int q = p * 256 + threadIdx.x;
+      const int q = p * NT + threadIdx.x;
       if constexpr (!TB) {
         constexpr int PER_ROW = BK / 4;
         const int k = k0 + (q % PER_ROW) * 4, n = n0 + q / PER_ROW;
@@ -88,7 +97,7 @@ struct G32 {
   __device__ void store_b(float* S) const {
 #pragma unroll
     for (int p = 0; p < B_V4; ++p) {
-      const int q = p * 256 + threadIdx.x;
+      const int q = p * NT + threadIdx.x;
       if constexpr (!TB) {
         constexpr int PER_ROW = BK / 4;
         const int k = (q % PER_ROW) * 4, n = q / PER_ROW;
@@ -107,7 +116,7 @@ struct G32 {
   __device__ void mainloop(int M, int N, int K, const float* __restrict__ A, int lda, const float* __restrict__ B,
                            int ldb, int m0, int n0, float* As, float* Bs, floatx16 (&acc)[TMB][TNB]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave & 1, wn = (wave >> 1) & 1, kg = wave >> 2;
 #pragma unroll
     for (int i = 0; i < TMB; ++i)
 #pragma unroll
@@ -131,7 +140,8 @@ struct G32 {
         load_b(B, ldb, N, K, n0, (kt + 1) * BK);
       }
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 2) {
+      for (int k2 = 0; k2 < BK / KG; k2 += 2) {
+        const int kk = kg * (BK / KG) + k2;
         float a[TMB], b[TNB];
 #pragma unroll
         for (int i = 0; i < TMB; ++i) a[i] = Ac[(kk + kidx) * LDA + wm * (BM / 2) + i * 32 + midx];
@@ -259,13 +269,16 @@ __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
 }
 
 // rank-mu SYRK partials: workgroup (tile t, split s) writes its lower tile's
-// partial product over k-range s into work[(s ntl + t) BM^2 ...]
-template <int BM, int BK>
-__global__ void __launch_bounds__(256) k_syrk32(int n, int K, int kspan, const float* __restrict__ Y, int ldy,
-                                                float* __restrict__ work, int ntl) {
-  using G = G32<BM, BM, BK, true>;
-  __shared__ float As[2 * BK * G::LDA];
-  __shared__ float Bs[2 * BK * G::LDB];
+// partial product over k-range s into work[(s ntl + t) BM^2 ...].  With
+// NT = 512 the two k-groups of waves are folded through LDS first, so a
+// workgroup covers twice the k-range per partial tile written.
+template <int BM, int BK, int NT>
+__global__ void __launch_bounds__(NT) k_syrk32(int n, int K, int kspan, const float* __restrict__ Y, int ldy,
+                                               float* __restrict__ work, int ntl) {
+  using G = G32<BM, BM, BK, true, NT>;
+  __shared__ float smem[2 * BK * G::LDA + 2 * BK * G::LDB];
+  float* As = smem;
+  float* Bs = smem + 2 * BK * G::LDA;
   const int item = xcd_swizzle(blockIdx.x, static_cast<int>(gridDim.x));
   const int t = item % ntl, s = item / ntl;
   int tm, tn;
@@ -275,9 +288,30 @@ __global__ void __launch_bounds__(256) k_syrk32(int n, int K, int kspan, const f
   const float* Yk = Y + static_cast<int64_t>(k0) * ldy;
   G g;
   g.mainloop(n, n, max(0, k1 - k0), Yk, ldy, Yk, ldy, tm * BM, tn * BM, As, Bs, acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if constexpr (G::KG == 2) {
+    // k-group 1 hands its sums to k-group 0 (lane-contiguous, conflict free)
+    static_assert(4 * G::TMB * G::TMB * 64 * 16 <= 2 * BK * (G::LDA + G::LDB), "fold buffer exceeds LDS");
+    const int wq = wave & 3;
+    if (wave >= 4) {
+#pragma unroll
+      for (int i = 0; i < G::TMB; ++i)
+#pragma unroll
+        for (int j = 0; j < G::TMB; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) smem[(((r * 4 + wq) * G::TMB + i) * G::TMB + j) * 64 + lane] = acc[i][j][r];
+    }
+    __syncthreads();
+    if (wave >= 4) return;
+#pragma unroll
+    for (int i = 0; i < G::TMB; ++i)
+#pragma unroll
+      for (int j = 0; j < G::TMB; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] += smem[(((r * 4 + wq) * G::TMB + i) * G::TMB + j) * 64 + lane];
+  }
   // fragment-native layout: each lane stores its 16 accumulator values
   // contiguously, so a wave writes one contiguous 4 KiB run per 32x32 block
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float* out = work + (static_cast<int64_t>(s) * ntl + t) * (BM * BM);
 #pragma unroll
   for (int i = 0; i < G::TMB; ++i)
@@ -285,46 +319,84 @@ __global__ void __launch_bounds__(256) k_syrk32(int n, int K, int kspan, const f
     for (int j = 0; j < G::TMB; ++j) {
       float4* dst = reinterpret_cast<float4*>(out + ((((wave * G::TMB + i) * G::TMB + j) * 64 + lane) << 4));
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
-        dst[g] = make_float4(acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2], acc[i][j][4 * g + 3]);
+      for (int q = 0; q < 4; ++q)
+        dst[q] = make_float4(acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]);
     }
 }
 
-// position of tile element (row, col) in the fragment-native layout above
-// (wave = wm + 2 wn owns rows wm*BM/2.., columns wn*BM/2..; lane and register
-// follow the 32x32 accumulator layout of acc_row)
-template <int BM>
-__device__ __forceinline__ int frag_index(int row, int col) {
-  constexpr int H = BM / 2, TB = BM / 64;
-  const int wave = row / H + 2 * (col / H);
-  const int i = (row % H) >> 5, j = (col % H) >> 5, rr = row & 31;
-  const int lane = ((rr >> 2) & 1) * 32 + (col & 31);
-  const int r = (rr >> 3) * 4 + (rr & 3);
-  return ((((wave * TB + i) * TB + j) * 64 + lane) << 4) + r;
-}
-
-// C <- a C + c1 pc pc^T + cmu * sum_s partial_s (lower triangle, mirrored),
-// partials summed in ascending split order
+// C <- a C + c1 pc pc^T + cmu * sum_s partial_s, one workgroup per 32 x 32
+// block (R, Q) of the lower block triangle (R >= Q, in units of 32 rows).  The
+// block is one contiguous 4 KiB run of every split's partial tile (fragment-
+// native layout above); wavefront g of the workgroup takes the 16-byte group g
+// of each lane's 16 values, so one 16-byte load per split and lane, and up to
+// eight splits are in flight at once.  Each value is summed in float64 in
+// ascending split order.  The sums pass through LDS so that both the block and
+// its mirror are written as whole columns of C.
 template <int BM>
 __global__ void __launch_bounds__(256) k_syrk32_epi(int n, int ntl, int splits, const float* __restrict__ work,
                                                     double* __restrict__ C, int ldc, const double* __restrict__ pc,
                                                     double c1, double cmu, const DevScalars* __restrict__ sc) {
-  constexpr int TILE = BM * BM;
-  const int t = blockIdx.x / 16, part = blockIdx.x % 16;
-  int tm, tn;
-  lower_tile(t, tm, tn);
+  constexpr int H = BM / 2, TB = BM / 64, PB = BM / 32;
+  constexpr int U = 8;  // splits per batch of loads
+  __shared__ double T[32 * 33];
+  int R, Q;
+  lower_tile(blockIdx.x, R, Q);
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int tm = R / PB, tn = Q / PB;
+  const int t = tm * (tm + 1) / 2 + tn;
+  const int rl = (R % PB) * 32, cl = (Q % PB) * 32;  // block origin inside its tile
+  const int wave = rl / H + 2 * (cl / H);
+  const int i = (rl % H) >> 5, j = (cl % H) >> 5;
+  const float4* src = reinterpret_cast<const float4*>(
+      work + static_cast<int64_t>(t) * (BM * BM) + ((((wave * TB + i) * TB + j) * 64 + lane) << 4)) + g;
+  const int64_t sstride = static_cast<int64_t>(ntl) * (BM * BM / 4);  // in float4
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int s = 0;
+  for (; s + U <= splits; s += U) {
+    float4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = src[(s + u) * sstride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc[0] += static_cast<double>(v[u].x);
+      acc[1] += static_cast<double>(v[u].y);
+      acc[2] += static_cast<double>(v[u].z);
+      acc[3] += static_cast<double>(v[u].w);
+    }
+  }
+  for (; s < splits; ++s) {
+    const float4 v = src[s * sstride];
+    acc[0] += static_cast<double>(v.x);
+    acc[1] += static_cast<double>(v.y);
+    acc[2] += static_cast<double>(v.z);
+    acc[3] += static_cast<double>(v.w);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) T[(lane & 31) * 33 + acc_row(4 * g + r, lane)] = acc[r];
+  __syncthreads();
   const double a = sc->c_coef;
-  for (int e = part * 256 + threadIdx.x; e < TILE; e += 16 * 256) {
-    const int rl = e % BM, cl = e / BM;
-    const int row = tm * BM + rl, col = tn * BM + cl;
-    if (row >= n || col >= n || row < col) continue;
-    const int fi = frag_index<BM>(rl, cl);
-    double acc = 0.0;
-    for (int s = 0; s < splits; ++s) acc += static_cast<double>(work[(static_cast<int64_t>(s) * ntl + t) * TILE + fi]);
-    const int64_t at = static_cast<int64_t>(col) * ldc + row;
-    const double v = a * C[at] + c1 * pc[row] * pc[col] + cmu * acc;
-    C[at] = v;
-    if (row != col) C[static_cast<int64_t>(row) * ldc + col] = v;
+  const int r0 = R * 32, q0 = Q * 32;
+  const int row = threadIdx.x & 31, sub = threadIdx.x >> 5;  // 8 columns per pass
+  // the block, column by column
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) {
+    const int col = 8 * cc + sub;
+    const int gr = r0 + row, gc = q0 + col;
+    if (gr < n && gc < n && (R != Q || row >= col)) {
+      const int64_t at = static_cast<int64_t>(gc) * ldc + gr;
+      const double v = a * C[at] + c1 * pc[gr] * pc[gc] + cmu * T[col * 33 + row];
+      C[at] = v;
+      T[col * 33 + row] = v;
+    }
+  }
+  __syncthreads();
+  // the mirror: element (row, col) of the block goes to C(q0 + col, r0 + row)
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int brow = 8 * rr + sub, bcol = threadIdx.x & 31;
+    const int gr = r0 + brow, gc = q0 + bcol;
+    if (gr < n && gc < n && (R != Q || brow > bcol))
+      C[static_cast<int64_t>(gr) * ldc + gc] = T[bcol * 33 + brow];
   }
 }
 
@@ -343,15 +415,22 @@ hipError_t launch_cfg(hipStream_t st, int site, int M, int N, int K, const float
   return hipGetLastError();
 }
 
-template <int BM, int BK>
-hipError_t launch_syrk_cfg(hipStream_t st, int n, int K, const float* Y, int ldy, float* work, double* C, int ldc,
-                           const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only) {
+template <int BM, int BK, int NT>
+hipError_t launch_syrk_cfg(hipStream_t st, int cfg, int n, int K, const float* Y, int ldy, float* work, double* C,
+                           int ldc, const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only,
+                           KTimer* kt) {
   int ntl, splits, kspan;
   size_t we;
-  syrk32_plan(BM, n, K, &ntl, &splits, &kspan, &we);
-  k_syrk32<BM, BK><<<ntl * splits, 256, 0, st>>>(n, K, kspan, Y, ldy, work, ntl);
-  if (!partial_only)
-    k_syrk32_epi<BM><<<ntl * 16, 256, 0, st>>>(n, ntl, splits, work, C, ldc, pc, c1, cmu, sc);
+  syrk32_plan(cfg, n, K, &ntl, &splits, &kspan, &we);
+  kt_begin(kt, KID_SYRK);
+  k_syrk32<BM, BK, NT><<<ntl * splits, NT, 0, st>>>(n, K, kspan, Y, ldy, work, ntl);
+  kt_end(kt);
+  if (!partial_only) {
+    const int nb = (n + 31) / 32;
+    kt_begin(kt, KID_SYRK_EPI);
+    k_syrk32_epi<BM><<<nb * (nb + 1) / 2, 256, 0, st>>>(n, ntl, splits, work, C, ldc, pc, c1, cmu, sc);
+    kt_end(kt);
+  }
   return hipGetLastError();
 }
 
@@ -362,10 +441,19 @@ const G32Config kG32Configs[kG32NumConfigs] = {
     {128, 128, 16}, {128, 64, 16}, {64, 128, 16}, {256, 128, 16}, {128, 128, 32}, {64, 64, 32}, {64, 64, 16},
 };
 
-void syrk32_plan(int bm, int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems) {
+// threads per workgroup of the SYRK products of square configuration cfg:
+// 128 x 128 x 32 runs as two k-groups of 4 waves
+int syrk32_threads(int cfg) { return cfg == 4 ? 512 : 256; }
+
+// split-k plan: at most as many workgroups as are resident at once on 256 CUs
+// (two 4-wave 128-tile workgroups, one 8-wave one, or four 64-tile ones per
+// CU), k-ranges a multiple of 32
+void syrk32_plan(int cfg, int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems) {
+  const int bm = kG32Configs[cfg].bm;
   const int tm = ceil_div(n, bm);
   *ntl = tm * (tm + 1) / 2;
-  int s = ceil_div(512, *ntl);
+  const int target = syrk32_threads(cfg) == 512 ? 256 : (bm == 64 ? 1024 : 512);
+  int s = target / *ntl;
   s = std::max(1, std::min(s, ceil_div(K, 64)));
   *kspan = round_up(ceil_div(std::max(K, 1), s), 32);
   *splits = ceil_div(std::max(K, 1), *kspan);
@@ -375,10 +463,10 @@ void syrk32_plan(int bm, int n, int K, int* ntl, int* splits, int* kspan, size_t
 size_t syrk32_max_work(int n, int K) {
   size_t best = 0;
   for (int c = 0; c < kG32NumConfigs; ++c) {
-    if (kG32Configs[c].bm != kG32Configs[c].bn) continue;
+    if (!g32_config_valid(c, G32_SYRK)) continue;
     int ntl, splits, kspan;
     size_t we;
-    syrk32_plan(kG32Configs[c].bm, n, K, &ntl, &splits, &kspan, &we);
+    syrk32_plan(c, n, K, &ntl, &splits, &kspan, &we);
     best = std::max(best, we);
   }
   return best;
@@ -407,12 +495,12 @@ hipError_t g32_gemm(hipStream_t st, int cfg, int site, int M, int N, int K, cons
 }
 
 hipError_t g32_syrk(hipStream_t st, int cfg, int n, int K, const float* Y, int ldy, float* work, double* C, int ldc,
-                    const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only) {
+                    const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only, KTimer* kt) {
   switch (cfg) {
-    case 0: return launch_syrk_cfg<128, 16>(st, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only);
-    case 4: return launch_syrk_cfg<128, 32>(st, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only);
-    case 5: return launch_syrk_cfg<64, 32>(st, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only);
-    case 6: return launch_syrk_cfg<64, 16>(st, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only);
+    case 0: return launch_syrk_cfg<128, 16, 256>(st, 0, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
+    case 4: return launch_syrk_cfg<128, 32, 512>(st, 4, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
+    case 5: return launch_syrk_cfg<64, 32, 256>(st, 5, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
+    case 6: return launch_syrk_cfg<64, 16, 256>(st, 6, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
     default: return hipErrorInvalidValue;
   }
 }

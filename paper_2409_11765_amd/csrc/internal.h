@@ -44,7 +44,7 @@ struct StopParams {
 // When enabled, begin/end events are recorded around selected launches; the
 // host folds them into per-kernel totals after the generation.
 enum KernelId { KID_NORMALS = 0, KID_SAMPLE_GEMM, KID_FITNESS, KID_RANK, KID_SYRK, KID_EIG_GEMM,
-                KID_JACOBI, KID_COUNT };
+                KID_JACOBI, KID_SYRK_EPI, KID_COUNT };
 struct KTimer {
   static constexpr int kMax = 4096;
   bool on = false;
@@ -164,12 +164,14 @@ int g32_row_tiles(int cfg, int M);
 // partial objective sums of d + sigma A*B ([row_tiles][N] floats, ld ldo)
 hipError_t g32_gemm(hipStream_t st, int cfg, int site, int M, int N, int K, const float* A, int lda, const float* B,
                     int ldb, void* out, int ldo, const G32FitArgs* fa);
-void syrk32_plan(int bm, int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems);
+void syrk32_plan(int cfg, int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems);
+int syrk32_threads(int cfg);
 size_t syrk32_max_work(int n, int K);
 // C <- a C + c1 pc pc^T + cmu Y Y^T; partial_only stops after the split-k
-// products (the tuner times that part alone, C is left untouched)
+// products (the tuner times that part alone, C is left untouched); kt (or
+// null) times the products and the epilogue as KID_SYRK and KID_SYRK_EPI
 hipError_t g32_syrk(hipStream_t st, int cfg, int n, int K, const float* Y, int ldy, float* work, double* C, int ldc,
-                    const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only);
+                    const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only, KTimer* kt);
 
 // generic FP64 GEMM: C = op(A) * op(B), column-major
 hipError_t launch_dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,

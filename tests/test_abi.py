@@ -73,6 +73,26 @@ def test_gemm_tile_table_without_device():
         P.cmaes_gemm_config_info(-1)
 
 
+def test_syrk_split_plan_without_device():
+    import paper_2409_11765_amd as P
+    # headline covariance update (n = 1000, mu = 3072): 128-tiles, two 4-wave
+    # workgroups per CU, or one 8-wave workgroup per CU for 128 x 128 x 32
+    assert P.cmaes_syrk_plan(0, 1000, 3072) == (36, 224, 14)
+    assert P.cmaes_syrk_plan(4, 1000, 3072) == (36, 448, 7)
+    for cfg in (0, 4, 5, 6):
+        bm = P.cmaes_gemm_config_info(cfg)[0]
+        for n, K in [(1, 1), (10, 5), (40, 64), (200, 4864), (1000, 3072), (2000, 2048), (97, 33)]:
+            tiles, kspan, splits = P.cmaes_syrk_plan(cfg, n, K)
+            tm = -(-n // bm)
+            assert tiles == tm * (tm + 1) // 2
+            # the splits cover [0, K) exactly once, none of them empty
+            assert kspan % 32 == 0 and splits >= 1
+            assert (splits - 1) * kspan < K <= splits * kspan
+    for bad in [(1, 100, 100), (3, 100, 100), (7, 100, 100), (0, 0, 10), (0, 10, 0)]:
+        with pytest.raises(P.CmaesError):
+            P.cmaes_syrk_plan(*bad)
+
+
 def test_krep_status_layout():
     import paper_2409_11765_amd.binding as B
     assert ctypes.sizeof(B.KrepStatus) == 4 * 4 + 8 * 3
