@@ -110,13 +110,14 @@ struct cmaes {
   double phase_us[CMAES_NUM_PHASES] = {};
   KTimer kt;
   bool eig_due = false;
+  bool reorth_due = false;  // the eigen step starts by re-orthogonalising B
   int gcfg[G32_NUM_SITES] = {0, 0, 0};  // float32 GEMM tile per call site
   // captured front of a generation (sampling .. eigensolve set-up), one per
-  // value of eig_due, valid while gkey matches (see front_key)
+  // (eig_due, reorth_due) case, valid while gkey matches (see front_key)
   bool graphs = true;
   uint64_t epoch = 1;
-  hipGraphExec_t gx[2] = {nullptr, nullptr};
-  uint64_t gkey[2] = {0, 0};
+  hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
+  uint64_t gkey[3] = {0, 0, 0};
 
   // float64 state
   DevScalars* sc = nullptr;
@@ -155,10 +156,10 @@ void free_pop_buffers(cmaes* h) {
 }
 
 void drop_graphs(cmaes* h) {
-  if ((h->gx[0] || h->gx[1] || h->ew.gx[0] || h->ew.gx[1] || h->ew.gx[2]) && h->st)
+  if ((h->gx[0] || h->gx[1] || h->gx[2] || h->ew.gx[0] || h->ew.gx[1] || h->ew.gx[2]) && h->st)
     (void)hipStreamSynchronize(h->st);  // no replay in flight
   eigen_drop_graphs(h->ew);
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < 3; ++i) {
     if (h->gx[i]) (void)hipGraphExecDestroy(h->gx[i]);
     h->gx[i] = nullptr;
     h->gkey[i] = 0;
@@ -450,13 +451,31 @@ int phase_update_pre(cmaes* h) {
                      &h->kt));
   }
   rec(h, 5);
-  if (h->eig_due) return eigen_begin(h->st, n, h->C, ldn, h->B, ldn, h->ew, &h->kt);
-  return 0;
+  if (!h->eig_due) return 0;
+  if (h->reorth_due) {
+    // B drifts from orthogonality by the rounding of each eigensolve's
+    // rotations (B = B_old V); one Newton-Schulz step B <- B (3 I - B^T B) / 2
+    // removes the accumulated drift (to second order) before the warm start
+    kt_begin(&h->kt, KID_EIG_GEMM);
+    CMX_HIP(launch_dgemm(h->st, true, false, n, n, n, h->B, ldn, h->B, ldn, h->ew.A2, h->ew.N));  // G = B^T B
+    kt_end(&h->kt);
+    kt_begin(&h->kt, KID_EIG_GEMM);
+    CMX_HIP(launch_dgemm(h->st, false, false, n, n, n, h->B, ldn, h->ew.A2, h->ew.N, h->ew.T, ldn));  // T = B G
+    kt_end(&h->kt);
+    CMX_HIP(launch_polar_step(h->st, n, h->B, ldn, h->ew.T, ldn));
+  }
+  return eigen_begin(h->st, n, h->C, ldn, h->B, ldn, h->ew, &h->kt);
 }
 
-// host-side counters of the generation just queued; eig_due must be set
-// (due_next) before its launches are queued
+// host-side counters of the generation just queued; eig_due and reorth_due
+// must be set (set_due) before its launches are queued
 bool due_next(const cmaes* h) { return (h->gen + 1) % h->hp.kp.kappa == 0; }
+// every kReorthEvery-th eigendecomposition of a descent re-orthogonalises B
+constexpr int kReorthEvery = 8;
+void set_due(cmaes* h) {
+  h->eig_due = due_next(h);
+  h->reorth_due = h->eig_due && ((h->gen + 1) / h->hp.kp.kappa) % kReorthEvery == 0;
+}
 void advance_counters(cmaes* h) {
   h->gen += 1;
   h->evals += h->lam;
@@ -500,7 +519,7 @@ int phase_update_post(cmaes* h) {
 }
 
 int phase_update(cmaes* h) {
-  h->eig_due = due_next(h);
+  set_due(h);
   if (int rc = phase_update_pre(h)) return rc;
   advance_counters(h);
   if (h->eig_due) {
@@ -529,13 +548,14 @@ uint64_t front_key(const cmaes* h, bool due) {
   mix(static_cast<uint64_t>(h->opt.precision));
   for (int i = 0; i < G32_NUM_SITES; ++i) mix(static_cast<uint64_t>(h->gcfg[i]));
   mix(due ? 1u : 0u);
+  mix(h->reorth_due ? 1u : 0u);
   return k | 1u;  // never 0 (0 marks an empty slot)
 }
 
 // the launches of a generation up to the eigensolve set-up, eagerly or by
 // replaying a captured graph; then the host counters
 int front(cmaes* h) {
-  h->eig_due = due_next(h);
+  set_due(h);
   const bool can_graph = h->graphs && h->st != nullptr && !h->timing && !h->kt.on;
   if (!can_graph) {
     if (int rc = phase_sample(h, nullptr)) return rc;
@@ -544,7 +564,7 @@ int front(cmaes* h) {
     advance_counters(h);
     return 0;
   }
-  const int slot = h->eig_due ? 1 : 0;
+  const int slot = h->eig_due ? (h->reorth_due ? 2 : 1) : 0;
   const uint64_t key = front_key(h, h->eig_due);
   if (h->gx[slot] == nullptr || h->gkey[slot] != key) {
     if (h->gx[slot]) (void)hipGraphExecDestroy(h->gx[slot]);

@@ -219,6 +219,8 @@ hipError_t launch_stop(hipStream_t st, const KParams& kp, const StopParams& sp, 
                        const double* pc, const double* hist, DevScalars* sc);
 
 // misc
+// B <- (3 B - T) / 2 with T = B (B^T B) (Newton-Schulz step, rows < n)
+hipError_t launch_polar_step(hipStream_t st, int n, double* B, int ldb, const double* T, int ldt);
 hipError_t launch_set_identity(hipStream_t st, double* A, int n, int ld);
 hipError_t launch_to_precision(hipStream_t st, bool fp64, const double* src, int ld_src, void* dst,
                                int ld_dst, int rows, int cols);

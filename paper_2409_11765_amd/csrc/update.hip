@@ -371,6 +371,23 @@ hipError_t launch_shift(hipStream_t st, int n, const double* R, int ldr, const d
   return hipGetLastError();
 }
 
+// B <- (3 B - B (B^T B)) / 2 from T = B (B^T B): one Newton-Schulz step
+// towards the orthogonal polar factor of B (rows < n only)
+__global__ void k_polar_step(int n, double* __restrict__ B, int ldb, const double* __restrict__ T, int ldt) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t total = static_cast<int64_t>(n) * n;
+  if (idx >= total) return;
+  const int col = static_cast<int>(idx / n), row = static_cast<int>(idx % n);
+  double& b = B[static_cast<int64_t>(col) * ldb + row];
+  b = 1.5 * b - 0.5 * T[static_cast<int64_t>(col) * ldt + row];
+}
+
+hipError_t launch_polar_step(hipStream_t st, int n, double* B, int ldb, const double* T, int ldt) {
+  const int64_t total = static_cast<int64_t>(n) * n;
+  k_polar_step<<<static_cast<int>((total + 255) / 256), 256, 0, st>>>(n, B, ldb, T, ldt);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_identity(hipStream_t st, double* A, int n, int ld) {
   const int64_t total = static_cast<int64_t>(n) * ld;
   k_set_identity<<<static_cast<int>((total + 255) / 256), 256, 0, st>>>(A, n, ld);

@@ -116,6 +116,25 @@ def test_eigen_cold_start_from_identity(P):
     assert np.max(np.abs(B.T @ B - np.eye(n))) <= 1e-12
 
 
+@pytest.mark.parametrize("n,lam,precision", [(1000, 2048, "mixed"), (400, 800, "fp64")])
+def test_eigenvectors_stay_orthonormal_over_a_long_run(P, n, lam, precision):
+    """B is carried from one warm-started eigensolve to the next (B = B_old V),
+    so rounding in the rotations accumulates unless B is re-orthogonalised;
+    after 103 generations (7 since the last re-orthogonalisation) C = B D^2 B^T
+    and B^T B = I must still hold to 1e-12."""
+    R, xs = synth.problem(n, seed=1)
+    print(f"case long run n={n} lam={lam} {precision}", flush=True)
+    with P.CMAES(n, lam, 2.0, seed=1, precision=precision, objective="rastrigin", R=R, xstar=xs,
+                 eigen_interval=1) as es:
+        for _ in range(103):
+            es.generation()
+        s = es.state()
+    C, B, D = s["C"], s["B"], s["D"]
+    assert s["stop"] == 0
+    assert np.linalg.norm(B @ np.diag(D ** 2) @ B.T - C) <= 1e-12 * np.linalg.norm(C)
+    assert np.max(np.abs(B.T @ B - np.eye(n))) <= 1e-12
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_run_is_bitwise_deterministic(P, precision):
     outs = []
