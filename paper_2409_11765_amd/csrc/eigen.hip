@@ -526,25 +526,32 @@ __global__ void k_identity(double* __restrict__ V, int N) {
 }
 
 // eigenvalue ranks (ascending, ties by index) and positive-definiteness flag;
-// the diagonal is staged through LDS in chunks
+// the diagonal is staged through LDS in chunks, kRankTPI threads count for one
+// eigenvalue (every kRankTPI-th entry each) and sum their integer counts
+constexpr int kRankTPI = 8;
 __global__ void __launch_bounds__(256) k_eig_rank(const double* __restrict__ A, int N, int n,
                                                   int32_t* __restrict__ perm, double* __restrict__ ev,
                                                   const int* __restrict__ status, DevScalars* __restrict__ sc) {
   __shared__ double dg[1024];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x % kRankTPI;
+  const int i = blockIdx.x * (256 / kRankTPI) + threadIdx.x / kRankTPI;
   const double vi = i < n ? A[static_cast<int64_t>(i) * N + i] : 0.0;
   int cnt = 0;
   for (int base = 0; base < n; base += 1024) {
     const int lim = min(1024, n - base);
     for (int j = threadIdx.x; j < lim; j += 256) dg[j] = A[static_cast<int64_t>(base + j) * N + base + j];
     __syncthreads();
-    for (int j = 0; j < lim; ++j) {
+#pragma unroll 8
+    for (int j = sub; j < lim; j += kRankTPI) {
       const double vj = dg[j];
       cnt += (vj < vi) || (vj == vi && base + j < i);
     }
     __syncthreads();
   }
-  if (i >= n) return;
+  // the kRankTPI counts of eigenvalue i sit in consecutive, aligned lanes
+#pragma unroll
+  for (int o = kRankTPI / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+  if (i >= n || sub != 0) return;
   perm[cnt] = i;
   ev[i] = vi;
   if (cnt == 0) {
@@ -723,7 +730,7 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
   kt_begin(kt, KID_EIG_GEMM);
   CMX_HIP(launch_dgemm(st, false, false, n, n, n, B, ldb, w.V, N, w.T, ldb));
   kt_end(kt);
-  k_eig_rank<<<ceil_div(n, 256), 256, 0, st>>>(w.Acur, N, n, w.perm, w.evals, w.status, sc);
+  k_eig_rank<<<ceil_div(n, 256 / kRankTPI), 256, 0, st>>>(w.Acur, N, n, w.perm, w.evals, w.status, sc);
   k_colsign<<<n, 256, 0, st>>>(w.T, ldb, n, w.sign);
   dim3 grid(ceil_div(n, 256), n);
   if (fp64_bd)
