@@ -199,10 +199,10 @@ void free_all(cmaes* h) {
   dev_free(h->ew.sign);
   dev_free(h->ew.part);
   dev_free(h->ew.scale);
-  dev_free(h->ew.flags);
   dev_free(h->ew.status);
   if (h->ew.hflags) (void)hipHostFree(h->ew.hflags);
   h->ew.hflags = nullptr;
+  h->ew.dflags = nullptr;
   h->allocated = false;
 }
 
@@ -272,15 +272,21 @@ int alloc_fixed(cmaes* h) {
       (rc = dev_alloc(&h->ew.A2, 8ull * N * N)) || (rc = dev_alloc(&h->ew.Q2, 8ull * (N / 32) * 32 * 32)) ||
       (rc = dev_alloc(&h->ew.evals, 8ull * N)) || (rc = dev_alloc(&h->ew.perm, 4ull * N)) ||
       (rc = dev_alloc(&h->ew.sign, 8ull * N)) || (rc = dev_alloc(&h->ew.scale, 16)) ||
-      (rc = dev_alloc(&h->ew.flags, 16)) || (rc = dev_alloc(&h->ew.status, 16)))
+      (rc = dev_alloc(&h->ew.status, 16)))
     return rc;
   {
     const int q = N / 32;
     if ((rc = dev_alloc(&h->ew.part, 8ull * 3 * std::max(n, q * (q + 1) / 2)))) return rc;
   }
+  // convergence flags: pinned, mapped host memory the device writes directly
   void* hf = nullptr;
-  if (hipHostMalloc(&hf, 16, hipHostMallocDefault) != hipSuccess) return fail(CMAES_ENOMEM, "hipHostMalloc failed");
+  if (hipHostMalloc(&hf, 16, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+    return fail(CMAES_ENOMEM, "hipHostMalloc failed");
   h->ew.hflags = static_cast<int*>(hf);
+  h->ew.hflags[0] = h->ew.hflags[1] = 0;
+  void* dp = nullptr;
+  if (hipHostGetDevicePointer(&dp, hf, 0) != hipSuccess) return fail(CMAES_EDEVICE, "hipHostGetDevicePointer failed");
+  h->ew.dflags = static_cast<int*>(dp);
   return 0;
 }
 

@@ -484,7 +484,10 @@ __global__ void __launch_bounds__(256) k_offnorm_cols(const double* __restrict__
 }
 
 // reduce count (off, tot, dmax) triples in a fixed order: flags[0] = 1 if more
-// sweeps are needed, flags[1] = 1 if non-finite; scale[0] = max |a_ii|
+// sweeps are needed, flags[1] = 1 if non-finite; scale[0] = max |a_ii|.
+// flags is the device address of pinned host memory: the host reads it once
+// the stream has drained, so the stores are system-scope (written through to
+// host memory) and no copy is queued for them.
 __global__ void __launch_bounds__(256) k_offnorm_final(const double* __restrict__ part, int count,
                                                        int* __restrict__ flags, double* __restrict__ scale) {
   __shared__ double red[3][256];
@@ -509,8 +512,9 @@ __global__ void __launch_bounds__(256) k_offnorm_final(const double* __restrict_
   }
   if (t == 0) {
     const bool finite = isfinite(red[1][0]);
-    flags[0] = (finite && red[0][0] > kOffTol * kOffTol * red[1][0]) ? 1 : 0;
-    flags[1] = finite ? 0 : 1;
+    __hip_atomic_store(&flags[0], (finite && red[0][0] > kOffTol * kOffTol * red[1][0]) ? 1 : 0, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&flags[1], finite ? 0 : 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     scale[0] = red[2][0];
   }
 }
@@ -640,9 +644,8 @@ int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B
   CMX_HIP(launch_dgemm(st, true, false, n, n, n, B, ldb, w.T, ldb, w.Acur, N));   // A = B^T T
   kt_end(kt);
   k_offnorm_cols<<<n, 256, 0, st>>>(w.Acur, N, n, w.part);
-  k_offnorm_final<<<1, 256, 0, st>>>(w.part, n, w.flags, w.scale);
+  k_offnorm_final<<<1, 256, 0, st>>>(w.part, n, w.dflags, w.scale);
   CMX_HIP(hipGetLastError());
-  CMX_HIP(hipMemcpyAsync(w.hflags, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   w.pending = true;
   return 0;
 }
@@ -690,10 +693,8 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
         std::swap(a0, a1);
         std::swap(q0, q1);
       }
-      k_offnorm_final<<<1, 256, 0, st>>>(w.part, ntiles, w.flags, w.scale);
-      hipError_t e = hipGetLastError();
-      if (e == hipSuccess) e = hipMemcpyAsync(w.hflags, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
-      return e;
+      k_offnorm_final<<<1, 256, 0, st>>>(w.part, ntiles, w.dflags, w.scale);
+      return hipGetLastError();
     };
     const bool first = (w.sweeps == 0);
     if (use_graph && !(kt && kt->on)) {

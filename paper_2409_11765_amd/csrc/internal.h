@@ -191,9 +191,9 @@ struct EigWork {
   double* sign;   // N
   double* part;   // 3 * max(n, tiles) partial sums
   double* scale;  // max |a_ii|
-  int* flags;     // [0] more sweeps needed, [1] non-finite
   int* status;    // [0] 1 converged, 2 sweep limit, 3 non-finite; [1] sweeps
-  int* hflags;    // pinned host copy of flags
+  int* hflags;    // pinned host memory: [0] more sweeps needed, [1] non-finite
+  int* dflags;    // device address of hflags (written by the convergence test)
   // progress of the eigensolve in flight
   double *Acur, *Anext, *Qcur, *Qnext;
   int sweeps;
