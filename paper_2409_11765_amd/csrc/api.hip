@@ -111,6 +111,8 @@ struct cmaes {
   KTimer kt;
   bool eig_due = false;
   bool reorth_due = false;  // the eigen step starts by re-orthogonalising B
+  int reorth_sweeps = 0;    // Jacobi sweeps applied to B since it was last orthogonal
+  bool eig_uncounted = false;  // the last eigensolve's sweeps are not yet in reorth_sweeps
   int gcfg[G32_NUM_SITES] = {0, 0, 0};  // float32 GEMM tile per call site
   // captured front of a generation (sampling .. eigensolve set-up), one per
   // (eig_due, reorth_due) case, valid while gkey matches (see front_key)
@@ -350,6 +352,8 @@ int init_descent(cmaes* h, bool fresh) {
   h->gen = 0;
   h->evals = 0;
   h->ask_pending = false;
+  h->reorth_sweeps = 0;  // B = I
+  h->eig_uncounted = false;
   refresh_stop_params(h);
   return 0;
 }
@@ -476,11 +480,19 @@ int phase_update_pre(cmaes* h) {
 // host-side counters of the generation just queued; eig_due and reorth_due
 // must be set (set_due) before its launches are queued
 bool due_next(const cmaes* h) { return (h->gen + 1) % h->hp.kp.kappa == 0; }
-// every kReorthEvery-th eigendecomposition of a descent re-orthogonalises B
-constexpr int kReorthEvery = 8;
+// B's drift from orthogonality grows with the rotation sweeps applied to it
+// (B = B_old V per eigensolve): an eigen step re-orthogonalises B first once
+// kReorthSweeps sweeps have accumulated since B was last orthogonal
+constexpr int kReorthSweeps = 48;
 void set_due(cmaes* h) {
+  if (h->eig_uncounted) {  // the previous generation's eigensolve has finished
+    h->reorth_sweeps += h->ew.sweeps;
+    h->eig_uncounted = false;
+  }
   h->eig_due = due_next(h);
-  h->reorth_due = h->eig_due && ((h->gen + 1) / h->hp.kp.kappa) % kReorthEvery == 0;
+  h->reorth_due = h->eig_due && h->reorth_sweeps >= kReorthSweeps;
+  if (h->reorth_due) h->reorth_sweeps = 0;
+  if (h->eig_due) h->eig_uncounted = true;
 }
 void advance_counters(cmaes* h) {
   h->gen += 1;
@@ -924,7 +936,11 @@ int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in) {
   if (in->p_c) CMX_HIP(hipMemcpy(h->pc, in->p_c, 8ull * n, hipMemcpyHostToDevice));
   if (in->D) CMX_HIP(hipMemcpy(h->D, in->D, 8ull * n, hipMemcpyHostToDevice));
   if (in->C) CMX_HIP(hipMemcpy2D(h->C, 8ull * ldn, in->C, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
-  if (in->B) CMX_HIP(hipMemcpy2D(h->B, 8ull * ldn, in->B, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
+  if (in->B) {
+    CMX_HIP(hipMemcpy2D(h->B, 8ull * ldn, in->B, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
+    h->reorth_sweeps = 0;  // taken as orthogonal
+    h->eig_uncounted = false;
+  }
   if (in->B || in->D) {
     // B D in the sampling precision
     std::vector<double> Bh(static_cast<size_t>(n) * n), Dh(n);
