@@ -354,6 +354,7 @@ int init_descent(cmaes* h, bool fresh) {
   h->ask_pending = false;
   h->reorth_sweeps = 0;  // B = I
   h->eig_uncounted = false;
+  h->ew.last_sweeps = 0;
   refresh_stop_params(h);
   return 0;
 }
@@ -940,6 +941,7 @@ int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in) {
     CMX_HIP(hipMemcpy2D(h->B, 8ull * ldn, in->B, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
     h->reorth_sweeps = 0;  // taken as orthogonal
     h->eig_uncounted = false;
+    h->ew.last_sweeps = 0;
   }
   if (in->B || in->D) {
     // B D in the sampling precision

@@ -696,33 +696,39 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
       k_offnorm_final<<<1, 256, 0, st>>>(w.part, ntiles, w.dflags, w.scale);
       return hipGetLastError();
     };
-    const bool first = (w.sweeps == 0);
-    if (use_graph && !(kt && kt->on)) {
-      const int slot = first ? 2 : (w.Acur == w.A ? 0 : 1);
-      if (w.gx[slot] == nullptr || w.gstream != st) {
-        if (w.gstream != st) eigen_drop_graphs(w);
-        CMX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        const hipError_t qe = queue_sweep(w.Acur, w.Anext, w.Qcur, w.Qnext, first);
-        hipGraph_t g = nullptr;
-        const hipError_t ce = hipStreamEndCapture(st, &g);
-        if (qe != hipSuccess || ce != hipSuccess) {
-          if (g) (void)hipGraphDestroy(g);
-          return fail(-3, std::string("sweep capture: ") + hipGetErrorString(qe != hipSuccess ? qe : ce));
+    // the first check queues (previous solve's sweep count - 1) sweeps at
+    // once: a warm-started solve rarely needs fewer, and while it needs at
+    // least as many the sweeps run are those of a check after every sweep
+    const int batch = w.sweeps == 0 ? std::max(1, std::min(w.last_sweeps - 1, max_sweeps)) : 1;
+    for (int i = 0; i < batch; ++i) {
+      const bool first = (w.sweeps == 0);
+      if (use_graph && !(kt && kt->on)) {
+        const int slot = first ? 2 : (w.Acur == w.A ? 0 : 1);
+        if (w.gx[slot] == nullptr || w.gstream != st) {
+          if (w.gstream != st) eigen_drop_graphs(w);
+          CMX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          const hipError_t qe = queue_sweep(w.Acur, w.Anext, w.Qcur, w.Qnext, first);
+          hipGraph_t g = nullptr;
+          const hipError_t ce = hipStreamEndCapture(st, &g);
+          if (qe != hipSuccess || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(-3, std::string("sweep capture: ") + hipGetErrorString(qe != hipSuccess ? qe : ce));
+          }
+          const hipError_t ie = hipGraphInstantiate(&w.gx[slot], g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          if (ie != hipSuccess) return fail(-3, std::string("sweep graph: ") + hipGetErrorString(ie));
+          w.gstream = st;
         }
-        const hipError_t ie = hipGraphInstantiate(&w.gx[slot], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) return fail(-3, std::string("sweep graph: ") + hipGetErrorString(ie));
-        w.gstream = st;
+        CMX_HIP(hipGraphLaunch(w.gx[slot], st));
+      } else {
+        CMX_HIP(queue_sweep(w.Acur, w.Anext, w.Qcur, w.Qnext, first));
       }
-      CMX_HIP(hipGraphLaunch(w.gx[slot], st));
-    } else {
-      CMX_HIP(queue_sweep(w.Acur, w.Anext, w.Qcur, w.Qnext, first));
+      for (int r = 0; r < p - 1; ++r) {
+        std::swap(w.Acur, w.Anext);
+        std::swap(w.Qcur, w.Qnext);
+      }
+      ++w.sweeps;
     }
-    for (int r = 0; r < p - 1; ++r) {
-      std::swap(w.Acur, w.Anext);
-      std::swap(w.Qcur, w.Qnext);
-    }
-    ++w.sweeps;
     return 0;
   }
   // converged (1), sweep limit (2) or non-finite (3): finish
@@ -742,6 +748,7 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
                                            static_cast<float*>(BD), ldbd);
   CMX_HIP(hipGetLastError());
   w.pending = false;
+  w.last_sweeps = w.sweeps;
   *done = true;
   return 0;
 }

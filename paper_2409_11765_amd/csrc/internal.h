@@ -197,6 +197,7 @@ struct EigWork {
   // progress of the eigensolve in flight
   double *Acur, *Anext, *Qcur, *Qnext;
   int sweeps;
+  int last_sweeps;  // sweeps of the previous solve (0: none, or B replaced)
   bool pending;
   // captured sweeps: [0] starting from A, [1] from A2, [2] the first sweep
   hipGraphExec_t gx[3];
