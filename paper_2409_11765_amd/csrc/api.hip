@@ -128,6 +128,7 @@ struct cmaes {
   double *xstar = nullptr, *Rd = nullptr, *yw = nullptr, *zw = nullptr;
   double *part_yw = nullptr, *part_zw = nullptr, *part_bz = nullptr, *f = nullptr, *X = nullptr;
   int32_t* order = nullptr;
+  int32_t* rank_work = nullptr;  // partial rank counts
   // sampling-precision buffers
   void *BD = nullptr, *Rt = nullptr, *Z = nullptr, *Y = nullptr, *Ysel = nullptr, *coef = nullptr;
   void* partial = nullptr;
@@ -150,6 +151,7 @@ void free_pop_buffers(cmaes* h) {
   dev_free(h->f);
   dev_free(h->X);
   dev_free(h->order);
+  dev_free(h->rank_work);
   dev_free(h->w);
   dev_free(h->sqrtw);
   dev_free(h->hist);
@@ -235,7 +237,8 @@ int alloc_pop(cmaes* h) {
       (rc = dev_alloc(&h->Ysel, e * ldn * mu)) || (rc = dev_alloc(&h->partial, 8ull * row_tiles * lam)) ||
       (rc = dev_alloc(&h->part_yw, 8ull * ceil_div(mu, 64) * n)) ||
       (rc = dev_alloc(&h->part_zw, 8ull * ceil_div(mu, 64) * n)) || (rc = dev_alloc(&h->f, 8ull * lam)) ||
-      (rc = dev_alloc(&h->order, 4ull * 2 * lam)) || (rc = dev_alloc(&h->w, 8ull * mu)) ||
+      (rc = dev_alloc(&h->order, 4ull * lam)) || (rc = dev_alloc(&h->rank_work, 4ull * rank_work_elems(lam))) ||
+      (rc = dev_alloc(&h->w, 8ull * mu)) ||
       (rc = dev_alloc(&h->sqrtw, 8ull * mu)) || (rc = dev_alloc(&h->hist, 8ull * hist_len_for(n, lam))))
     return rc;
   {
@@ -440,7 +443,7 @@ int phase_update_pre(cmaes* h) {
   const int n = h->n, lam = h->lam, ldn = h->ldn, mu = h->hp.kp.mu;
   rec(h, 2);
   kt_begin(&h->kt, KID_RANK);
-  CMX_HIP(launch_rank(h->st, h->f, lam, h->order));
+  CMX_HIP(launch_rank(h->st, h->f, lam, h->order, h->rank_work));
   kt_end(&h->kt);
   CMX_HIP(launch_best(h->st, h->fp64, n, lam, h->f, h->order, h->Y, ldn, h->m, h->x_best, h->hist, h->sp.hist_len, h->sc));
   rec(h, 3);

@@ -122,7 +122,9 @@ hipError_t launch_fitness_reduce(hipStream_t st, bool fp64, int kind, int n, int
                                  const void* partial, int ld_partial, int row_tiles, double* f);
 
 // ranking
-hipError_t launch_rank(hipStream_t st, const double* f, int lam, int32_t* order);
+// order[r] = index of rank r; work holds rank_work_elems(lam) int32 partial counts
+hipError_t launch_rank(hipStream_t st, const double* f, int lam, int32_t* order, int32_t* work);
+size_t rank_work_elems(int lam);
 
 // recombination and vector updates
 hipError_t launch_recombine(hipStream_t st, bool fp64, int n, int lam, int mu, const void* Y,

@@ -18,39 +18,55 @@ __device__ __forceinline__ double rank_key(double v) { return v != v ? __builtin
 // Rank by counting: rank(i) = #{ j : f_j < f_i or (f_j == f_i and j < i) },
 // NaN counted as +inf.  Keys (f, index) are distinct, so the ranks form a
 // permutation and the result is the stable ascending order.  The j range is
-// split over blockIdx.y; partial counts are summed with integer atomics
-// (order independent, hence deterministic).
+// split over blockIdx.y (span values each, staged through LDS kRankChunk at a
+// time); each thread counts for kRankPer candidates per value read and writes
+// its partial count to part[y][i] (summed by k_scatter_order; integers, so
+// the sum is order independent).
+constexpr int kRankChunk = 128, kRankPer = 4, kRankMaxSplits = 64;
 __global__ void __launch_bounds__(256) k_rank_count(const double* __restrict__ f, int lam, int span,
-                                                    int32_t* __restrict__ rank) {
-  __shared__ double sf[256];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const double fi = i < lam ? rank_key(f[i]) : 0.0;
-  const int j0 = blockIdx.y * span, j1 = min(lam, j0 + span);
-  int cnt = 0;
-  for (int base = j0; base < j1; base += 256) {
-    const int j = base + threadIdx.x;
-    sf[threadIdx.x] = j < j1 ? rank_key(f[j]) : 0.0;
-    __syncthreads();
-    const int lim = min(256, j1 - base);
-    for (int q = 0; q < lim; ++q) {
-      const double fj = sf[q];
-      cnt += (fj < fi) || (fj == fi && base + q < i);
-    }
-    __syncthreads();
+                                                    int32_t* __restrict__ part) {
+  __shared__ double sf[kRankChunk];
+  int idx[kRankPer], cnt[kRankPer];
+  double fi[kRankPer];
+#pragma unroll
+  for (int r = 0; r < kRankPer; ++r) {
+    idx[r] = (blockIdx.x * kRankPer + r) * 256 + threadIdx.x;
+    fi[r] = idx[r] < lam ? rank_key(f[idx[r]]) : 0.0;
+    cnt[r] = 0;
   }
-  if (i < lam && cnt) atomicAdd(&rank[i], cnt);
+  const int j1 = min(lam, (blockIdx.y + 1) * span);
+  for (int j0 = blockIdx.y * span; j0 < j1; j0 += kRankChunk) {
+    const int lim = min(kRankChunk, j1 - j0);
+    __syncthreads();
+    if (threadIdx.x < lim) sf[threadIdx.x] = rank_key(f[j0 + threadIdx.x]);
+    __syncthreads();
+    if (lim == kRankChunk) {
+#pragma unroll 8
+      for (int q = 0; q < kRankChunk; ++q) {
+        const double fj = sf[q];
+#pragma unroll
+        for (int r = 0; r < kRankPer; ++r) cnt[r] += (fj < fi[r]) || (fj == fi[r] && j0 + q < idx[r]);
+      }
+    } else {
+      for (int q = 0; q < lim; ++q) {
+        const double fj = sf[q];
+#pragma unroll
+        for (int r = 0; r < kRankPer; ++r) cnt[r] += (fj < fi[r]) || (fj == fi[r] && j0 + q < idx[r]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kRankPer; ++r)
+    if (idx[r] < lam) part[static_cast<int64_t>(blockIdx.y) * lam + idx[r]] = cnt[r];
 }
 
-// zero fill by a kernel, so the sequence stays free of memset nodes when a
-// generation is captured into a graph
-__global__ void k_zero_i32(int32_t* __restrict__ p, int count) {
+__global__ void k_scatter_order(const int32_t* __restrict__ part, int splits, int lam,
+                                int32_t* __restrict__ order) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = 0;
-}
-
-__global__ void k_scatter_order(const int32_t* __restrict__ rank, int lam, int32_t* __restrict__ order) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < lam) order[rank[i]] = i;
+  if (i >= lam) return;
+  int rank = 0;
+  for (int y = 0; y < splits; ++y) rank += part[static_cast<int64_t>(y) * lam + i];
+  order[rank] = i;
 }
 
 // y_w = sum_{r<mu} w_r y_{order[r]}, z_w likewise (float64 accumulation), and
@@ -291,17 +307,18 @@ __global__ void k_convert(const double* __restrict__ s, int lds, T* __restrict__
 
 }  // namespace
 
-hipError_t launch_rank(hipStream_t st, const double* f, int lam, int32_t* order) {
-  // the rank counters live in order[lam, 2 lam)
-  int32_t* rank = order + lam;
-  k_zero_i32<<<ceil_div(lam, 256), 256, 0, st>>>(rank, lam);
-  const int splits = max(1, min(16, lam / 512));
-  const int span = ceil_div(lam, splits);
-  dim3 grid(ceil_div(lam, 256), splits);
-  k_rank_count<<<grid, 256, 0, st>>>(f, lam, span, rank);
-  k_scatter_order<<<ceil_div(lam, 256), 256, 0, st>>>(rank, lam, order);
+// j values per split: chunks of kRankChunk, at most kRankMaxSplits splits
+int rank_span(int lam) { return round_up(ceil_div(lam, kRankMaxSplits), kRankChunk); }
+
+hipError_t launch_rank(hipStream_t st, const double* f, int lam, int32_t* order, int32_t* work) {
+  const int span = rank_span(lam), splits = ceil_div(lam, span);
+  dim3 grid(ceil_div(lam, 256 * kRankPer), splits);
+  k_rank_count<<<grid, 256, 0, st>>>(f, lam, span, work);
+  k_scatter_order<<<ceil_div(lam, 256), 256, 0, st>>>(work, splits, lam, order);
   return hipGetLastError();
 }
+
+size_t rank_work_elems(int lam) { return static_cast<size_t>(ceil_div(lam, rank_span(lam))) * lam; }
 
 hipError_t launch_recombine(hipStream_t st, bool fp64, int n, int lam, int mu, const void* Y, const void* Z,
                             int ld, const int32_t* order, const double* w, const double* sqrtw, void* Ysel,
