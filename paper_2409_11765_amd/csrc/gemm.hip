@@ -71,10 +71,11 @@ __device__ __forceinline__ void vload(const T* p, T (&v)[Cfg<T>::VEC]) {
 //   P[k + r*ld]   (KCONTIG = true:  k contiguous),
 // rows r0.., k0.., into registers (2 vectors per thread), zero outside
 // [0, R) x [0, K).
-template <typename T, int ROWS, bool KCONTIG>
+template <typename T, int ROWS, bool KCONTIG, int NT = 256>
 struct SlabLoader {
   static constexpr int VEC = Cfg<T>::VEC, BK = Cfg<T>::BK;
-  static constexpr int PASSES = ROWS * BK / VEC / 256;
+  static constexpr int PASSES = ROWS * BK / VEC / NT;
+  static_assert(PASSES >= 1, "slab too small for the thread count");
   T v[PASSES][VEC];
 
   __device__ void load(const T* __restrict__ P, int ld, int R, int K, int r0, int k0) {
@@ -84,7 +85,7 @@ struct SlabLoader {
       int r, k;
       if constexpr (!KCONTIG) {
         constexpr int PER_COL = ROWS / VEC;
-        const int q = p * 256 + t;
+        const int q = p * NT + t;
         r = r0 + (q % PER_COL) * VEC;
         k = k0 + q / PER_COL;
         if (k < K && r + VEC <= R) {
@@ -96,7 +97,7 @@ struct SlabLoader {
         }
       } else {
         constexpr int PER_ROW = BK / VEC;
-        const int q = p * 256 + t;
+        const int q = p * NT + t;
         k = k0 + (q % PER_ROW) * VEC;
         r = r0 + q / PER_ROW;
         if (r < R && k + VEC <= K) {
@@ -118,13 +119,13 @@ struct SlabLoader {
     for (int p = 0; p < PASSES; ++p) {
       if constexpr (!KCONTIG) {
         constexpr int PER_COL = ROWS / VEC;
-        const int q = p * 256 + t;
+        const int q = p * NT + t;
         const int r = (q % PER_COL) * VEC, k = q / PER_COL;
 #pragma unroll
         for (int c = 0; c < VEC; ++c) S[k * LD + r + c] = v[p][c];
       } else {
         constexpr int PER_ROW = BK / VEC;
-        const int q = p * 256 + t;
+        const int q = p * NT + t;
         const int k = (q % PER_ROW) * VEC, r = q / PER_ROW;
 #pragma unroll
         for (int c = 0; c < VEC; ++c) S[(k + c) * LD + r] = v[p][c];
@@ -136,14 +137,18 @@ struct SlabLoader {
 // Main loop: acc[i][j] += opA(tile) * opB(tile) for one block tile (m0, n0).
 // TA: A is stored K x M (element (m,k) at A[k + m*lda]); otherwise M x K.
 // TB: B is stored N x K (element (k,n) at B[n + k*ldb]); otherwise K x N.
-template <typename T, bool TA, bool TB>
+// NT = 512: two k-groups of 4 waves, waves 4-7 taking the second half of
+// every k-tile into accumulators of their own (the caller folds them).
+template <typename T, bool TA, bool TB, int NT = 256>
 __device__ __forceinline__ void gemm_mainloop(int M, int N, int K, const T* __restrict__ A, int lda,
                                               const T* __restrict__ B, int ldb, int m0, int n0,
                                               T* As, T* Bs, typename Cfg<T>::acc_t (&acc)[2][2]) {
   using C = Cfg<T>;
   constexpr int LDA = C::BM + C::PAD, LDB = C::BN + C::PAD;
+  constexpr int KG = NT / 256;
+  static_assert(C::BK % (KG * C::KS) == 0, "k-tile must split evenly over the k-groups");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave & 1, wn = (wave >> 1) & 1, kg = wave >> 2;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -151,8 +156,8 @@ __device__ __forceinline__ void gemm_mainloop(int M, int N, int K, const T* __re
 #pragma unroll
       for (int r = 0; r < C::NACC; ++r) acc[i][j][r] = T(0);
 
-  SlabLoader<T, C::BM, TA> la;   // TA -> k contiguous in memory
-  SlabLoader<T, C::BN, !TB> lb;  // !TB -> k contiguous in memory
+  SlabLoader<T, C::BM, TA, NT> la;   // TA -> k contiguous in memory
+  SlabLoader<T, C::BN, !TB, NT> lb;  // !TB -> k contiguous in memory
   const int nk = (K + C::BK - 1) / C::BK;
   if (nk == 0) return;
   la.load(A, lda, M, K, m0, 0);
@@ -167,7 +172,8 @@ __device__ __forceinline__ void gemm_mainloop(int M, int N, int K, const T* __re
       lb.load(B, ldb, N, K, n0, (kt + 1) * C::BK);
     }
 #pragma unroll
-    for (int kk = 0; kk < C::BK; kk += C::KS) {
+    for (int k2 = 0; k2 < C::BK / KG; k2 += C::KS) {
+      const int kk = kg * (C::BK / KG) + k2;
       T a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) a[i] = As[(kk + kidx) * LDA + wm * C::WM + i * C::MB + midx];
@@ -292,6 +298,42 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const T* __re
   const int n0 = (blockIdx.x / tiles_m) * C::BN;
   typename C::acc_t acc[2][2];
   gemm_mainloop<T, TA, TB>(M, N, K, A, lda, B, ldb, m0, n0, As, Bs, acc);
+  epi(acc, M, N, m0, n0, As);
+}
+
+// float64 C = op(A) op(B) for the eigensolver's n x n products: 64 x 64 tiles
+// as two k-groups of 4 waves, so that two waves share each SIMD even when
+// there is one tile per CU; k-group 1's sums are folded into waves 0-3
+// through LDS (fixed order), which then store the tile.
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(512) k_dgemm_kg(int M, int N, int K, const double* __restrict__ A, int lda,
+                                                  const double* __restrict__ B, int ldb, EpiStore<double> epi) {
+  using C = Cfg<double>;
+  __shared__ double As[C::BK * (C::BM + C::PAD)];
+  __shared__ double Bs[C::BK * (C::BN + C::PAD)];
+  __shared__ double fold[4 * 4 * C::NACC * 64];
+  const int tiles_m = (M + C::BM - 1) / C::BM;
+  const int m0 = (blockIdx.x % tiles_m) * C::BM;
+  const int n0 = (blockIdx.x / tiles_m) * C::BN;
+  typename C::acc_t acc[2][2];
+  gemm_mainloop<double, TA, TB, 512>(M, N, K, A, lda, B, ldb, m0, n0, As, Bs, acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wq = wave & 3;
+  if (wave >= 4) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < C::NACC; ++r) fold[(((r * 4 + wq) * 2 + i) * 2 + j) * 64 + lane] = acc[i][j][r];
+  }
+  __syncthreads();
+  if (wave >= 4) return;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < C::NACC; ++r) acc[i][j][r] += fold[(((r * 4 + wq) * 2 + i) * 2 + j) * 64 + lane];
   epi(acc, M, N, m0, n0, As);
 }
 
@@ -611,11 +653,15 @@ hipError_t launch_syrk_update_f64(hipStream_t st, int n, int mu, const double* Y
 
 hipError_t launch_dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A, int lda,
                         const double* B, int ldb, double* C, int ldc) {
+  using Cf = Cfg<double>;
+  const int tiles = ceil_div(M, Cf::BM) * ceil_div(N, Cf::BN);
+  if (tiles == 0) return hipSuccess;
   EpiStore<double> e{C, ldc};
-  if (!ta && !tb) return run_gemm<double, false, false>(st, M, N, K, A, lda, B, ldb, e);
-  if (ta && !tb) return run_gemm<double, true, false>(st, M, N, K, A, lda, B, ldb, e);
-  if (!ta && tb) return run_gemm<double, false, true>(st, M, N, K, A, lda, B, ldb, e);
-  return run_gemm<double, true, true>(st, M, N, K, A, lda, B, ldb, e);
+  if (!ta && !tb) k_dgemm_kg<false, false><<<tiles, 512, 0, st>>>(M, N, K, A, lda, B, ldb, e);
+  else if (ta && !tb) k_dgemm_kg<true, false><<<tiles, 512, 0, st>>>(M, N, K, A, lda, B, ldb, e);
+  else if (!ta && tb) k_dgemm_kg<false, true><<<tiles, 512, 0, st>>>(M, N, K, A, lda, B, ldb, e);
+  else k_dgemm_kg<true, true><<<tiles, 512, 0, st>>>(M, N, K, A, lda, B, ldb, e);
+  return hipGetLastError();
 }
 
 }  // namespace cmx
