@@ -26,8 +26,8 @@ PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
 
 
 def kernel_work(n, lam, precision, sweeps, syrk_cfg=None):
-    """Algorithmic work per launch of each timed kernel:
-    (amount, unit, peak, bound)."""
+    """Algorithmic work per launch of each timed kernel: (amount, unit, peak,
+    bound)."""
     mu = lam // 2
     N = 32 * ((n + 31) // 32)
     q = N // 32                      # Jacobi block pairs per round
@@ -422,7 +422,7 @@ def run_ert(P, torch, seeds=(1, 2, 3), dims=(10, 40), budget_s=3.0, kmax=64, lam
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch

@@ -17,7 +17,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  Written from the paper
 The paper prints no parameter formula, no step-size rule and no stopping
 thresholds (it defers to the default settings of the reference C code and to
 the usual stopping conditions).  Readings taken here, all of them shared with
-the GPU path and listed in the design doc:
+the GPU path:
 
 * parameters, weights, cumulation and step-size rules: the published CMA-ES
   tutorial (Hansen, arXiv:1604.00772) with positive weights only;
