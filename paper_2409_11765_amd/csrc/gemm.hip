@@ -445,6 +445,7 @@ __global__ void __launch_bounds__(256) k_fitness_reduce(int lam, const T* __rest
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= lam) return;
   double s = 0.0;
+#pragma unroll 16
   for (int t = 0; t < tiles; ++t) s += static_cast<double>(partial[static_cast<int64_t>(t) * ldp + k]);
   f[k] = s + add;
 }

@@ -65,6 +65,7 @@ __global__ void k_scatter_order(const int32_t* __restrict__ part, int splits, in
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= lam) return;
   int rank = 0;
+#pragma unroll 16
   for (int y = 0; y < splits; ++y) rank += part[static_cast<int64_t>(y) * lam + i];
   order[rank] = i;
 }
@@ -84,6 +85,8 @@ __global__ void __launch_bounds__(256) k_recombine(int n, int mu, const T* __res
   if (i >= n) return;
   const int r0 = blockIdx.y * 64, r1 = min(mu, r0 + 64);
   double ay = 0.0, az = 0.0;
+  // unrolled so that many loads are in flight; the sums keep rank order
+#pragma unroll 16
   for (int r = r0; r < r1; ++r) {
     const int64_t c = static_cast<int64_t>(order[r]) * ld;
     const T y = Y[c + i];
@@ -101,6 +104,7 @@ __global__ void k_reduce_yz(int n, int nchunks, const double* __restrict__ py, c
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double a = 0.0, b = 0.0;
+#pragma unroll 16
   for (int c = 0; c < nchunks; ++c) {
     a += py[static_cast<int64_t>(c) * n + i];
     b += pz[static_cast<int64_t>(c) * n + i];
@@ -116,6 +120,7 @@ __global__ void __launch_bounds__(256) k_matvec(int n, const double* __restrict_
   if (i >= n) return;
   const int j0 = blockIdx.y * 64, j1 = min(n, j0 + 64);
   double s = 0.0;
+#pragma unroll 16
   for (int j = j0; j < j1; ++j) s += B[static_cast<int64_t>(j) * ldb + i] * x[j];
   part[static_cast<int64_t>(blockIdx.y) * n + i] = s;
 }
@@ -147,6 +152,7 @@ __global__ void __launch_bounds__(1024) k_vec_update(KParams kp, int nchunks, co
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += 1024) {
     double bz = 0.0;
+#pragma unroll 16
     for (int c = 0; c < nchunks; ++c) bz += part_bz[static_cast<int64_t>(c) * n + i];
     const double v = (1.0 - kp.cs) * ps[i] + fps * bz;
     ps[i] = v;
@@ -285,6 +291,7 @@ __global__ void k_reduce_vec(int n, int nchunks, const double* __restrict__ part
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double a = 0.0;
+#pragma unroll 16
   for (int c = 0; c < nchunks; ++c) a += part[static_cast<int64_t>(c) * n + i];
   out[i] = a;
 }
