@@ -140,8 +140,9 @@ __device__ __forceinline__ void pair_idx(int r, int x, int& a, int& b) {
 }
 
 // One inner round: every thread owns one 2x2 block (rotation x, rotation y),
-// recomputes the two rotations it needs, updates its block of S into the
-// other buffer and rows r0, r1 of Q for rotation x.
+// computes rotation x and takes rotation y from the lane of its wave that
+// computed it (lanes 16 g .. 16 g + 15 hold rotations 0..15), updates its
+// block of S into the other buffer and rows r0, r1 of Q for rotation x.
 template <bool INTRA>
 __device__ __forceinline__ void inner_round(const double* S, double* Sn, double* Q, double thr, double inv, int rr,
                                             int x, int y) {
@@ -150,14 +151,15 @@ __device__ __forceinline__ void inner_round(const double* S, double* Sn, double*
   pair_idx<INTRA>(rr, y, ay, by);
   const int r0 = 2 * y, r1 = 2 * y + 1;
   const double xaa = S[ax * kLD + ax], xbb = S[bx * kLD + bx], xab = S[ax * kLD + bx];
-  const double yaa = S[ay * kLD + ay], ybb = S[by * kLD + by], yab = S[ay * kLD + by];
   const double m00 = S[ax * kLD + ay], m01 = S[ax * kLD + by];
   const double m10 = S[bx * kLD + ay], m11 = S[bx * kLD + by];
   const double q0a = Q[r0 * kLD + ax], q0b = Q[r0 * kLD + bx];
   const double q1a = Q[r1 * kLD + ax], q1b = Q[r1 * kLD + bx];
-  double cx, sx, cy, sy;
+  double cx, sx;
   jacobi_rotation(xaa, xbb, xab, thr, inv, cx, sx);
-  jacobi_rotation(yaa, ybb, yab, thr, inv, cy, sy);
+  // y = t / 16 lies in this wave's lane group; its rotation is lane (lane & 48) | y's
+  const int src = static_cast<int>(threadIdx.x & 48) | y;
+  const double cy = __shfl(cx, src), sy = __shfl(sx, src);
   // S_xy <- J_x^T S_xy J_y,  J = [[c, s], [-s, c]] on (a, b)
   const double p00 = m00 * cy - m01 * sy, p01 = m00 * sy + m01 * cy;
   const double p10 = m10 * cy - m11 * sy, p11 = m10 * sy + m11 * cy;
