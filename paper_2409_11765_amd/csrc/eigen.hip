@@ -139,10 +139,20 @@ __device__ __forceinline__ void pair_idx(int r, int x, int& a, int& b) {
   }
 }
 
+// Value held by lane 0 of this lane's 16-lane row (DPP row broadcast, two
+// 32-bit moves).
+__device__ __forceinline__ double row_lane0(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x150, 0xF, 0xF, false);  // row_newbcast:0
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x150, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // One inner round: every thread owns one 2x2 block (rotation x, rotation y),
-// computes rotation x and takes rotation y from the lane of its wave that
-// computed it (lanes 16 g .. 16 g + 15 hold rotations 0..15), updates its
-// block of S into the other buffer and rows r0, r1 of Q for rotation x.
+// computes rotation x and takes rotation y from lane 0 of its 16-lane row
+// (the caller lays the threads out so that a row shares y and its lane 0
+// has x = y), updates its block of S into the other buffer and rows r0, r1
+// of Q for rotation x.
 template <bool INTRA>
 __device__ __forceinline__ void inner_round(const double* S, double* Sn, double* Q, double thr, double inv, int rr,
                                             int x, int y) {
@@ -157,9 +167,7 @@ __device__ __forceinline__ void inner_round(const double* S, double* Sn, double*
   const double q1a = Q[r1 * kLD + ax], q1b = Q[r1 * kLD + bx];
   double cx, sx;
   jacobi_rotation(xaa, xbb, xab, thr, inv, cx, sx);
-  // y = t / 16 lies in this wave's lane group; its rotation is lane (lane & 48) | y's
-  const int src = static_cast<int>(threadIdx.x & 48) | y;
-  const double cy = __shfl(cx, src), sy = __shfl(sx, src);
+  const double cy = row_lane0(cx), sy = row_lane0(sx);
   // S_xy <- J_x^T S_xy J_y,  J = [[c, s], [-s, c]] on (a, b)
   const double p00 = m00 * cy - m01 * sy, p01 = m00 * sy + m01 * cy;
   const double p10 = m10 * cy - m11 * sy, p11 = m10 * sy + m11 * cy;
@@ -185,7 +193,9 @@ __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, doubl
                             double* __restrict__ qout) {
   const int t = threadIdx.x;
   for (int idx = t; idx < kS * kS; idx += 256) Q[(idx % kS) * kLD + idx / kS] = (idx % kS == idx / kS) ? 1.0 : 0.0;
-  const int x = t % (kS / 2), y = t / (kS / 2);
+  // a row of 16 lanes shares y; x = (lane + y) mod 16, so lane 0 of the row
+  // computes rotation y
+  const int y = t / (kS / 2), x = ((t & 15) + y) & 15;
   double* Sa = S0;
   double* Sb = S1;
   __syncthreads();
