@@ -148,7 +148,48 @@ __device__ __forceinline__ double row_lane0(double v) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
-// One inner round: every thread owns one 2x2 block (rotation x, rotation y),
+// Value held by lane (lane + 1) mod 16 of this lane's 16-lane row (DPP
+// row_ror:15, two 32-bit moves).
+__device__ __forceinline__ double row_next(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x12F, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x12F, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// One cross inner round (rotation x pairs a = x with b = 16 + (x + rr) mod 16)
+// with the thread's four Q entries in registers: qa0, qa1 = Q[2y, a],
+// Q[2y + 1, a] and qb0, qb1 = Q[2y, b], Q[2y + 1, b].  Otherwise as
+// inner_round below.
+__device__ __forceinline__ void inner_round_cross(const double* S, double* Sn, double thr, double inv, int rr, int x,
+                                                  int y, double& qa0, double& qa1, double& qb0, double& qb1) {
+  int ax, bx, ay, by;
+  pair_idx<false>(rr, x, ax, bx);
+  pair_idx<false>(rr, y, ay, by);
+  const double xaa = S[ax * kLD + ax], xbb = S[bx * kLD + bx], xab = S[ax * kLD + bx];
+  const double m00 = S[ax * kLD + ay], m01 = S[ax * kLD + by];
+  const double m10 = S[bx * kLD + ay], m11 = S[bx * kLD + by];
+  double cx, sx;
+  jacobi_rotation(xaa, xbb, xab, thr, inv, cx, sx);
+  const double cy = row_lane0(cx), sy = row_lane0(sx);
+  const double p00 = m00 * cy - m01 * sy, p01 = m00 * sy + m01 * cy;
+  const double p10 = m10 * cy - m11 * sy, p11 = m10 * sy + m11 * cy;
+  const double n00 = cx * p00 - sx * p10, n11 = sx * p01 + cx * p11;
+  const double n01 = cx * p01 - sx * p11, n10 = sx * p00 + cx * p10;
+  Sn[ax * kLD + ay] = n00;
+  Sn[ax * kLD + by] = n01;
+  Sn[bx * kLD + ay] = n10;
+  Sn[bx * kLD + by] = n11;
+  const double a0 = cx * qa0 - sx * qb0, b0 = sx * qa0 + cx * qb0;
+  const double a1 = cx * qa1 - sx * qb1, b1 = sx * qa1 + cx * qb1;
+  qa0 = a0;
+  qb0 = b0;
+  qa1 = a1;
+  qb1 = b1;
+}
+
+// One inner round (INTRA: the round-robin pairs inside each 16-block, with Q
+// in LDS): every thread owns one 2x2 block (rotation x, rotation y),
 // computes rotation x and takes rotation y from lane 0 of its 16-lane row
 // (the caller lays the threads out so that a row shares y and its lane 0
 // has x = y), updates its block of S into the other buffer and rows r0, r1
@@ -208,13 +249,31 @@ __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, doubl
       __syncthreads();
     }
   }
+  // cross rounds: the thread's Q entries (rows 2y, 2y + 1; columns a = x and
+  // b) stay in registers; the next round's column b is the one lane
+  // (lane + 1) mod 16 of the row holds now
+  const int r0 = 2 * y, r1 = 2 * y + 1;
+  double qa0 = Q[r0 * kLD + x], qa1 = Q[r1 * kLD + x];
+  double qb0 = Q[r0 * kLD + kNB + x], qb1 = Q[r1 * kLD + kNB + x];
   for (int rr = 0; rr < kNB; ++rr) {
-    inner_round<false>(Sa, Sb, Q, thr, inv, rr, x, y);
+    inner_round_cross(Sa, Sb, thr, inv, rr, x, y, qa0, qa1, qb0, qb1);
     double* tmp = Sa;
     Sa = Sb;
     Sb = tmp;
+    if (rr + 1 < kNB) {
+      qb0 = row_next(qb0);
+      qb1 = row_next(qb1);
+    }
     __syncthreads();
   }
+  {
+    const int b = kNB + ((x + kNB - 1) & (kNB - 1));
+    Q[r0 * kLD + x] = qa0;
+    Q[r1 * kLD + x] = qa1;
+    Q[r0 * kLD + b] = qb0;
+    Q[r1 * kLD + b] = qb1;
+  }
+  __syncthreads();
   for (int idx = t; idx < kS * kS; idx += 256) qout[idx] = Q[(idx % kS) * kLD + idx / kS];
   __syncthreads();
 }
