@@ -158,17 +158,20 @@ __device__ __forceinline__ double row_next(double v) {
 }
 
 // One cross inner round (rotation x pairs a = x with b = 16 + (x + rr) mod 16)
-// with the thread's four Q entries in registers: qa0, qa1 = Q[2y, a],
-// Q[2y + 1, a] and qb0, qb1 = Q[2y, b], Q[2y + 1, b].  Otherwise as
-// inner_round below.
+// with the thread's four Q entries in registers (qa0, qa1 = Q[2y, a],
+// Q[2y + 1, a]; qb0, qb1 = Q[2y, b], Q[2y + 1, b]) and two of its four S
+// entries: m00 = S[x, y], which no other thread reads unless x = y (then it
+// is also stored, for rotation x), and m10 = S[b, y], which next round
+// belongs to lane (lane + 1) mod 16 of the row.  S[x, b_y] and S[b, b_y] go
+// through LDS.  Otherwise as inner_round below.
 __device__ __forceinline__ void inner_round_cross(const double* S, double* Sn, double thr, double inv, int rr, int x,
-                                                  int y, double& qa0, double& qa1, double& qb0, double& qb1) {
+                                                  int y, double& qa0, double& qa1, double& qb0, double& qb1,
+                                                  double& m00, double& m10) {
   int ax, bx, ay, by;
   pair_idx<false>(rr, x, ax, bx);
   pair_idx<false>(rr, y, ay, by);
   const double xaa = S[ax * kLD + ax], xbb = S[bx * kLD + bx], xab = S[ax * kLD + bx];
-  const double m00 = S[ax * kLD + ay], m01 = S[ax * kLD + by];
-  const double m10 = S[bx * kLD + ay], m11 = S[bx * kLD + by];
+  const double m01 = S[ax * kLD + by], m11 = S[bx * kLD + by];
   double cx, sx;
   jacobi_rotation(xaa, xbb, xab, thr, inv, cx, sx);
   const double cy = row_lane0(cx), sy = row_lane0(sx);
@@ -176,10 +179,11 @@ __device__ __forceinline__ void inner_round_cross(const double* S, double* Sn, d
   const double p10 = m10 * cy - m11 * sy, p11 = m10 * sy + m11 * cy;
   const double n00 = cx * p00 - sx * p10, n11 = sx * p01 + cx * p11;
   const double n01 = cx * p01 - sx * p11, n10 = sx * p00 + cx * p10;
-  Sn[ax * kLD + ay] = n00;
+  if (x == y) Sn[ax * kLD + ay] = n00;  // the diagonal, read by rotation x's threads
   Sn[ax * kLD + by] = n01;
-  Sn[bx * kLD + ay] = n10;
   Sn[bx * kLD + by] = n11;
+  m00 = n00;
+  m10 = n10;
   const double a0 = cx * qa0 - sx * qb0, b0 = sx * qa0 + cx * qb0;
   const double a1 = cx * qa1 - sx * qb1, b1 = sx * qa1 + cx * qb1;
   qa0 = a0;
@@ -250,19 +254,21 @@ __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, doubl
     }
   }
   // cross rounds: the thread's Q entries (rows 2y, 2y + 1; columns a = x and
-  // b) stay in registers; the next round's column b is the one lane
-  // (lane + 1) mod 16 of the row holds now
+  // b) and S entries S[x, y], S[b, y] stay in registers; the next round's b
+  // entries are the ones lane (lane + 1) mod 16 of the row holds now
   const int r0 = 2 * y, r1 = 2 * y + 1;
   double qa0 = Q[r0 * kLD + x], qa1 = Q[r1 * kLD + x];
   double qb0 = Q[r0 * kLD + kNB + x], qb1 = Q[r1 * kLD + kNB + x];
+  double m00 = Sa[x * kLD + y], m10 = Sa[(kNB + x) * kLD + y];
   for (int rr = 0; rr < kNB; ++rr) {
-    inner_round_cross(Sa, Sb, thr, inv, rr, x, y, qa0, qa1, qb0, qb1);
+    inner_round_cross(Sa, Sb, thr, inv, rr, x, y, qa0, qa1, qb0, qb1, m00, m10);
     double* tmp = Sa;
     Sa = Sb;
     Sb = tmp;
     if (rr + 1 < kNB) {
       qb0 = row_next(qb0);
       qb1 = row_next(qb1);
+      m10 = row_next(m10);
     }
     __syncthreads();
   }
