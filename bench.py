@@ -22,7 +22,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
+PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "bf16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0}
 
 
 def kernel_work(n, lam, precision, sweeps, syrk_cfg=None):
@@ -112,6 +112,10 @@ def parse():
                          "traffic, for scaling HBM counters)")
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the headline line: per-phase mixed-vs-FP64 table over n and K")
+    ap.add_argument("--large", action="store_true",
+                    help="instead of the headline line: the large workload (n=2000, lambda=4096, rotated "
+                         "ellipsoid, bf16x3 sampling)")
+    ap.add_argument("--large-steps", type=int, default=50)
     ap.add_argument("--ert", action="store_true",
                     help="instead of the headline line: ERT / ECDF of IPOP, K-Distributed and K-Replicated on "
                          "synthetic functions")
@@ -121,11 +125,11 @@ def parse():
     return ap.parse_args()
 
 
-def run_gpu(P, torch, n, lam, precision, steps, warmup, seed, R, xs, tune=True, tiles=None):
+def run_gpu(P, torch, n, lam, precision, steps, warmup, seed, R, xs, tune=True, tiles=None, objective="rastrigin"):
     # a dedicated (default-priority) torch stream, handed to the library, so
     # the timing events below bracket exactly the library's work
     stream = torch.cuda.Stream()
-    es = P.CMAES(n, lam, 2.0, seed=seed, precision=precision, objective="rastrigin", R=R, xstar=xs,
+    es = P.CMAES(n, lam, 2.0, seed=seed, precision=precision, objective=objective, R=R, xstar=xs,
                  stream=stream.cuda_stream)
     tiles_out = None
     try:
@@ -177,6 +181,30 @@ def run_gpu(P, torch, n, lam, precision, steps, warmup, seed, R, xs, tune=True, 
         es.close()
     return {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "phases_us": phases, "state": st,
             "kernels": kt, "tiles": tiles_out}
+
+
+def run_large(P, torch, steps, seed):
+    """The large workload: n = 2000, lambda = 4096, mu = 2048, rotated
+    ellipsoid (condition 1e6), y = B D z as bf16 hi/lo split products with
+    float32 accumulation, float32 SYRK, float64 eigensolve every generation
+    (the rule max(1, ceil(1/(10 n (c1 + cmu)))) gives 1 here)."""
+    import synth
+    n, lam = 2000, 4096
+    R, xs = synth.problem(n, seed)
+    res = run_gpu(P, torch, n, lam, "mixed_bf16x3", steps, 5, seed, R, xs, objective="ellipsoid")
+    kt = res["kernels"]
+    work = kernel_work(n, lam, "mixed", res["state"]["eig_sweeps"],
+                       res["tiles"]["syrk"]["config"] if res["tiles"] else None)
+    # the sampling product runs as three bf16 products: priced as executed
+    # bf16 flops against the bf16 MFMA peak
+    work["sample_gemm"] = (3 * 2.0 * n * n * lam, "TFLOP/s", PEAK["bf16_mfma_tflops"], "mfma")
+    per_kernel = {k: roofline_entry(k, kt, work) for k in kt if kt[k]["calls"] and k in work}
+    return {"workload": f"rotated ellipsoid (cond 1e6) n={n} lambda={lam} mu={lam // 2}, bf16x3 sampling, "
+                        "float32 SYRK, float64 eigensolve every generation",
+            "evals_per_s": lam * 1e3 / res["ms_per_step"], "gens_per_s": 1e3 / res["ms_per_step"],
+            "ms_per_step": res["ms_per_step"], "steps": steps, "eig_sweeps_last": res["state"]["eig_sweeps"],
+            "phases_us": res["phases_us"], "gemm_tiles": res["tiles"],
+            "kernels": {k: {**kt[k], "roofline": per_kernel.get(k)} for k in kt}}
 
 
 def run_batch(P, torch, steps, warmup, seed):
@@ -446,6 +474,9 @@ def main():
         return
     if a.ert:
         print(json.dumps({"ert": run_ert(P, torch)}), flush=True)
+        return
+    if a.large:
+        print(json.dumps({"large": run_large(P, torch, a.large_steps, a.seed)}), flush=True)
         return
     tiles = [int(v) for v in a.tiles.split(",")] if a.tiles else None
     mixed = run_gpu(P, torch, n, lam, a.precision, a.steps, a.warmup, a.seed, R, xs, tune=not a.no_tune,
