@@ -203,6 +203,7 @@ def run_large(P, torch, steps, seed):
                         "float32 SYRK, float64 eigensolve every generation",
             "evals_per_s": lam * 1e3 / res["ms_per_step"], "gens_per_s": 1e3 / res["ms_per_step"],
             "ms_per_step": res["ms_per_step"], "steps": steps, "eig_sweeps_last": res["state"]["eig_sweeps"],
+            "eig_corrections_last": res["state"]["eig_corrections"],
             "phases_us": res["phases_us"], "gemm_tiles": res["tiles"],
             "kernels": {k: {**kt[k], "roofline": per_kernel.get(k)} for k in kt}}
 
@@ -512,6 +513,7 @@ def main():
                    "n": n, "lambda": lam, "mu": mu, "precision": a.precision, "parallelism": "single GPU"},
         "gens_per_s": gens,
         "eig_sweeps_last": mixed["state"]["eig_sweeps"],
+        "eig_corrections_last": mixed["state"]["eig_corrections"],
         "phases_us": ph,
         "phase_share": phase_share,
         "dominant_phase": dom,

@@ -107,7 +107,7 @@ typedef struct {
   uint32_t stop;       /* CMAES_STOP_* bits of the current descent             */
   int32_t kappa;       /* eigendecomposition interval in use                   */
   int32_t eig_sweeps;  /* Jacobi sweeps used by the last eigendecomposition    */
-  int32_t reserved;
+  int32_t eig_corrections; /* closing corrections it used after the sweeps    */
   double* m;
   double* C;
   double* B;
@@ -234,11 +234,24 @@ int cmaes_phase_times(const cmaes_t* h, double* out);
  * covariance update and the eigensolve set-up -- as one hipGraph, captured on
  * first use and replayed while the handle's shapes, stream, objective,
  * options and GEMM tiles are unchanged (any change re-captures).  The
- * data-dependent sweeps of the eigensolve and the stop tests stay eager.
+ * eigensolve's sweeps and corrections, whose number depends on the data, are
+ * replayed from graphs of their own between the host's convergence checks.
  * Results are bit-identical with graphs on or off.  Default on; graphs are
  * not used while phase or kernel timing is enabled, with caller-supplied z,
  * or on the legacy null stream. */
 int cmaes_enable_graphs(cmaes_t* h, int on);
+/* Closing correction of the eigensolve (C = B D^2 B^T, Sec. 2.1).  Once the
+ * block-Jacobi sweeps have brought off(A) below 1e-8 of ||A||_F, one
+ * simultaneous rotation of every index pair by its 2 x 2 Jacobi angle
+ * (five float64 products) takes the place of the last sweep.  A correction
+ * whose angles are not small (||Theta||_F > max_angle_norm) leaves A
+ * unchanged and the solve finishes with sweeps.  Either way the solve stops
+ * at the same off(A) <= 1e-13 ||A||_F.  on: 0 or 1 (default 1);
+ * max_angle_norm in [0, 2e-3] (default 2e-3, the bound below which the
+ * rotation is orthogonal to rounding; 0 rejects every correction that would
+ * rotate).  CMAES_EINVAL outside that range.  cmaes_state() reports the
+ * sweeps and corrections (rejected ones included) of the last eigensolve. */
+int cmaes_set_eigen_correction(cmaes_t* h, int on, double max_angle_norm);
 int cmaes_enable_kernel_timing(cmaes_t* h, int on);
 int cmaes_kernel_times(const cmaes_t* h, double* total_us, int64_t* calls);
 

@@ -14,6 +14,6 @@ from .binding import (CMAES, CMAESBatch, CmaesError, CmaesOptions, KERNELS, OBJE
                       cmaes_batch_generation, cmaes_batch_set_objective, cmaes_batch_set_options,
                       cmaes_batch_state, SITES, cmaes_autotune, cmaes_device_arch, cmaes_syrk_plan, cmaes_gemm_config_count,
                       cmaes_gemm_config_info, cmaes_get_gemm_config, cmaes_set_gemm_config,
-                      cmaes_enable_graphs, cmaes_batch_enable_graphs, KReplicated, cmaes_krep_create,
+                      cmaes_enable_graphs, cmaes_batch_enable_graphs, cmaes_set_eigen_correction, KReplicated, cmaes_krep_create,
                       cmaes_krep_destroy, cmaes_krep_generation, cmaes_krep_run, cmaes_krep_set_objective,
                       cmaes_krep_set_options, cmaes_krep_status)

@@ -55,7 +55,7 @@ class CmaesState(C.Structure):
     _fields_ = [("n", C.c_int32), ("lambda_", C.c_int32), ("mu", C.c_int32), ("restart", C.c_int32),
                 ("gen", C.c_int64), ("evals", C.c_int64), ("total_evals", C.c_int64),
                 ("sigma", C.c_double), ("f_best", C.c_double), ("stop", C.c_uint32), ("kappa", C.c_int32),
-                ("eig_sweeps", C.c_int32), ("reserved", C.c_int32), ("m", _PD), ("C", _PD), ("B", _PD), ("D", _PD), ("p_sigma", _PD), ("p_c", _PD),
+                ("eig_sweeps", C.c_int32), ("eig_corrections", C.c_int32), ("m", _PD), ("C", _PD), ("B", _PD), ("D", _PD), ("p_sigma", _PD), ("p_c", _PD),
                 ("x_best", _PD), ("f", _PD), ("order", _PI)]
 
 
@@ -90,6 +90,7 @@ def _load():
         "cmaes_phase_times": (C.c_int, [H, _PD]),
         "cmaes_enable_kernel_timing": (C.c_int, [H, C.c_int]),
         "cmaes_enable_graphs": (C.c_int, [H, C.c_int]),
+        "cmaes_set_eigen_correction": (C.c_int, [H, C.c_int, C.c_double]),
         "cmaes_batch_enable_graphs": (C.c_int, [H, C.c_int]),
         "cmaes_kernel_times": (C.c_int, [H, _PD, C.POINTER(C.c_int64)]),
         "cmaes_last_error": (C.c_char_p, []),
@@ -128,7 +129,7 @@ EXPORTED = ["cmaes_default_options", "cmaes_create", "cmaes_destroy", "cmaes_set
             "cmaes_get_options", "cmaes_set_objective", "cmaes_generation", "cmaes_generation_with_z",
             "cmaes_ask", "cmaes_tell", "cmaes_restart_ipop", "cmaes_ipop_run", "cmaes_state",
             "cmaes_set_state", "cmaes_enable_timing", "cmaes_phase_times", "cmaes_enable_kernel_timing",
-            "cmaes_enable_graphs", "cmaes_batch_enable_graphs",
+            "cmaes_enable_graphs", "cmaes_batch_enable_graphs", "cmaes_set_eigen_correction",
             "cmaes_kernel_times", "cmaes_last_error", "cmaes_gemm_config_count", "cmaes_gemm_config_info",
             "cmaes_set_gemm_config", "cmaes_get_gemm_config", "cmaes_autotune", "cmaes_device_arch",
             "cmaes_syrk_plan", "cmaes_batch_create", "cmaes_batch_destroy",
@@ -233,7 +234,8 @@ def cmaes_state(h, arrays: bool = True, _fetch=None) -> dict:
     _check(fetch(s))  # scalars first, to learn n and lambda
     out = {"n": s.n, "lambda": s.lambda_, "mu": s.mu, "restart": s.restart, "gen": s.gen,
            "evals": s.evals, "total_evals": s.total_evals, "sigma": s.sigma, "f_best": s.f_best,
-           "stop": s.stop, "kappa": s.kappa, "eig_sweeps": s.eig_sweeps}
+           "stop": s.stop, "kappa": s.kappa, "eig_sweeps": s.eig_sweeps,
+           "eig_corrections": s.eig_corrections}
     if arrays:
         n, lam = s.n, s.lambda_
         bufs = {k: np.zeros(n) for k in ("m", "D", "p_sigma", "p_c", "x_best")}
@@ -283,6 +285,10 @@ def cmaes_phase_times(h) -> dict:
 
 def cmaes_enable_graphs(h, on: bool = True):
     _check(_lib.cmaes_enable_graphs(h, 1 if on else 0))
+
+
+def cmaes_set_eigen_correction(h, on: bool = True, max_angle_norm: float = 2e-3):
+    _check(_lib.cmaes_set_eigen_correction(h, 1 if on else 0, float(max_angle_norm)))
 
 
 def cmaes_batch_enable_graphs(b, on: bool = True):
@@ -426,6 +432,9 @@ class CMAES:
 
     def enable_graphs(self, on=True):
         cmaes_enable_graphs(self.h, on)
+
+    def set_eigen_correction(self, on=True, max_angle_norm=2e-3):
+        cmaes_set_eigen_correction(self.h, on, max_angle_norm)
 
     def enable_kernel_timing(self, on=True):
         cmaes_enable_kernel_timing(self.h, on)

@@ -160,8 +160,9 @@ void free_pop_buffers(cmaes* h) {
 }
 
 void drop_graphs(cmaes* h) {
-  if ((h->gx[0] || h->gx[1] || h->gx[2] || h->ew.gx[0] || h->ew.gx[1] || h->ew.gx[2]) && h->st)
-    (void)hipStreamSynchronize(h->st);  // no replay in flight
+  bool any = h->gx[0] || h->gx[1] || h->gx[2];
+  for (auto g : h->ew.gx) any = any || g;
+  if (any && h->st) (void)hipStreamSynchronize(h->st);  // no replay in flight
   eigen_drop_graphs(h->ew);
   for (int i = 0; i < 3; ++i) {
     if (h->gx[i]) (void)hipGraphExecDestroy(h->gx[i]);
@@ -197,6 +198,8 @@ void free_all(cmaes* h) {
   dev_free(h->ew.Q);
   dev_free(h->ew.T);
   dev_free(h->ew.A2);
+  dev_free(h->ew.X1);
+  dev_free(h->ew.X2);
   dev_free(h->ew.Q2);
   dev_free(h->ew.evals);
   dev_free(h->ew.perm);
@@ -275,6 +278,7 @@ int alloc_fixed(cmaes* h) {
       (rc = dev_alloc(&h->ew.A, 8ull * N * N)) || (rc = dev_alloc(&h->ew.V, 8ull * N * N)) ||
       (rc = dev_alloc(&h->ew.Q, 8ull * (N / 32) * 32 * 32)) || (rc = dev_alloc(&h->ew.T, 8 * nn)) ||
       (rc = dev_alloc(&h->ew.A2, 8ull * N * N)) || (rc = dev_alloc(&h->ew.Q2, 8ull * (N / 32) * 32 * 32)) ||
+      (rc = dev_alloc(&h->ew.X1, 8ull * N * N)) || (rc = dev_alloc(&h->ew.X2, 8ull * N * N)) ||
       (rc = dev_alloc(&h->ew.evals, 8ull * N)) || (rc = dev_alloc(&h->ew.perm, 4ull * N)) ||
       (rc = dev_alloc(&h->ew.sign, 8ull * N)) || (rc = dev_alloc(&h->ew.scale, 16)) ||
       (rc = dev_alloc(&h->ew.status, 16)))
@@ -288,7 +292,7 @@ int alloc_fixed(cmaes* h) {
   if (hipHostMalloc(&hf, 16, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
     return fail(CMAES_ENOMEM, "hipHostMalloc failed");
   h->ew.hflags = static_cast<int*>(hf);
-  h->ew.hflags[0] = h->ew.hflags[1] = 0;
+  h->ew.hflags[0] = h->ew.hflags[1] = h->ew.hflags[2] = h->ew.hflags[3] = 0;
   void* dp = nullptr;
   if (hipHostGetDevicePointer(&dp, hf, 0) != hipSuccess) return fail(CMAES_EDEVICE, "hipHostGetDevicePointer failed");
   h->ew.dflags = static_cast<int*>(dp);
@@ -358,6 +362,7 @@ int init_descent(cmaes* h, bool fresh) {
   h->reorth_sweeps = 0;  // B = I
   h->eig_uncounted = false;
   h->ew.last_sweeps = 0;
+  h->ew.last_closed = false;
   refresh_stop_params(h);
   return 0;
 }
@@ -899,7 +904,7 @@ int cmaes_state(const cmaes_t* hc, cmaes_state_t* out) {
   out->stop = s.stop;
   out->kappa = h->hp.kp.kappa;
   out->eig_sweeps = s.jac_sweeps;
-  out->reserved = 0;
+  out->eig_corrections = s.jac_corr;
   auto vec = [&](double* dst, const double* src) -> int {
     if (dst) CMX_HIP(hipMemcpy(dst, src, 8ull * n, hipMemcpyDeviceToHost));
     return 0;
@@ -945,6 +950,7 @@ int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in) {
     h->reorth_sweeps = 0;  // taken as orthogonal
     h->eig_uncounted = false;
     h->ew.last_sweeps = 0;
+    h->ew.last_closed = false;
   }
   if (in->B || in->D) {
     // B D in the sampling precision
@@ -971,6 +977,16 @@ int cmaes_enable_graphs(cmaes_t* h, int on) {
   if (int rc = check(h)) return rc;
   h->graphs = on != 0;
   drop_graphs(h);
+  return CMAES_OK;
+}
+
+int cmaes_set_eigen_correction(cmaes_t* h, int on, double max_angle_norm) {
+  if (int rc = check(h)) return rc;
+  if (!(max_angle_norm >= 0.0 && max_angle_norm <= 2e-3)) return fail(CMAES_EINVAL, "max_angle_norm not in [0, 2e-3]");
+  if (max_angle_norm != h->ew.corr_max_theta) eigen_drop_graphs(h->ew);  // captured as a kernel argument
+  h->ew.correct_on = on != 0;
+  h->ew.corr_max_theta = max_angle_norm;
+  h->ew.last_closed = false;
   return CMAES_OK;
 }
 

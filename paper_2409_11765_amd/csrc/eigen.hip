@@ -31,6 +31,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <functional>
 #include <vector>
 
 #include "internal.h"
@@ -43,6 +44,10 @@ constexpr int kNB = 16;          // indices per block
 constexpr int kS = 2 * kNB;      // pair problem size
 constexpr int kLD = kS + 1;      // LDS row stride (bank-conflict padding)
 constexpr double kOffTol = 1e-13;
+// closing correction: queued once off(A) <= kCorrOff ||A||_F, applied only if
+// the angles satisfy ||Theta||_F <= EigWork::corr_max_theta (at most 2e-3)
+constexpr double kCorrOff = 1e-8;
+constexpr int kMaxCorrections = 4;  // per solve
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
@@ -561,7 +566,8 @@ __global__ void __launch_bounds__(256) k_offnorm_cols(const double* __restrict__
 }
 
 // reduce count (off, tot, dmax) triples in a fixed order: flags[0] = 1 if more
-// sweeps are needed, flags[1] = 1 if non-finite; scale[0] = max |a_ii|.
+// sweeps are needed, flags[1] = 1 if non-finite, flags[2] = 1 if off(A) is
+// small enough for a closing correction; scale[0] = max |a_ii|.
 // flags is the device address of pinned host memory: the host reads it once
 // the stream has drained, so the stores are system-scope (written through to
 // host memory) and no copy is queued for them.
@@ -592,6 +598,8 @@ __global__ void __launch_bounds__(256) k_offnorm_final(const double* __restrict_
     __hip_atomic_store(&flags[0], (finite && red[0][0] > kOffTol * kOffTol * red[1][0]) ? 1 : 0, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(&flags[1], finite ? 0 : 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&flags[2], (finite && red[0][0] <= kCorrOff * kCorrOff * red[1][0]) ? 1 : 0,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     scale[0] = red[2][0];
   }
 }
@@ -604,6 +612,149 @@ __global__ void k_fill(double* __restrict__ A, int64_t count, double v) {
 __global__ void k_identity(double* __restrict__ V, int N) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < static_cast<int64_t>(N) * N) V[i] = (i / N == i % N) ? 1.0 : 0.0;
+}
+
+// ---- closing correction.  Once the sweeps have made A nearly diagonal,
+// rotating every index pair (i, j) at once by the angle that would
+// annihilate a_ij in its own 2 x 2 subproblem,
+//   theta_ij = atan(2 a_ij / (a_jj - a_ii)) / 2   (|theta_ij| <= pi/4),
+// is a Newton-type step: the off-diagonal norm after it is of the order of
+// its square over the relative eigenvalue gaps (Jacobi's method for
+// symmetric matrices, quadratic convergence of simultaneous rotations).
+// Theta is antisymmetric; the rotation Q = I + Theta + S/2 - S^2/8 with
+// S = Theta^2 satisfies Q^T Q = I - S^3/8 + O(Theta^8), orthogonal to rounding
+// for ||Theta||_F <= 2e-3, the acceptance bound.  A <- Q^T A Q and V <- V Q
+// then take five float64 products instead of one more sweep's 63 rounds.
+
+__global__ void k_diag(const double* __restrict__ A, int N, int n, double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = A[static_cast<int64_t>(i) * N + i];
+}
+
+// Theta over 32 x 32 tiles: workgroup (bi >= bj) reads tiles (bi, bj) and
+// (bj, bi) of A and writes both tiles of Theta and their sum of squares.
+// A is symmetric only to rounding (the sweeps' diagonal tiles and the warm
+// start are computed, not mirrored), and an angle magnifies that rounding by
+// 1 / (a_jj - a_ii); so every angle is taken from (a_ij + a_ji) / 2, the
+// same value for (i, j) and (j, i) because the sum commutes, which makes
+// Theta antisymmetric bit for bit.  Entries at or below the sweeps' rotation
+// threshold get no rotation, as in a sweep.
+constexpr int kCT = 32;
+__device__ __forceinline__ void lower_tile(int b, int& bi, int& bj) {
+  bi = 0;
+  while (b > bi) {  // lower tile index b -> (bi, bj), bj <= bi
+    b -= bi + 1;
+    ++bi;
+  }
+  bj = b;
+}
+
+__global__ void __launch_bounds__(256) k_corr_theta(const double* __restrict__ A, int N, int n,
+                                                    const double* __restrict__ d, const double* __restrict__ scale,
+                                                    double* __restrict__ Th, int ldt, double* __restrict__ part) {
+  __shared__ double tl[kCT][kCT + 1], tu[kCT][kCT + 1];
+  __shared__ double red[256];
+  int bi, bj;
+  lower_tile(blockIdx.x, bi, bj);
+  const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
+  const int r0 = bi * kCT, c0 = bj * kCT;
+  for (int k = ty; k < kCT; k += 8) {
+    // tl[tx][k] = A(r0 + tx, c0 + k), tu[tx][k] = A(c0 + tx, r0 + k)
+    tl[tx][k] = (r0 + tx < n && c0 + k < n) ? A[static_cast<int64_t>(c0 + k) * N + r0 + tx] : 0.0;
+    tu[tx][k] = (c0 + tx < n && r0 + k < n) ? A[static_cast<int64_t>(r0 + k) * N + c0 + tx] : 0.0;
+  }
+  __syncthreads();
+  const double thr = 2.2e-16 * scale[0];
+  double acc = 0.0;
+  for (int k = ty; k < kCT; k += 8) {
+    const int r = r0 + tx, c = c0 + k;
+    double th = 0.0;
+    if (r < n && c < n && r != c) {
+      const double a = 0.5 * (tl[tx][k] + tu[k][tx]);
+      if (fabs(a) > thr) {
+        const double g = r < c ? d[c] - d[r] : d[r] - d[c];  // d[max] - d[min]
+        const double h = g < 0.0 ? 0.5 * atan2(-2.0 * a, -g) : 0.5 * atan2(2.0 * a, g);
+        th = r < c ? h : -h;
+      }
+    }
+    tl[tx][k] = th;  // each thread overwrites only the entries it read
+    acc = fma(th, th, acc);
+  }
+  __syncthreads();
+  for (int k = ty; k < kCT; k += 8) {
+    if (r0 + tx < n && c0 + k < n) Th[static_cast<int64_t>(c0 + k) * ldt + r0 + tx] = tl[tx][k];
+    // the mirror tile: Theta(c0 + tx, r0 + k) = -Theta(r0 + k, c0 + tx)
+    if (bi != bj && c0 + tx < n && r0 + k < n) Th[static_cast<int64_t>(r0 + k) * ldt + c0 + tx] = -tl[k][tx];
+  }
+  red[t] = bi != bj ? 2.0 * acc : acc;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (t < s2) red[t] += red[t + s2];
+    __syncthreads();
+  }
+  if (t == 0) part[blockIdx.x] = red[0];
+}
+
+// Q = I + Theta + S/2 - S2/8 in place of Theta (rows, columns < n) if
+// ||Theta||_F^2 = sum(part) <= theta2, else Q = I, which leaves A and V
+// unchanged bit for bit.  Every workgroup reduces the count partial sums in the
+// same order, so all take the same decision; workgroup 0 reports a rejection
+// in flags[3] (pinned host memory, system-scope store).
+__global__ void __launch_bounds__(256) k_corr_q(double* __restrict__ Th, int ldt, const double* __restrict__ S,
+                                                int lds, const double* __restrict__ S2, int lds2, int n,
+                                                const double* __restrict__ part, int count, double theta2,
+                                                int* __restrict__ flags) {
+  __shared__ double red[256];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double acc = 0.0;
+  for (int i = t; i < count; i += 256) acc += part[i];
+  red[t] = acc;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (t < s2) red[t] += red[t + s2];
+    __syncthreads();
+  }
+  const double tot = red[0];
+  const bool accept = isfinite(tot) && tot <= theta2;
+  if (c == 0 && t == 0) __hip_atomic_store(&flags[3], accept ? 0 : 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  for (int r = t; r < n; r += 256) {
+    const int64_t i = static_cast<int64_t>(c) * ldt + r;
+    double v = accept ? Th[i] + 0.5 * S[static_cast<int64_t>(c) * lds + r] -
+                            0.125 * S2[static_cast<int64_t>(c) * lds2 + r]
+                      : 0.0;
+    if (r == c) v += 1.0;
+    Th[i] = v;
+  }
+}
+
+// dst = the lower triangle of src mirrored (n x n), 32 x 32 tiles through LDS:
+// workgroup (bi >= bj) reads tile (bi, bj) and writes it and its transpose
+__global__ void __launch_bounds__(256) k_sym_lower(const double* __restrict__ src, int lds, int n,
+                                                   double* __restrict__ dst, int ldd) {
+  __shared__ double tile[kCT][kCT + 1];
+  int bi, bj;
+  lower_tile(blockIdx.x, bi, bj);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int r0 = bi * kCT, c0 = bj * kCT;
+  for (int k = ty; k < kCT; k += 8) {  // tile(row tx, col k)
+    const int r = r0 + tx, c = c0 + k;
+    tile[tx][k] = (r < n && c < n) ? src[static_cast<int64_t>(c) * lds + r] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < kCT; k += 8) {
+    // (r0 + tx, c0 + k): lower of the tile, or its mirror on a diagonal tile
+    const int r = r0 + tx, c = c0 + k;
+    if (r < n && c < n) dst[static_cast<int64_t>(c) * ldd + r] = (bi == bj && tx < k) ? tile[k][tx] : tile[tx][k];
+    // transpose: (c0 + tx, r0 + k) = tile(k, tx)
+    const int r2 = c0 + tx, c2 = r0 + k;
+    if (bi != bj && r2 < n && c2 < n) dst[static_cast<int64_t>(c2) * ldd + r2] = tile[k][tx];
+  }
+}
+
+// dst[:n, :n] = src[:n, :n]
+__global__ void k_copy_block(const double* __restrict__ src, int lds, int n, double* __restrict__ dst, int ldd) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (r < n) dst[static_cast<int64_t>(c) * ldd + r] = src[static_cast<int64_t>(c) * lds + r];
 }
 
 // eigenvalue ranks (ascending, ties by index) and positive-definiteness flag;
@@ -638,6 +789,7 @@ __global__ void __launch_bounds__(256) k_eig_rank(const double* __restrict__ A, 
   if (cnt == 0) {
     sc->eig_ok = (vi > 0.0 && status[0] == 1) ? 1 : 0;
     sc->jac_sweeps = status[1];
+    sc->jac_corr = status[2];
   }
 }
 
@@ -702,6 +854,10 @@ void eigen_begin_host(EigWork& w) {
   w.Qcur = w.Q;
   w.Qnext = w.Q2;
   w.sweeps = 0;
+  w.corrections = 0;
+  w.fresh = true;
+  w.corr_queued = false;
+  w.corr_blocked = false;
   w.pending = true;
 }
 
@@ -727,10 +883,11 @@ int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B
   return 0;
 }
 
-__global__ void k_set_status(int* status, int code, int sweeps) {
+__global__ void k_set_status(int* status, int code, int sweeps, int corrections) {
   if (threadIdx.x == 0) {
     status[0] = code;
     status[1] = sweeps;
+    status[2] = corrections;
   }
 }
 
@@ -748,12 +905,15 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
   const int N = w.N;
   const int p = N / kNB, q = p / 2;
   const int ntiles = q * (q + 1) / 2;
+  if (w.corr_queued) {  // a rejected correction (its rotation was not small) is not tried again
+    if (w.hflags[3] || w.corrections >= kMaxCorrections) w.corr_blocked = true;
+    w.corr_queued = false;
+  }
   const bool more = w.hflags[0] && !w.hflags[1];
   if (more && w.sweeps < max_sweeps) {
     const int round_blocks = q + ntiles + (N / kS) * q;
-    // one sweep's launches; with from_graph they are replayed from a graph
-    // captured for this starting buffer (sweeps alternate between the two A
-    // and Q buffers because a sweep has an odd number p - 1 of rounds)
+    // one sweep's launches (sweeps alternate between the two A and Q buffers
+    // because a sweep has an odd number p - 1 of rounds)
     auto queue_sweep = [&](double* a0, double* a1, double* q0, double* q1, bool first) -> hipError_t {
       if (first) {
         kt_begin(kt, KID_JACOBI);
@@ -773,43 +933,106 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
       k_offnorm_final<<<1, 256, 0, st>>>(w.part, ntiles, w.dflags, w.scale);
       return hipGetLastError();
     };
-    // the first check queues (previous solve's sweep count - 1) sweeps at
-    // once: a warm-started solve rarely needs fewer, and while it needs at
-    // least as many the sweeps run are those of a check after every sweep
-    const int batch = w.sweeps == 0 ? std::max(1, std::min(w.last_sweeps - 1, max_sweeps)) : 1;
-    for (int i = 0; i < batch; ++i) {
-      const bool first = (w.sweeps == 0);
-      if (use_graph && !(kt && kt->on)) {
-        const int slot = first ? 2 : (w.Acur == w.A ? 0 : 1);
-        if (w.gx[slot] == nullptr || w.gstream != st) {
-          if (w.gstream != st) eigen_drop_graphs(w);
-          CMX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-          const hipError_t qe = queue_sweep(w.Acur, w.Anext, w.Qcur, w.Qnext, first);
-          hipGraph_t g = nullptr;
-          const hipError_t ce = hipStreamEndCapture(st, &g);
-          if (qe != hipSuccess || ce != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return fail(-3, std::string("sweep capture: ") + hipGetErrorString(qe != hipSuccess ? qe : ce));
-          }
-          const hipError_t ie = hipGraphInstantiate(&w.gx[slot], g, nullptr, nullptr, 0);
-          (void)hipGraphDestroy(g);
-          if (ie != hipSuccess) return fail(-3, std::string("sweep graph: ") + hipGetErrorString(ie));
-          w.gstream = st;
-        }
-        CMX_HIP(hipGraphLaunch(w.gx[slot], st));
-      } else {
-        CMX_HIP(queue_sweep(w.Acur, w.Anext, w.Qcur, w.Qnext, first));
+    // one closing correction from a0 into a1 (X1: Theta, then Q; X2: S, then
+    // A Q, then V Q; a1 holds S^2 until the result replaces it)
+    auto queue_correction = [&](double* a0, double* a1) -> hipError_t {
+      hipError_t e;
+      k_diag<<<ceil_div(n, 256), 256, 0, st>>>(a0, N, n, w.evals);
+      const int nt = ceil_div(n, kCT), ntl = nt * (nt + 1) / 2;
+      k_corr_theta<<<ntl, 256, 0, st>>>(a0, N, n, w.evals, w.scale, w.X1, N, w.part);
+      kt_begin(kt, KID_EIG_GEMM);
+      e = launch_dgemm(st, false, false, n, n, n, w.X1, N, w.X1, N, w.X2, N);  // S = Theta^2
+      kt_end(kt);
+      if (e != hipSuccess) return e;
+      kt_begin(kt, KID_EIG_GEMM);
+      e = launch_dgemm(st, false, false, n, n, n, w.X2, N, w.X2, N, a1, N);  // S^2
+      kt_end(kt);
+      if (e != hipSuccess) return e;
+      k_corr_q<<<n, 256, 0, st>>>(w.X1, N, w.X2, N, a1, N, n, w.part, ntl, w.corr_max_theta * w.corr_max_theta,
+                                  w.dflags);
+      kt_begin(kt, KID_EIG_GEMM);
+      e = launch_dgemm(st, false, false, n, n, n, a0, N, w.X1, N, w.X2, N);  // A Q
+      kt_end(kt);
+      if (e != hipSuccess) return e;
+      kt_begin(kt, KID_EIG_GEMM);
+      e = launch_dgemm(st, true, false, n, n, n, w.X1, N, w.X2, N, w.T, ldb);  // Q^T (A Q)
+      kt_end(kt);
+      if (e != hipSuccess) return e;
+      k_sym_lower<<<ntl, 256, 0, st>>>(w.T, ldb, n, a1, N);
+      kt_begin(kt, KID_EIG_GEMM);
+      e = launch_dgemm(st, false, false, n, n, n, w.V, N, w.X1, N, w.X2, N);  // V Q
+      kt_end(kt);
+      if (e != hipSuccess) return e;
+      k_copy_block<<<dim3(ceil_div(n, 256), n), 256, 0, st>>>(w.X2, N, n, w.V, N);
+      k_offnorm_cols<<<n, 256, 0, st>>>(a1, N, n, w.part);
+      k_offnorm_final<<<1, 256, 0, st>>>(w.part, n, w.dflags, w.scale);
+      return hipGetLastError();
+    };
+    // replay step `slot` from a graph captured on first use (queue() queues
+    // its launches), or queue it directly
+    auto run = [&](int slot, const std::function<hipError_t()>& queue) -> int {
+      if (!(use_graph && !(kt && kt->on))) {
+        CMX_HIP(queue());
+        return 0;
       }
+      if (w.gx[slot] == nullptr || w.gstream != st) {
+        if (w.gstream != st) eigen_drop_graphs(w);
+        CMX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const hipError_t qe = queue();
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(st, &g);
+        if (qe != hipSuccess || ce != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          return fail(-3, std::string("eigen step capture: ") + hipGetErrorString(qe != hipSuccess ? qe : ce));
+        }
+        const hipError_t ie = hipGraphInstantiate(&w.gx[slot], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return fail(-3, std::string("eigen step graph: ") + hipGetErrorString(ie));
+        w.gstream = st;
+      }
+      CMX_HIP(hipGraphLaunch(w.gx[slot], st));
+      return 0;
+    };
+    const bool from_a = (w.Acur == w.A);
+    if (w.correct_on && !w.corr_blocked && w.hflags[2]) {
+      double *a0 = w.Acur, *a1 = w.Anext;
+      if (const int rc = run(from_a ? 4 : 5, [&] { return queue_correction(a0, a1); })) return rc;
+      // the Q buffers flip with the A buffers, as in a round: the captured
+      // sweeps are keyed by the A buffer they start from and assume the
+      // matching Q buffer (the next sweep recomputes its first pair
+      // solves from A, so the Q contents do not matter)
+      std::swap(w.Acur, w.Anext);
+      std::swap(w.Qcur, w.Qnext);
+      ++w.sweeps;
+      ++w.corrections;
+      w.fresh = true;  // the pair solves the last sweep carried over are stale
+      w.corr_queued = true;
+      return 0;
+    }
+    // the first check queues as many sweeps as the previous solve ran before
+    // its closing correction (one fewer if it closed with a sweep): a
+    // warm-started solve rarely needs fewer, and while it needs at least as
+    // many the sweeps run are those of a check after every sweep
+    int batch = 1;
+    if (w.sweeps == 0) batch = std::max(1, w.last_closed ? w.last_sweeps : w.last_sweeps - 1);
+    batch = std::min(batch, max_sweeps - w.sweeps);
+    for (int i = 0; i < batch; ++i) {
+      const bool first = w.fresh;
+      const int slot = first ? (w.Acur == w.A ? 2 : 3) : (w.Acur == w.A ? 0 : 1);
+      double *a0 = w.Acur, *a1 = w.Anext, *q0 = w.Qcur, *q1 = w.Qnext;
+      if (const int rc = run(slot, [&] { return queue_sweep(a0, a1, q0, q1, first); })) return rc;
       for (int r = 0; r < p - 1; ++r) {
         std::swap(w.Acur, w.Anext);
         std::swap(w.Qcur, w.Qnext);
       }
       ++w.sweeps;
+      w.fresh = false;
     }
     return 0;
   }
   // converged (1), sweep limit (2) or non-finite (3): finish
-  k_set_status<<<1, 64, 0, st>>>(w.status, w.hflags[1] ? 3 : (w.hflags[0] ? 2 : 1), w.sweeps);
+  k_set_status<<<1, 64, 0, st>>>(w.status, w.hflags[1] ? 3 : (w.hflags[0] ? 2 : 1), w.sweeps - w.corrections,
+                                 w.corrections);
   // B_new = B V (into T), then canonical order / signs into B, D, BD
   kt_begin(kt, KID_EIG_GEMM);
   CMX_HIP(launch_dgemm(st, false, false, n, n, n, B, ldb, w.V, N, w.T, ldb));
@@ -825,7 +1048,8 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
                                            static_cast<float*>(BD), ldbd);
   CMX_HIP(hipGetLastError());
   w.pending = false;
-  w.last_sweeps = w.sweeps;
+  w.last_sweeps = w.sweeps - w.corrections;
+  w.last_closed = w.corrections > 0;
   *done = true;
   return 0;
 }

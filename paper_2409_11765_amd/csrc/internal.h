@@ -26,6 +26,8 @@ struct DevScalars {
   int32_t eig_ok;     // last eigendecomposition positive definite
   int32_t hist_count; // entries written into the f-history ring
   int32_t jac_sweeps; // sweeps used by the last eigensolve
+  int32_t jac_corr;   // closing corrections among them
+  int32_t pad_;
 };
 
 // Strategy parameters passed by value to kernels.
@@ -188,21 +190,33 @@ struct EigWork {
   double* Q;      // (N/32) * 32*32, ping-pong with Q2
   double* Q2;
   double* T;      // n*n scratch
+  double* X1;     // N*N: angles, then the correction's rotation
+  double* X2;     // N*N: products of the correction
   double* evals;  // N
   int32_t* perm;  // N
   double* sign;   // N
   double* part;   // 3 * max(n, tiles) partial sums
   double* scale;  // max |a_ii|
   int* status;    // [0] 1 converged, 2 sweep limit, 3 non-finite; [1] sweeps
-  int* hflags;    // pinned host memory: [0] more sweeps needed, [1] non-finite
+  int* hflags;    // pinned host memory: [0] more sweeps needed, [1] non-finite,
+                  // [2] off(A) small enough for a closing correction, [3] the last
+                  // correction was rejected (its rotation was not small)
   int* dflags;    // device address of hflags (written by the convergence test)
   // progress of the eigensolve in flight
   double *Acur, *Anext, *Qcur, *Qnext;
-  int sweeps;
-  int last_sweeps;  // sweeps of the previous solve (0: none, or B replaced)
+  int sweeps;       // sweeps and corrections queued so far
+  int corrections;  // closing corrections among them
+  int last_sweeps;  // sweeps (not corrections) of the previous solve (0: none, or B replaced)
+  bool last_closed; // the previous solve ended with a correction
+  bool fresh;       // the next sweep starts from A alone (no pair solves carried over)
+  bool corr_queued; // the last step queued was a correction
+  bool corr_blocked;  // a correction was rejected: sweeps only for the rest of this solve
+  bool correct_on = true;  // closing corrections enabled
+  double corr_max_theta = 2e-3;  // acceptance bound on ||Theta||_F (graphs capture it)
   bool pending;
-  // captured sweeps: [0] starting from A, [1] from A2, [2] the first sweep
-  hipGraphExec_t gx[3];
+  // captured steps: [0] sweep from A, [1] from A2, [2] first sweep from A,
+  // [3] from A2, [4] correction from A, [5] from A2
+  hipGraphExec_t gx[6];
   hipStream_t gstream;
 };
 // Queue the warm start and the first convergence test; the host then

@@ -1,0 +1,156 @@
+"""GPU tests of the eigensolve's closing correction (C = B D^2 B^T, Sec. 2.1).
+
+Once the block-Jacobi sweeps have brought off(A) below 1e-8 of ||A||_F, the
+library rotates every index pair at once by its 2 x 2 Jacobi angle instead of
+running one more sweep.  Whatever closes the solve, the decomposition must meet
+the same bar as a sweeps-only solve: C = B D^2 B^T and B^T B = I to 1e-12,
+eigenvalues equal to a library eigensolver's, and from the same state the
+same eigenvalues and (where they are separated) eigenvectors as a sweeps-only
+solve.  A correction whose angles are too
+large for the rotation to be orthogonal is rejected (exact no-op) and the solve
+finishes with sweeps; an acceptance bound of 0 forces that path here.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_11765_amd as P
+    return P
+
+
+def check_decomposition(s, tol=1e-12):
+    C, B, D = s["C"], s["B"], s["D"]
+    n = C.shape[0]
+    rec = float(np.linalg.norm(B @ np.diag(D ** 2) @ B.T - C) / np.linalg.norm(C))
+    assert rec <= tol, rec
+    orth = float(np.max(np.abs(B.T @ B - np.eye(n))))
+    assert orth <= tol, orth
+    ev = np.linalg.eigvalsh(0.5 * (C + C.T))
+    assert np.max(np.abs(D ** 2 - ev)) <= tol * np.max(np.abs(ev))
+    assert np.all(np.diff(D) >= 0)
+
+
+def run(P, n, lam, precision, objective, gens, on=True, bound=2e-3, seed=1, graphs=True):
+    """Run `gens` generations with an eigensolve each; returns the final state
+    and the (sweeps, corrections) of every generation's eigensolve."""
+    R, xs = synth.problem(n, seed=1)
+    hist = []
+    with P.CMAES(n, lam, 2.0, seed=seed, precision=precision, objective=objective, R=R, xstar=xs,
+                 eigen_interval=1) as es:
+        es.set_eigen_correction(on, bound)
+        es.enable_graphs(graphs)
+        for _ in range(gens):
+            es.generation()
+            s = es.state(arrays=False)
+            hist.append((s["eig_sweeps"], s["eig_corrections"]))
+        return es.state(), hist
+
+
+@pytest.mark.parametrize("n,lam,precision,objective", [(1000, 2048, "mixed", "rastrigin"),
+                                                       (400, 800, "fp64", "ellipsoid"),
+                                                       (130, 301, "fp64", "rastrigin"),
+                                                       (37, 53, "mixed", "sphere")])
+def test_correction_closes_warm_started_solves(P, n, lam, precision, objective):
+    print(f"case closing correction n={n} lam={lam} {precision} {objective}", flush=True)
+    s, hist = run(P, n, lam, precision, objective, 30)
+    assert s["stop"] == 0
+    check_decomposition(s)
+    corr = [c for _, c in hist]
+    assert all(0 <= c <= 4 for c in corr)
+    if n >= 400:  # warm-started solves of this size end in the quadratic regime
+        assert sum(c > 0 for c in corr) >= 10, hist
+
+
+def one_generation_from(P, s0, objective, on, bound=2e-3):
+    """One generation from the injected state s0 (same C update, same draws);
+    only the way the eigensolve is closed differs between calls."""
+    n = s0["n"]
+    R, xs = synth.problem(n, seed=1)
+    with P.CMAES(n, s0["lambda"], 2.0, seed=1, precision="fp64", objective=objective, R=R, xstar=xs,
+                 eigen_interval=1) as es:
+        es.set_state(s0)
+        es.set_eigen_correction(on, bound)
+        es.generation()
+        return es.state()
+
+
+def compare_closings(s_a, s_b):
+    """Both decompositions of the same C: equal eigenvalues, and equal
+    eigenvectors where the eigenvalues are separated (inside a near-multiple
+    eigenvalue the basis is not unique; off(A) / gap decides how far apart
+    two correct bases may be)."""
+    for k in ("m", "C", "p_sigma", "p_c"):
+        assert np.array_equal(s_a[k], s_b[k]), k
+    check_decomposition(s_a)
+    check_decomposition(s_b)
+    ev = s_b["D"] ** 2
+    assert np.max(np.abs(s_a["D"] ** 2 - ev)) <= 1e-12 * np.max(ev)
+    gaps = np.minimum(np.r_[np.inf, np.diff(ev)], np.r_[np.diff(ev), np.inf])
+    ok = gaps > 1e-6 * np.max(ev)
+    assert ok.sum() >= len(ev) // 2
+    assert np.max(np.abs(s_a["B"][:, ok] - s_b["B"][:, ok])) < 1e-8
+
+
+@pytest.mark.parametrize("n,lam,objective,warm", [(300, 600, "ellipsoid", 25), (1000, 2048, "rastrigin", 20)])
+def test_correction_and_sweeps_agree_on_one_generation(P, n, lam, objective, warm):
+    """From the same state, a solve closed by the correction and a sweeps-only
+    solve decompose the same C alike."""
+    print(f"case correction on/off n={n} lam={lam}", flush=True)
+    s0, _ = run(P, n, lam, "fp64", objective, warm)
+    s_on = one_generation_from(P, s0, objective, True)
+    s_off = one_generation_from(P, s0, objective, False)
+    assert s_on["eig_corrections"] >= 1 and s_off["eig_corrections"] == 0
+    compare_closings(s_on, s_off)
+
+
+def test_rejected_correction_falls_back_to_sweeps(P):
+    """Acceptance bound 0: the correction is rejected and leaves A as it was;
+    the solve then finishes with sweeps (one attempt per solve at most)."""
+    n, lam = 400, 800
+    print(f"case rejected correction n={n} lam={lam}", flush=True)
+    s_rej_run, h_rej = run(P, n, lam, "fp64", "ellipsoid", 20, on=True, bound=0.0)
+    assert any(c == 1 for _, c in h_rej), h_rej
+    assert all(c <= 1 for _, c in h_rej), h_rej
+    check_decomposition(s_rej_run)
+    s0, _ = run(P, n, lam, "fp64", "ellipsoid", 20)
+    s_rej = one_generation_from(P, s0, "ellipsoid", True, bound=0.0)
+    s_off = one_generation_from(P, s0, "ellipsoid", False)
+    assert s_rej["eig_corrections"] == 1
+    compare_closings(s_rej, s_off)
+
+
+@pytest.mark.parametrize("bound", [2e-3, 0.0])
+def test_correction_graph_replay_bit_identical(P, bound):
+    """Corrections and the sweeps after them, replayed from captured graphs,
+    give the eager launches' bits.  With bound 0 every correction is rejected,
+    so sweeps follow a correction inside each solve: the captured sweeps must
+    then start from the buffers the correction left (a correction flips the A
+    and the pair-rotation buffers together, as a round does)."""
+    n, lam = 400, 800
+    print(f"case correction graphs n={n} lam={lam} bound={bound}", flush=True)
+    s_g, h_g = run(P, n, lam, "mixed", "rastrigin", 25, bound=bound, graphs=True)
+    s_e, h_e = run(P, n, lam, "mixed", "rastrigin", 25, bound=bound, graphs=False)
+    assert h_g == h_e
+    assert any(c > 0 for _, c in h_g), h_g
+    for k in ("m", "C", "B", "D", "p_sigma", "p_c", "f"):
+        assert np.array_equal(s_g[k], s_e[k]), k
+
+
+def test_set_eigen_correction_checks_its_bound(P):
+    with P.CMAES(8, 8, 1.0, seed=1, objective="sphere") as es:
+        for bad in (-1e-3, 2.5e-3, float("nan")):
+            with pytest.raises(P.CmaesError) as e:
+                es.set_eigen_correction(True, bad)
+            assert e.value.code == -1
+        es.set_eigen_correction(False, 1e-3)
+        es.set_eigen_correction(True, 2e-3)
