@@ -24,8 +24,10 @@
 //     Rotation angles are formed in float32 (they only set how far an entry
 //     is reduced); cosines and sines are float64 and orthogonal to rounding.
 //     Sweeps stop when the off-diagonal Frobenius norm of A falls below
-//     1e-13 of its total norm (summed per tile by the last round).
-//  3. B = B_old V, D = sqrt(diag A), then the pairs are canonicalised like the
+//     1e-13 of its total norm (summed per tile by the last round); once it
+//     is below 1e-8, a closing correction (below) takes the last sweep's place.
+//     V starts as B_old, so the rotations land straight in B = B_old V.
+//  3. D = sqrt(diag A), then the pairs are canonicalised like the
 //     oracle: ascending eigenvalues, each column's largest-magnitude entry
 //     positive.  B D is also written in the sampling precision.
 #include <hip/hip_ext.h>
@@ -609,9 +611,13 @@ __global__ void k_fill(double* __restrict__ A, int64_t count, double v) {
   if (i < count) A[i] = v;
 }
 
-__global__ void k_identity(double* __restrict__ V, int N) {
+// V = [B_old 0; 0 I] (N x N): the rotations are accumulated straight into the
+// previous eigenvectors, so the new ones need no final product B_old V
+__global__ void k_init_v(double* __restrict__ V, int N, int n, const double* __restrict__ B, int ldb) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < static_cast<int64_t>(N) * N) V[i] = (i / N == i % N) ? 1.0 : 0.0;
+  if (i >= static_cast<int64_t>(N) * N) return;
+  const int r = static_cast<int>(i % N), c = static_cast<int>(i / N);
+  V[i] = (r < n && c < n) ? B[static_cast<int64_t>(c) * ldb + r] : (r == c ? 1.0 : 0.0);
 }
 
 // ---- closing correction.  Once the sweeps have made A nearly diagonal,
@@ -868,7 +874,7 @@ int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B
   eigen_begin_host(w);
   k_fill<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.Acur, NN, 0.0);
   k_fill<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.Anext, NN, 0.0);
-  k_identity<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.V, N);
+  k_init_v<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.V, N, n, B, ldb);
   CMX_HIP(hipGetLastError());
   kt_begin(kt, KID_EIG_GEMM);
   CMX_HIP(launch_dgemm(st, false, false, n, n, n, C, ldc, B, ldb, w.T, ldb));   // T = C B
@@ -1033,18 +1039,15 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
   // converged (1), sweep limit (2) or non-finite (3): finish
   k_set_status<<<1, 64, 0, st>>>(w.status, w.hflags[1] ? 3 : (w.hflags[0] ? 2 : 1), w.sweeps - w.corrections,
                                  w.corrections);
-  // B_new = B V (into T), then canonical order / signs into B, D, BD
-  kt_begin(kt, KID_EIG_GEMM);
-  CMX_HIP(launch_dgemm(st, false, false, n, n, n, B, ldb, w.V, N, w.T, ldb));
-  kt_end(kt);
+  // V holds B_new = B_old V_rot: canonical order / signs into B, D, BD
   k_eig_rank<<<ceil_div(n, 256 / kRankTPI), 256, 0, st>>>(w.Acur, N, n, w.perm, w.evals, w.status, sc);
-  k_colsign<<<n, 256, 0, st>>>(w.T, ldb, n, w.sign);
+  k_colsign<<<n, 256, 0, st>>>(w.V, N, n, w.sign);
   dim3 grid(ceil_div(n, 256), n);
   if (fp64_bd)
-    k_permute<double><<<grid, 256, 0, st>>>(w.T, ldb, n, w.perm, w.evals, w.sign, B, ldb, D,
+    k_permute<double><<<grid, 256, 0, st>>>(w.V, N, n, w.perm, w.evals, w.sign, B, ldb, D,
                                             static_cast<double*>(BD), ldbd);
   else
-    k_permute<float><<<grid, 256, 0, st>>>(w.T, ldb, n, w.perm, w.evals, w.sign, B, ldb, D,
+    k_permute<float><<<grid, 256, 0, st>>>(w.V, N, n, w.perm, w.evals, w.sign, B, ldb, D,
                                            static_cast<float*>(BD), ldbd);
   CMX_HIP(hipGetLastError());
   w.pending = false;
