@@ -511,12 +511,23 @@ void advance_counters(cmaes* h) {
 
 // one step of the eigensolve in flight (the stream must have been
 // synchronised since the last call); *done once the decomposition is final
-int eigen_advance(cmaes* h, bool* done) {
+int eigen_advance(cmaes* h, bool* done, bool ahead = false) {
   // a decomposition that does not converge within the sweep limit (or meets
   // non-finite values) clears eig_ok on the device, which raises the
   // ConditionCov stop bit
   return eigen_step(h->st, h->n, h->B, h->ldn, h->D, h->BD, h->fp64, h->ldn, h->ew, h->sc, 40, &h->kt,
-                    h->graphs && h->st != nullptr && !h->timing, done);
+                    h->graphs && h->st != nullptr && !h->timing, done, ahead);
+}
+// the eigensolve of the generation just queued: its first batch of sweeps
+// goes in behind the warm start, then one host check per step
+int eigen_run(cmaes* h) {
+  bool done = false;
+  if (int rc = eigen_advance(h, &done, true)) return rc;
+  while (!done) {
+    CMX_HIP(hipStreamSynchronize(h->st));
+    if (int rc = eigen_advance(h, &done)) return rc;
+  }
+  return 0;
 }
 
 // stop tests, then fold the optional timers
@@ -550,10 +561,7 @@ int phase_update(cmaes* h) {
   if (int rc = phase_update_pre(h)) return rc;
   advance_counters(h);
   if (h->eig_due) {
-    for (bool done = false; !done;) {
-      CMX_HIP(hipStreamSynchronize(h->st));
-      if (int rc = eigen_advance(h, &done)) return rc;
-    }
+    if (int rc = eigen_run(h)) return rc;
   }
   return phase_update_post(h);
 }
@@ -782,10 +790,7 @@ int cmaes_generation(cmaes_t* h) {
   if (int rc = ensure_ready(h)) return rc;
   if (int rc = front(h)) return rc;
   if (h->eig_due) {
-    for (bool done = false; !done;) {
-      CMX_HIP(hipStreamSynchronize(h->st));
-      if (int rc = eigen_advance(h, &done)) return rc;
-    }
+    if (int rc = eigen_run(h)) return rc;
   }
   return phase_update_post(h);
 }
@@ -1172,7 +1177,11 @@ int lockstep_generation(const std::vector<cmaes*>& hs) {
   }
   std::vector<cmaes*> pending;
   for (cmaes* h : hs)
-    if (h->eig_due) pending.push_back(h);
+    if (h->eig_due) {
+      bool done = false;
+      if (int rc = eigen_advance(h, &done, true)) return rc;  // first batch, no wait
+      pending.push_back(h);
+    }
   while (!pending.empty()) {
     for (cmaes* h : pending) CMX_HIP(hipStreamSynchronize(h->st));
     std::vector<cmaes*> still;

@@ -606,18 +606,19 @@ __global__ void __launch_bounds__(256) k_offnorm_final(const double* __restrict_
   }
 }
 
-__global__ void k_fill(double* __restrict__ A, int64_t count, double v) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < count) A[i] = v;
-}
-
-// V = [B_old 0; 0 I] (N x N): the rotations are accumulated straight into the
-// previous eigenvectors, so the new ones need no final product B_old V
-__global__ void k_init_v(double* __restrict__ V, int N, int n, const double* __restrict__ B, int ldb) {
+// Set-up of a solve, one pass over N x N: both A buffers cleared (their
+// padded rows and columns must be zero; a solve that met non-finite values
+// can leave NaN there) and V = [B_old 0; 0 I]: the rotations are accumulated
+// straight into the previous eigenvectors, so the new ones need no final
+// product B_old V
+__global__ void k_init_solve(double* __restrict__ V, double* __restrict__ A0, double* __restrict__ A1, int N, int n,
+                             const double* __restrict__ B, int ldb) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= static_cast<int64_t>(N) * N) return;
   const int r = static_cast<int>(i % N), c = static_cast<int>(i / N);
   V[i] = (r < n && c < n) ? B[static_cast<int64_t>(c) * ldb + r] : (r == c ? 1.0 : 0.0);
+  A0[i] = 0.0;
+  A1[i] = 0.0;
 }
 
 // ---- closing correction.  Once the sweeps have made A nearly diagonal,
@@ -872,9 +873,7 @@ int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B
   const int N = w.N;
   const int64_t NN = static_cast<int64_t>(N) * N;
   eigen_begin_host(w);
-  k_fill<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.Acur, NN, 0.0);
-  k_fill<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.Anext, NN, 0.0);
-  k_init_v<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.V, N, n, B, ldb);
+  k_init_solve<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.V, w.Acur, w.Anext, N, n, B, ldb);
   CMX_HIP(hipGetLastError());
   kt_begin(kt, KID_EIG_GEMM);
   CMX_HIP(launch_dgemm(st, false, false, n, n, n, C, ldc, B, ldb, w.T, ldb));   // T = C B
@@ -906,16 +905,21 @@ void eigen_drop_graphs(EigWork& w) {
 }
 
 int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, bool fp64_bd, int ldbd, EigWork& w,
-               DevScalars* sc, int max_sweeps, KTimer* kt, bool use_graph, bool* done) {
+               DevScalars* sc, int max_sweeps, KTimer* kt, bool use_graph, bool* done, bool ahead) {
   *done = false;
   const int N = w.N;
   const int p = N / kNB, q = p / 2;
   const int ntiles = q * (q + 1) / 2;
-  if (w.corr_queued) {  // a rejected correction (its rotation was not small) is not tried again
+  // ahead: the first batch of a warm-started solve, queued behind the warm
+  // start before its flags are read (a solve after one that took several
+  // sweeps needs at least that batch; on a converged or non-finite warm
+  // start the extra sweeps change nothing that the next check does not see)
+  if (ahead && (w.sweeps != 0 || w.last_sweeps < 2)) return 0;
+  if (!ahead && w.corr_queued) {  // a rejected correction (its rotation was not small) is not tried again
     if (w.hflags[3] || w.corrections >= kMaxCorrections) w.corr_blocked = true;
     w.corr_queued = false;
   }
-  const bool more = w.hflags[0] && !w.hflags[1];
+  const bool more = ahead || (w.hflags[0] && !w.hflags[1]);
   if (more && w.sweeps < max_sweeps) {
     const int round_blocks = q + ntiles + (N / kS) * q;
     // one sweep's launches (sweeps alternate between the two A and Q buffers
@@ -1000,7 +1004,7 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
       return 0;
     };
     const bool from_a = (w.Acur == w.A);
-    if (w.correct_on && !w.corr_blocked && w.hflags[2]) {
+    if (!ahead && w.correct_on && !w.corr_blocked && w.hflags[2]) {
       double *a0 = w.Acur, *a1 = w.Anext;
       if (const int rc = run(from_a ? 4 : 5, [&] { return queue_correction(a0, a1); })) return rc;
       // the Q buffers flip with the A buffers, as in a round: the captured

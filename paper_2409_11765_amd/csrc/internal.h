@@ -225,8 +225,10 @@ struct EigWork {
 int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B, int ldb, EigWork& w, KTimer* kt);
 // the host-side part of eigen_begin alone (after replaying its launches from a graph)
 void eigen_begin_host(EigWork& w);
+// ahead = true: queue the first batch of sweeps of a warm-started solve
+// without reading the flags (no synchronisation needed; a no-op otherwise)
 int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, bool fp64_bd, int ldbd, EigWork& w,
-               DevScalars* sc, int max_sweeps, KTimer* kt, bool use_graph, bool* done);
+               DevScalars* sc, int max_sweeps, KTimer* kt, bool use_graph, bool* done, bool ahead = false);
 // release the captured sweep graphs (the stream or the buffers change)
 void eigen_drop_graphs(EigWork& w);
 
