@@ -944,7 +944,7 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
       return hipGetLastError();
     };
     // one closing correction from a0 into a1 (X1: Theta, then Q; X2: S, then
-    // A Q, then V Q; a1 holds S^2 until the result replaces it)
+    // A Q; a1: S^2, then V Q, then the result)
     auto queue_correction = [&](double* a0, double* a1) -> hipError_t {
       hipError_t e;
       k_diag<<<ceil_div(n, 256), 256, 0, st>>>(a0, N, n, w.evals);
@@ -961,19 +961,15 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
       k_corr_q<<<n, 256, 0, st>>>(w.X1, N, w.X2, N, a1, N, n, w.part, ntl, w.corr_max_theta * w.corr_max_theta,
                                   w.dflags);
       kt_begin(kt, KID_EIG_GEMM);
-      e = launch_dgemm(st, false, false, n, n, n, a0, N, w.X1, N, w.X2, N);  // A Q
+      e = launch_dgemm2(st, n, n, n, a0, N, w.V, N, w.X1, N, w.X2, N, a1, N);  // A Q and V Q
       kt_end(kt);
       if (e != hipSuccess) return e;
+      k_copy_block<<<dim3(ceil_div(n, 256), n), 256, 0, st>>>(a1, N, n, w.V, N);
       kt_begin(kt, KID_EIG_GEMM);
       e = launch_dgemm(st, true, false, n, n, n, w.X1, N, w.X2, N, w.T, ldb);  // Q^T (A Q)
       kt_end(kt);
       if (e != hipSuccess) return e;
       k_sym_lower<<<ntl, 256, 0, st>>>(w.T, ldb, n, a1, N);
-      kt_begin(kt, KID_EIG_GEMM);
-      e = launch_dgemm(st, false, false, n, n, n, w.V, N, w.X1, N, w.X2, N);  // V Q
-      kt_end(kt);
-      if (e != hipSuccess) return e;
-      k_copy_block<<<dim3(ceil_div(n, 256), n), 256, 0, st>>>(w.X2, N, n, w.V, N);
       k_offnorm_cols<<<n, 256, 0, st>>>(a1, N, n, w.part);
       k_offnorm_final<<<1, 256, 0, st>>>(w.part, n, w.dflags, w.scale);
       return hipGetLastError();

@@ -337,6 +337,50 @@ __global__ void __launch_bounds__(512) k_dgemm_kg(int M, int N, int K, const dou
   epi(acc, M, N, m0, n0, As);
 }
 
+// two independent products of one shape in one launch (two tiles per CU at
+// n ~ 1000 instead of one, so twice the waves hide the MFMA and LDS latency);
+// each tile is computed exactly as by k_dgemm_kg
+struct DProb {
+  const double* A;
+  int lda;
+  const double* B;
+  int ldb;
+  double* C;
+  int ldc;
+};
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(512) k_dgemm_kg2(int M, int N, int K, DProb p0, DProb p1) {
+  using C = Cfg<double>;
+  __shared__ double As[C::BK * (C::BM + C::PAD)];
+  __shared__ double Bs[C::BK * (C::BN + C::PAD)];
+  __shared__ double fold[4 * 4 * C::NACC * 64];
+  const int tiles_m = (M + C::BM - 1) / C::BM, tiles = tiles_m * ((N + C::BN - 1) / C::BN);
+  const int t = blockIdx.x % tiles;
+  const DProb pr = blockIdx.x < tiles ? p0 : p1;
+  const int m0 = (t % tiles_m) * C::BM;
+  const int n0 = (t / tiles_m) * C::BN;
+  typename C::acc_t acc[2][2];
+  gemm_mainloop<double, TA, TB, 512>(M, N, K, pr.A, pr.lda, pr.B, pr.ldb, m0, n0, As, Bs, acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wq = wave & 3;
+  if (wave >= 4) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < C::NACC; ++r) fold[(((r * 4 + wq) * 2 + i) * 2 + j) * 64 + lane] = acc[i][j][r];
+  }
+  __syncthreads();
+  if (wave >= 4) return;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < C::NACC; ++r) acc[i][j][r] += fold[(((r * 4 + wq) * 2 + i) * 2 + j) * 64 + lane];
+  EpiStore<double>{pr.C, pr.ldc}(acc, M, N, m0, n0, As);
+}
+
 __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
   tm = static_cast<int>((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
   while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
@@ -662,6 +706,16 @@ hipError_t launch_dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, c
   else if (ta && !tb) k_dgemm_kg<true, false><<<tiles, 512, 0, st>>>(M, N, K, A, lda, B, ldb, e);
   else if (!ta && tb) k_dgemm_kg<false, true><<<tiles, 512, 0, st>>>(M, N, K, A, lda, B, ldb, e);
   else k_dgemm_kg<true, true><<<tiles, 512, 0, st>>>(M, N, K, A, lda, B, ldb, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_dgemm2(hipStream_t st, int M, int N, int K, const double* A0, int lda0, const double* A1,
+                         int lda1, const double* B, int ldb, double* C0, int ldc0, double* C1, int ldc1) {
+  using Cf = Cfg<double>;
+  const int tiles = ceil_div(M, Cf::BM) * ceil_div(N, Cf::BN);
+  if (tiles == 0) return hipSuccess;
+  k_dgemm_kg2<false, false><<<2 * tiles, 512, 0, st>>>(M, N, K, DProb{A0, lda0, B, ldb, C0, ldc0},
+                                                      DProb{A1, lda1, B, ldb, C1, ldc1});
   return hipGetLastError();
 }
 
