@@ -186,41 +186,41 @@ hipError_t launch_dgemm2(hipStream_t st, int M, int N, int K, const double* A0, 
 
 // eigensolver
 struct EigWork {
-  int N;          // padded size (multiple of 32)
-  double* A;      // N*N, ping-pong with A2
-  double* A2;     // N*N
-  double* V;      // N*N
-  double* Q;      // (N/32) * 32*32, ping-pong with Q2
-  double* Q2;
-  double* T;      // n*n scratch
-  double* X1;     // N*N: angles, then the correction's rotation
-  double* X2;     // N*N: products of the correction
-  double* evals;  // N
-  int32_t* perm;  // N
-  double* sign;   // N
-  double* part;   // 3 * max(n, tiles) partial sums
-  double* scale;  // max |a_ii|
-  int* status;    // [0] 1 converged, 2 sweep limit, 3 non-finite; [1] sweeps
-  int* hflags;    // pinned host memory: [0] more sweeps needed, [1] non-finite,
+  int N = 0;      // padded size (multiple of 32)
+  double* A = nullptr;   // N*N, ping-pong with A2
+  double* A2 = nullptr;  // N*N
+  double* V = nullptr;   // N*N
+  double* Q = nullptr;   // (N/32) * 32*32, ping-pong with Q2
+  double* Q2 = nullptr;
+  double* T = nullptr;   // n*n scratch
+  double* X1 = nullptr;  // N*N: angles, then the correction's rotation
+  double* X2 = nullptr;  // N*N: products of the correction
+  double* evals = nullptr;  // N
+  int32_t* perm = nullptr;  // N
+  double* sign = nullptr;   // N
+  double* part = nullptr;   // 3 * max(n, tiles) partial sums
+  double* scale = nullptr;  // max |a_ii|
+  int* status = nullptr;  // [0] 1 converged, 2 sweep limit, 3 non-finite; [1] sweeps; [2] corrections
+  int* hflags = nullptr;  // pinned host memory: [0] more sweeps needed, [1] non-finite,
                   // [2] off(A) small enough for a closing correction, [3] the last
                   // correction was rejected (its rotation was not small)
-  int* dflags;    // device address of hflags (written by the convergence test)
+  int* dflags = nullptr;  // device address of hflags (written by the convergence test)
   // progress of the eigensolve in flight
-  double *Acur, *Anext, *Qcur, *Qnext;
-  int sweeps;       // sweeps and corrections queued so far
-  int corrections;  // closing corrections among them
-  int last_sweeps;  // sweeps (not corrections) of the previous solve (0: none, or B replaced)
-  bool last_closed; // the previous solve ended with a correction
-  bool fresh;       // the next sweep starts from A alone (no pair solves carried over)
-  bool corr_queued; // the last step queued was a correction
-  bool corr_blocked;  // a correction was rejected: sweeps only for the rest of this solve
+  double *Acur = nullptr, *Anext = nullptr, *Qcur = nullptr, *Qnext = nullptr;
+  int sweeps = 0;   // sweeps and corrections queued so far
+  int corrections = 0;  // closing corrections among them
+  int last_sweeps = 0;  // sweeps (not corrections) of the previous solve (0: none, or B replaced)
+  bool last_closed = false;  // the previous solve ended with a correction
+  bool fresh = true;  // the next sweep starts from A alone (no pair solves carried over)
+  bool corr_queued = false;  // the last step queued was a correction
+  bool corr_blocked = false;  // a correction was rejected: sweeps only for the rest of this solve
   bool correct_on = true;  // closing corrections enabled
   double corr_max_theta = 2e-3;  // acceptance bound on ||Theta||_F (graphs capture it)
-  bool pending;
+  bool pending = false;
   // captured steps: [0] sweep from A, [1] from A2, [2] first sweep from A,
   // [3] from A2, [4] correction from A, [5] from A2
-  hipGraphExec_t gx[6];
-  hipStream_t gstream;
+  hipGraphExec_t gx[6] = {};
+  hipStream_t gstream = nullptr;
 };
 // Queue the warm start and the first convergence test; the host then
 // synchronises the stream and calls eigen_step until it reports done (each
