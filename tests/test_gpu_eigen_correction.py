@@ -154,3 +154,33 @@ def test_set_eigen_correction_checks_its_bound(P):
             assert e.value.code == -1
         es.set_eigen_correction(False, 1e-3)
         es.set_eigen_correction(True, 2e-3)
+
+
+def test_non_finite_covariance_after_warm_solves(P):
+    """A non-finite C in the middle of a descent whose solves take several
+    sweeps: the first batch of sweeps is then queued before the warm start's
+    flags are read, runs on NaN, and the solve must still end with the
+    descent stopped (no hang, no error); a restart then decomposes correctly,
+    the solve's set-up having cleared what the NaN left in the A buffers."""
+    n, lam = 64, 128
+    print(f"case non-finite C n={n} lam={lam}", flush=True)
+    R, xs = synth.problem(n, seed=1)
+    with P.CMAES(n, lam, 2.0, seed=1, precision="fp64", objective="ellipsoid", R=R, xstar=xs,
+                 eigen_interval=1) as es:
+        for _ in range(6):
+            es.generation()
+        s = es.state()
+        assert s["eig_sweeps"] >= 2 and s["stop"] == 0
+        C = s["C"].copy()
+        C[3, 5] = C[5, 3] = np.nan
+        es.set_state({"n": n, "lambda": lam, "gen": s["gen"], "sigma": s["sigma"], "C": C})
+        es.generation()
+        stop = es.state(arrays=False)["stop"]
+        bits = {name: 1 << i for i, name in enumerate(P.STOP_BITS)}
+        assert stop & (bits["numeric"] | bits["conditioncov"]), stop
+        es.restart_ipop()
+        for _ in range(5):
+            es.generation()
+        s3 = es.state()
+    assert s3["stop"] == 0
+    check_decomposition(s3)
