@@ -476,10 +476,12 @@ int phase_update_pre(cmaes* h) {
     // rotations (B = B_old V); one Newton-Schulz step B <- B (3 I - B^T B) / 2
     // removes the accumulated drift (to second order) before the warm start
     kt_begin(&h->kt, KID_EIG_GEMM);
-    CMX_HIP(launch_dgemm(h->st, true, false, n, n, n, h->B, ldn, h->B, ldn, h->ew.A2, h->ew.N));  // G = B^T B
+    CMX_HIP(launch_dgemm_ksplit(h->st, true, false, n, n, n, h->B, ldn, h->B, ldn, h->ew.A2, h->ew.N, h->ew.X2,
+                                h->ew.N));  // G = B^T B
     kt_end(&h->kt);
     kt_begin(&h->kt, KID_EIG_GEMM);
-    CMX_HIP(launch_dgemm(h->st, false, false, n, n, n, h->B, ldn, h->ew.A2, h->ew.N, h->ew.T, ldn));  // T = B G
+    CMX_HIP(launch_dgemm_ksplit(h->st, false, false, n, n, n, h->B, ldn, h->ew.A2, h->ew.N, h->ew.T, ldn, h->ew.X2,
+                                h->ew.N));  // T = B G
     kt_end(&h->kt);
     CMX_HIP(launch_polar_step(h->st, n, h->B, ldn, h->ew.T, ldn));
   }

@@ -876,10 +876,10 @@ int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B
   k_init_solve<<<static_cast<int>((NN + 255) / 256), 256, 0, st>>>(w.V, w.Acur, w.Anext, N, n, B, ldb);
   CMX_HIP(hipGetLastError());
   kt_begin(kt, KID_EIG_GEMM);
-  CMX_HIP(launch_dgemm(st, false, false, n, n, n, C, ldc, B, ldb, w.T, ldb));   // T = C B
+  CMX_HIP(launch_dgemm_ksplit(st, false, false, n, n, n, C, ldc, B, ldb, w.T, ldb, w.X2, N));   // T = C B
   kt_end(kt);
   kt_begin(kt, KID_EIG_GEMM);
-  CMX_HIP(launch_dgemm(st, true, false, n, n, n, B, ldb, w.T, ldb, w.Acur, N));   // A = B^T T
+  CMX_HIP(launch_dgemm_ksplit(st, true, false, n, n, n, B, ldb, w.T, ldb, w.Acur, N, w.X2, N));   // A = B^T T
   kt_end(kt);
   k_offnorm_cols<<<n, 256, 0, st>>>(w.Acur, N, n, w.part);
   k_offnorm_final<<<1, 256, 0, st>>>(w.part, n, w.dflags, w.scale);
@@ -944,18 +944,19 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
       return hipGetLastError();
     };
     // one closing correction from a0 into a1 (X1: Theta, then Q; X2: S, then
-    // A Q; a1: S^2, then V Q, then the result)
+    // A Q; a1: S^2, then V Q, then the result; the k-split products use a1 or
+    // T as scratch while those are free)
     auto queue_correction = [&](double* a0, double* a1) -> hipError_t {
       hipError_t e;
       k_diag<<<ceil_div(n, 256), 256, 0, st>>>(a0, N, n, w.evals);
       const int nt = ceil_div(n, kCT), ntl = nt * (nt + 1) / 2;
       k_corr_theta<<<ntl, 256, 0, st>>>(a0, N, n, w.evals, w.scale, w.X1, N, w.part);
       kt_begin(kt, KID_EIG_GEMM);
-      e = launch_dgemm(st, false, false, n, n, n, w.X1, N, w.X1, N, w.X2, N);  // S = Theta^2
+      e = launch_dgemm_ksplit(st, false, false, n, n, n, w.X1, N, w.X1, N, w.X2, N, a1, N);  // S = Theta^2
       kt_end(kt);
       if (e != hipSuccess) return e;
       kt_begin(kt, KID_EIG_GEMM);
-      e = launch_dgemm(st, false, false, n, n, n, w.X2, N, w.X2, N, a1, N);  // S^2
+      e = launch_dgemm_ksplit(st, false, false, n, n, n, w.X2, N, w.X2, N, a1, N, w.T, ldb);  // S^2
       kt_end(kt);
       if (e != hipSuccess) return e;
       k_corr_q<<<n, 256, 0, st>>>(w.X1, N, w.X2, N, a1, N, n, w.part, ntl, w.corr_max_theta * w.corr_max_theta,
@@ -966,7 +967,7 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
       if (e != hipSuccess) return e;
       k_copy_block<<<dim3(ceil_div(n, 256), n), 256, 0, st>>>(a1, N, n, w.V, N);
       kt_begin(kt, KID_EIG_GEMM);
-      e = launch_dgemm(st, true, false, n, n, n, w.X1, N, w.X2, N, w.T, ldb);  // Q^T (A Q)
+      e = launch_dgemm_ksplit(st, true, false, n, n, n, w.X1, N, w.X2, N, w.T, ldb, a1, N);  // Q^T (A Q)
       kt_end(kt);
       if (e != hipSuccess) return e;
       k_sym_lower<<<ntl, 256, 0, st>>>(w.T, ldb, n, a1, N);

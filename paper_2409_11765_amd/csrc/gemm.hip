@@ -347,9 +347,10 @@ struct DProb {
   int ldb;
   double* C;
   int ldc;
+  int K;
 };
 template <bool TA, bool TB>
-__global__ void __launch_bounds__(512) k_dgemm_kg2(int M, int N, int K, DProb p0, DProb p1) {
+__global__ void __launch_bounds__(512) k_dgemm_kg2(int M, int N, DProb p0, DProb p1) {
   using C = Cfg<double>;
   __shared__ double As[C::BK * (C::BM + C::PAD)];
   __shared__ double Bs[C::BK * (C::BN + C::PAD)];
@@ -360,7 +361,7 @@ __global__ void __launch_bounds__(512) k_dgemm_kg2(int M, int N, int K, DProb p0
   const int m0 = (t % tiles_m) * C::BM;
   const int n0 = (t / tiles_m) * C::BN;
   typename C::acc_t acc[2][2];
-  gemm_mainloop<double, TA, TB, 512>(M, N, K, pr.A, pr.lda, pr.B, pr.ldb, m0, n0, As, Bs, acc);
+  gemm_mainloop<double, TA, TB, 512>(M, N, pr.K, pr.A, pr.lda, pr.B, pr.ldb, m0, n0, As, Bs, acc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wq = wave & 3;
   if (wave >= 4) {
 #pragma unroll
@@ -379,6 +380,12 @@ __global__ void __launch_bounds__(512) k_dgemm_kg2(int M, int N, int K, DProb p0
 #pragma unroll
       for (int r = 0; r < C::NACC; ++r) acc[i][j][r] += fold[(((r * 4 + wq) * 2 + i) * 2 + j) * 64 + lane];
   EpiStore<double>{pr.C, pr.ldc}(acc, M, N, m0, n0, As);
+}
+
+// C[:M, :N] += W[:M, :N]
+__global__ void k_add_block(double* __restrict__ Cm, int ldc, const double* __restrict__ W, int ldw, int M) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (r < M) Cm[static_cast<int64_t>(c) * ldc + r] += W[static_cast<int64_t>(c) * ldw + r];
 }
 
 __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
@@ -714,8 +721,27 @@ hipError_t launch_dgemm2(hipStream_t st, int M, int N, int K, const double* A0, 
   using Cf = Cfg<double>;
   const int tiles = ceil_div(M, Cf::BM) * ceil_div(N, Cf::BN);
   if (tiles == 0) return hipSuccess;
-  k_dgemm_kg2<false, false><<<2 * tiles, 512, 0, st>>>(M, N, K, DProb{A0, lda0, B, ldb, C0, ldc0},
-                                                      DProb{A1, lda1, B, ldb, C1, ldc1});
+  k_dgemm_kg2<false, false><<<2 * tiles, 512, 0, st>>>(M, N, DProb{A0, lda0, B, ldb, C0, ldc0, K},
+                                                      DProb{A1, lda1, B, ldb, C1, ldc1, K});
+  return hipGetLastError();
+}
+
+hipError_t launch_dgemm_ksplit(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A, int lda,
+                               const double* B, int ldb, double* Cm, int ldc, double* W, int ldw) {
+  using Cf = Cfg<double>;
+  const int tiles = ceil_div(M, Cf::BM) * ceil_div(N, Cf::BN);
+  if (tiles == 0) return hipSuccess;
+  const int K0 = round_up(ceil_div(K, 2), Cf::BK);
+  if (K0 >= K) return launch_dgemm(st, ta, tb, M, N, K, A, lda, B, ldb, Cm, ldc);
+  // op(A)[:, K0:] and op(B)[K0:, :]: A stored M x K (K x M if ta), B K x N (N x K if tb)
+  const double* A1 = ta ? A + K0 : A + static_cast<int64_t>(K0) * lda;
+  const double* B1 = tb ? B + static_cast<int64_t>(K0) * ldb : B + K0;
+  const DProb p0{A, lda, B, ldb, Cm, ldc, K0}, p1{A1, lda, B1, ldb, W, ldw, K - K0};
+  if (!ta && !tb) k_dgemm_kg2<false, false><<<2 * tiles, 512, 0, st>>>(M, N, p0, p1);
+  else if (ta && !tb) k_dgemm_kg2<true, false><<<2 * tiles, 512, 0, st>>>(M, N, p0, p1);
+  else if (!ta && tb) k_dgemm_kg2<false, true><<<2 * tiles, 512, 0, st>>>(M, N, p0, p1);
+  else k_dgemm_kg2<true, true><<<2 * tiles, 512, 0, st>>>(M, N, p0, p1);
+  k_add_block<<<dim3(ceil_div(M, 256), N), 256, 0, st>>>(Cm, ldc, W, ldw, M);
   return hipGetLastError();
 }
 

@@ -180,6 +180,10 @@ hipError_t g32_syrk(hipStream_t st, int cfg, int n, int K, const float* Y, int l
 // generic FP64 GEMM: C = op(A) * op(B), column-major
 hipError_t launch_dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
                         int lda, const double* B, int ldb, double* C, int ldc);
+// C = op(A) op(B) as two half-k products in one launch (two tiles per CU at
+// n ~ 1000), the second into the n x n scratch W, then C += W
+hipError_t launch_dgemm_ksplit(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A, int lda,
+                               const double* B, int ldb, double* C, int ldc, double* W, int ldw);
 // C0 = A0 B and C1 = A1 B (no transposes) in one launch
 hipError_t launch_dgemm2(hipStream_t st, int M, int N, int K, const double* A0, int lda0, const double* A1,
                          int lda1, const double* B, int ldb, double* C0, int ldc0, double* C1, int ldc1);
