@@ -731,8 +731,12 @@ hipError_t launch_dgemm_ksplit(hipStream_t st, bool ta, bool tb, int M, int N, i
   using Cf = Cfg<double>;
   const int tiles = ceil_div(M, Cf::BM) * ceil_div(N, Cf::BN);
   if (tiles == 0) return hipSuccess;
+  // split only while the whole product has at most one tile per CU (256 on
+  // gfx950): with more tiles the CUs are already shared and the add's extra
+  // pass over C costs more than the split gains
+  constexpr int kCUs = 256;
   const int K0 = round_up(ceil_div(K, 2), Cf::BK);
-  if (K0 >= K) return launch_dgemm(st, ta, tb, M, N, K, A, lda, B, ldb, Cm, ldc);
+  if (K0 >= K || tiles > kCUs) return launch_dgemm(st, ta, tb, M, N, K, A, lda, B, ldb, Cm, ldc);
   // op(A)[:, K0:] and op(B)[K0:, :]: A stored M x K (K x M if ta), B K x N (N x K if tb)
   const double* A1 = ta ? A + K0 : A + static_cast<int64_t>(K0) * lda;
   const double* B1 = tb ? B + static_cast<int64_t>(K0) * ldb : B + K0;

@@ -181,7 +181,8 @@ hipError_t g32_syrk(hipStream_t st, int cfg, int n, int K, const float* Y, int l
 hipError_t launch_dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
                         int lda, const double* B, int ldb, double* C, int ldc);
 // C = op(A) op(B) as two half-k products in one launch (two tiles per CU at
-// n ~ 1000), the second into the n x n scratch W, then C += W
+// n ~ 1000), the second into the n x n scratch W, then C += W; a plain
+// launch_dgemm when the product has more tiles than the GPU has CUs
 hipError_t launch_dgemm_ksplit(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A, int lda,
                                const double* B, int ldb, double* C, int ldc, double* W, int ldw);
 // C0 = A0 B and C1 = A1 B (no transposes) in one launch
