@@ -40,6 +40,9 @@ Pins (tests under ``tests/`` that tie this file to something other than itself):
   covariance, sample covariance of y, CSA drift under random selection,
   linear convergence on the sphere.
 * ``ipop``           - lambda sequence lambda_start * 2^k and K_max stop.
+* ``sphere``, ``rot_ellipsoid``, ``rot_rastrigin`` - zero at x* under any
+  rotation, the ellipsoid's axis scales 10^(6 (i-1)/(n-1)) along R^T e_i,
+  Rastrigin = sum u^2 at integer u and 20.25 n at u = 1/2, n = 1 edge case.
 """
 
 from __future__ import annotations
