@@ -16,9 +16,11 @@
  *    message describing the last failure.
  *  - Matrices are column-major.  Candidate k of a population is column k.
  *  - Unless stated otherwise every pointer argument is HOST memory owned by
- *    the caller; the library copies from / into it before returning and never
+ *    the caller; the library has finished reading or writing it when the
+ *    call returns (every such copy completes before the return) and never
  *    keeps it.  All device memory is owned by the handle and freed by
- *    cmaes_destroy() / cmaes_batch_destroy().
+ *    cmaes_destroy() / cmaes_batch_destroy(); it comes from hipMalloc, or
+ *    from the caller's allocator hook (options.dev_malloc / dev_free).
  *  - Work is queued on the handle's HIP stream (options.stream, NULL = the
  *    library's own stream).  Calls that hand data back to the host
  *    synchronise that stream; cmaes_generation() itself may return before the
@@ -28,6 +30,7 @@
 #ifndef CMAES_MI355X_H
 #define CMAES_MI355X_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -41,7 +44,7 @@ extern "C" {
 #define CMAES_EDEVICE (-3)  /* HIP runtime error or no gfx950 device          */
 #define CMAES_ESTATE (-4)   /* call not valid in the handle's current state   */
 #define CMAES_EKMAX (-5)    /* restart would exceed K_max (Alg. 2 loop end)   */
-#define CMAES_ENUMERIC (-6) /* non-finite values, eigen solver did not converge */
+#define CMAES_ENUMERIC (-6) /* the eigendecomposition met non-finite values     */
 
 /* ---- enums -------------------------------------------------------------- */
 typedef enum {
@@ -84,6 +87,18 @@ typedef struct {
   double tol_x_factor;    /* TolX = tol_x_factor * sigma0 (default 1e-12)         */
   double max_condition;   /* ConditionCov threshold on cond(C) (default 1e14)     */
   void* stream;           /* hipStream_t to run on; NULL = library-owned stream   */
+  /* Device allocator hook (both NULL = hipMalloc / hipFree, the default).
+   * dev_malloc(bytes, alloc_ctx) returns device memory of the current device
+   * (NULL on failure -> CMAES_ENOMEM); dev_free(ptr, alloc_ctx) releases it.
+   * The library synchronises the handle's stream before each release.  The
+   * hook in effect at the handle's first allocation (its first generation,
+   * state or objective call) serves the handle for its whole life; passing a
+   * different hook after that is CMAES_ESTATE, setting only one of the two
+   * functions CMAES_EINVAL.  The Python binding uses this to allocate from
+   * PyTorch's caching allocator. */
+  void* (*dev_malloc)(size_t bytes, void* alloc_ctx);
+  void (*dev_free)(void* ptr, void* alloc_ctx);
+  void* alloc_ctx;
 } cmaes_options_t;
 
 /* Fill *opt with the defaults listed above.  Returns CMAES_EINVAL if opt is NULL. */
@@ -146,20 +161,30 @@ int cmaes_get_options(const cmaes_t* h, cmaes_options_t* opt);
 int cmaes_set_objective(cmaes_t* h, int kind, const double* R, const double* xstar);
 
 /* One full generation on the device with the fused objective (Alg. 1 body).
- * CMAES_ESTATE if no objective is set or the descent has stopped. */
+ * Returns CMAES_ESTATE, and queues nothing, if no objective is set or the
+ * descent has stopped: a stop test of the previous generation fired (the
+ * call first waits for that generation's stop tests to finish on the
+ * device).  cmaes_restart_ipop() and cmaes_set_state() clear the stop.
+ * Returns CMAES_ENUMERIC if this generation's eigendecomposition met
+ * non-finite values in C; the generation's stop tests have then run and set
+ * CMAES_STOP_CONDITIONCOV (and CMAES_STOP_NUMERIC where m, sigma, p_c,
+ * diag C or D is non-finite), so the next call returns CMAES_ESTATE. */
 int cmaes_generation(cmaes_t* h);
 
 /* Parity hook: as cmaes_generation() but with the n*lambda normal matrix Z
- * (column-major, column k = z_k of eq. (1)) supplied by the caller. */
+ * (column-major, column k = z_k of eq. (1)) supplied by the caller; Z has
+ * been copied to the device when the call returns.  Same return codes. */
 int cmaes_generation_with_z(cmaes_t* h, const double* Z);
 
 /* Host blackbox path, first half: sample the generation's points
- * x_k = m + sigma B D z_k into X (n*lambda, column-major). */
+ * x_k = m + sigma B D z_k into X (n*lambda, column-major).  CMAES_ESTATE on
+ * a stopped descent (as cmaes_generation). */
 int cmaes_ask(cmaes_t* h, double* X);
 
 /* Host blackbox path, second half: supply the lambda fitness values of the
  * points returned by the last cmaes_ask() (NaN counts as +inf) and run the
- * rest of the generation.  CMAES_ESTATE without a pending ask. */
+ * rest of the generation.  CMAES_ESTATE without a pending ask;
+ * CMAES_ENUMERIC as cmaes_generation. */
 int cmaes_tell(cmaes_t* h, const double* f);
 
 /* Alg. 2 restart: lambda <- 2 lambda (K <- 2K), a fresh mean from the seed
@@ -167,9 +192,10 @@ int cmaes_tell(cmaes_t* h, const double* f);
  * descents is kept.  CMAES_EKMAX if 2K would exceed K_max (nothing changes). */
 int cmaes_restart_ipop(cmaes_t* h);
 
-/* Run Alg. 2 on the fused objective: generations until a stop bit fires,
- * then restart with doubled lambda, until K > K_max, f_best < f_target or
- * the evaluation budget is spent.  Writes the number of descents run into
+/* Run Alg. 2 on the fused objective: generations until a stop bit fires
+ * (a CMAES_ENUMERIC generation counts as stopped), then restart with doubled
+ * lambda, until K > K_max, f_best < f_target or the evaluation budget is
+ * spent.  Writes the number of descents run into
  * *descents (may be NULL).  Returns CMAES_OK when the loop ended normally. */
 int cmaes_ipop_run(cmaes_t* h, int* descents);
 

@@ -39,12 +39,54 @@ class CmaesError(RuntimeError):
         self.code = code
 
 
+DEV_MALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class CmaesOptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("eigen_interval", C.c_int32), ("k_max", C.c_int32),
                 ("max_gens", C.c_int32), ("max_evals", C.c_int64), ("box_lo", C.c_double),
                 ("box_hi", C.c_double), ("f_target", C.c_double), ("tol_hist_fun", C.c_double),
                 ("tol_fun", C.c_double), ("tol_x_factor", C.c_double), ("max_condition", C.c_double),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("dev_malloc", DEV_MALLOC), ("dev_free", DEV_FREE),
+                ("alloc_ctx", C.c_void_p)]
+
+
+class TorchAllocator:
+    """The allocator hook of cmaes_options_t backed by PyTorch's caching
+    allocator (device memory then shows up in torch.cuda.memory_allocated()).
+    Blocks are associated with `stream` (the handle's stream when it is a torch
+    stream, else torch's current stream); the library synchronises its own
+    stream before it releases a block.  Keep the object alive as long as the
+    handle (the CMAES wrapper does)."""
+
+    def __init__(self, device=None, stream=None):
+        import torch  # only this optional hook needs torch
+        self._torch = torch
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.stream = stream
+        self.live = {}
+
+        def _alloc(nbytes, _ctx):
+            try:
+                p = self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:
+                return None
+            self.live[int(p)] = int(nbytes)
+            return int(p)
+
+        def _free(ptr, _ctx):
+            if ptr:
+                self.live.pop(int(ptr), None)
+                self._torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.c_malloc = DEV_MALLOC(_alloc)
+        self.c_free = DEV_FREE(_free)
+
+    def install(self, opt: "CmaesOptions"):
+        opt.dev_malloc = self.c_malloc
+        opt.dev_free = self.c_free
+        opt.alloc_ctx = None
 
 
 _PD = C.POINTER(C.c_double)
@@ -203,6 +245,8 @@ def cmaes_generation(h):
 
 
 def cmaes_generation_with_z(h, Z):
+    # the library has copied Z when the call returns, so the temporary
+    # column-major copy may be released right after
     Zf = np.asfortranarray(np.asarray(Z, dtype=np.float64))
     _check(_lib.cmaes_generation_with_z(h, _dptr(Zf)))
 
@@ -365,7 +409,11 @@ class CMAES:
     """Owning wrapper of one handle (one descent plus its IPOP restarts)."""
 
     def __init__(self, n, lam=0, sigma0=2.0, seed=0, precision="mixed", objective=None, R=None,
-                 xstar=None, **options):
+                 xstar=None, allocator=None, **options):
+        """allocator: None (hipMalloc) or "torch" (PyTorch's caching allocator,
+        through the options' allocator hook)."""
+        self.h = None
+        self.allocator = None
         self.h = cmaes_create(n, lam, sigma0, seed)
         self.n = n
         opt = cmaes_default_options()
@@ -374,6 +422,15 @@ class CMAES:
             if k == "stream":
                 v = C.c_void_p(v) if v else None
             setattr(opt, k, v)
+        if allocator == "torch":
+            import torch
+            stream = None
+            if options.get("stream"):
+                stream = torch.cuda.ExternalStream(int(options["stream"]))
+            self.allocator = TorchAllocator(stream=stream)
+            self.allocator.install(opt)
+        elif allocator is not None:
+            raise ValueError("allocator must be None or 'torch'")
         cmaes_set_options(self.h, opt)
         if objective is not None:
             cmaes_set_objective(self.h, objective, n, R, xstar)

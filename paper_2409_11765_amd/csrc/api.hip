@@ -69,23 +69,6 @@ HostParams make_params(int n, int lam, int kappa_opt) {
 
 int default_lambda(int n) { return 4 + static_cast<int>(std::floor(3.0 * std::log(static_cast<double>(n)))); }
 
-template <typename P>
-int dev_alloc(P** p, size_t bytes) {
-  *p = nullptr;
-  if (bytes == 0) bytes = 16;
-  void* q = nullptr;
-  if (hipMalloc(&q, bytes) != hipSuccess) return fail(CMAES_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-  if (hipMemset(q, 0, bytes) != hipSuccess) return fail(CMAES_EDEVICE, "hipMemset failed");
-  *p = static_cast<P*>(q);
-  return 0;
-}
-
-template <typename P>
-void dev_free(P*& p) {
-  if (p) (void)hipFree(const_cast<void*>(static_cast<const void*>(p)));
-  p = nullptr;
-}
-
 }  // namespace
 
 struct cmaes {
@@ -95,6 +78,18 @@ struct cmaes {
   cmaes_options_t opt{};
   hipStream_t st = nullptr;
   bool own_stream = false;
+  // device allocator of every buffer of the handle, fixed at its first
+  // allocation (options.dev_malloc / dev_free / alloc_ctx; null = hipMalloc)
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* alloc_ctx = nullptr;
+  // stop bits of the last generation whose stop tests have run: the stop
+  // kernel stores them into this pinned, mapped host word (hstop; dstop is
+  // its device address), and ev_stop marks the end of that kernel
+  uint32_t* hstop = nullptr;
+  uint32_t* dstop = nullptr;
+  hipEvent_t ev_stop = nullptr;
+  bool stop_pending = false;  // ev_stop recorded and not yet waited for
   bool fp64 = false;
   HostParams hp;
   StopParams sp{};
@@ -139,23 +134,57 @@ struct cmaes {
 
 namespace {
 
+// Device buffer of the handle, zero-filled on the handle's stream (so the
+// handle's kernels see the zeros without any other synchronisation).
+template <typename P>
+int dev_alloc(cmaes* h, P** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  void* q = nullptr;
+  if (h->alloc_fn) {
+    q = h->alloc_fn(bytes, h->alloc_ctx);
+    if (!q) return fail(CMAES_ENOMEM, "caller allocator failed for " + std::to_string(bytes) + " bytes");
+  } else if (hipMalloc(&q, bytes) != hipSuccess) {
+    return fail(CMAES_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  *p = static_cast<P*>(q);
+  CMX_HIP(hipMemsetAsync(q, 0, bytes, h->st));
+  return 0;
+}
+
+// The caller must have synchronised the handle's stream (free_all and
+// free_pop_buffers do): a caller allocator may hand the memory to other work
+// at once.
+template <typename P>
+void dev_free(cmaes* h, P*& p) {
+  if (p) {
+    void* q = const_cast<void*>(static_cast<const void*>(p));
+    if (h->free_fn)
+      h->free_fn(q, h->alloc_ctx);
+    else
+      (void)hipFree(q);
+  }
+  p = nullptr;
+}
+
 size_t esz(const cmaes* h) { return h->fp64 ? sizeof(double) : sizeof(float); }
 
 void free_pop_buffers(cmaes* h) {
-  dev_free(h->Z);
-  dev_free(h->Y);
-  dev_free(h->Ysel);
-  dev_free(h->partial);
-  dev_free(h->part_yw);
-  dev_free(h->part_zw);
-  dev_free(h->f);
-  dev_free(h->X);
-  dev_free(h->order);
-  dev_free(h->rank_work);
-  dev_free(h->w);
-  dev_free(h->sqrtw);
-  dev_free(h->hist);
-  dev_free(h->syrk_work);
+  if (h->st) (void)hipStreamSynchronize(h->st);  // nothing in flight uses the buffers
+  dev_free(h, h->Z);
+  dev_free(h, h->Y);
+  dev_free(h, h->Ysel);
+  dev_free(h, h->partial);
+  dev_free(h, h->part_yw);
+  dev_free(h, h->part_zw);
+  dev_free(h, h->f);
+  dev_free(h, h->X);
+  dev_free(h, h->order);
+  dev_free(h, h->rank_work);
+  dev_free(h, h->w);
+  dev_free(h, h->sqrtw);
+  dev_free(h, h->hist);
+  dev_free(h, h->syrk_work);
   h->cap_lam = h->cap_mu = h->hist_cap = 0;
 }
 
@@ -173,43 +202,47 @@ void drop_graphs(cmaes* h) {
 }
 
 void free_all(cmaes* h) {
+  if (h->st) (void)hipStreamSynchronize(h->st);
   drop_graphs(h);
   free_pop_buffers(h);
-  dev_free(h->sc);
-  dev_free(h->m);
-  dev_free(h->ps);
-  dev_free(h->pc);
-  dev_free(h->C);
-  dev_free(h->B);
-  dev_free(h->D);
-  dev_free(h->x_best);
-  dev_free(h->d);
-  dev_free(h->u);
-  dev_free(h->xstar);
-  dev_free(h->Rd);
-  dev_free(h->yw);
-  dev_free(h->zw);
-  dev_free(h->part_bz);
-  dev_free(h->BD);
-  dev_free(h->Rt);
-  dev_free(h->coef);
-  dev_free(h->ew.A);
-  dev_free(h->ew.V);
-  dev_free(h->ew.Q);
-  dev_free(h->ew.T);
-  dev_free(h->ew.A2);
-  dev_free(h->ew.X1);
-  dev_free(h->ew.X2);
-  dev_free(h->ew.Q2);
-  dev_free(h->ew.evals);
-  dev_free(h->ew.perm);
-  dev_free(h->ew.sign);
-  dev_free(h->ew.part);
-  dev_free(h->ew.scale);
-  dev_free(h->ew.status);
+  dev_free(h, h->sc);
+  dev_free(h, h->m);
+  dev_free(h, h->ps);
+  dev_free(h, h->pc);
+  dev_free(h, h->C);
+  dev_free(h, h->B);
+  dev_free(h, h->D);
+  dev_free(h, h->x_best);
+  dev_free(h, h->d);
+  dev_free(h, h->u);
+  dev_free(h, h->xstar);
+  dev_free(h, h->Rd);
+  dev_free(h, h->yw);
+  dev_free(h, h->zw);
+  dev_free(h, h->part_bz);
+  dev_free(h, h->BD);
+  dev_free(h, h->Rt);
+  dev_free(h, h->coef);
+  dev_free(h, h->ew.A);
+  dev_free(h, h->ew.V);
+  dev_free(h, h->ew.Q);
+  dev_free(h, h->ew.T);
+  dev_free(h, h->ew.A2);
+  dev_free(h, h->ew.X1);
+  dev_free(h, h->ew.X2);
+  dev_free(h, h->ew.Q2);
+  dev_free(h, h->ew.evals);
+  dev_free(h, h->ew.perm);
+  dev_free(h, h->ew.sign);
+  dev_free(h, h->ew.part);
+  dev_free(h, h->ew.scale);
+  dev_free(h, h->ew.status);
   if (h->ew.hflags) (void)hipHostFree(h->ew.hflags);
   h->ew.hflags = nullptr;
   h->ew.dflags = nullptr;
+  h->hstop = nullptr;
+  h->dstop = nullptr;
+  h->stop_pending = false;
   h->allocated = false;
 }
 
@@ -236,13 +269,13 @@ int alloc_pop(cmaes* h) {
   const size_t e = esz(h);
   int rc = 0;
   const int row_tiles = ceil_div(n, 64);
-  if ((rc = dev_alloc(&h->Z, e * ldn * lam)) || (rc = dev_alloc(&h->Y, e * ldn * lam)) ||
-      (rc = dev_alloc(&h->Ysel, e * ldn * mu)) || (rc = dev_alloc(&h->partial, 8ull * row_tiles * lam)) ||
-      (rc = dev_alloc(&h->part_yw, 8ull * ceil_div(mu, 64) * n)) ||
-      (rc = dev_alloc(&h->part_zw, 8ull * ceil_div(mu, 64) * n)) || (rc = dev_alloc(&h->f, 8ull * lam)) ||
-      (rc = dev_alloc(&h->order, 4ull * lam)) || (rc = dev_alloc(&h->rank_work, 4ull * rank_work_elems(lam))) ||
-      (rc = dev_alloc(&h->w, 8ull * mu)) ||
-      (rc = dev_alloc(&h->sqrtw, 8ull * mu)) || (rc = dev_alloc(&h->hist, 8ull * hist_len_for(n, lam))))
+  if ((rc = dev_alloc(h, &h->Z, e * ldn * lam)) || (rc = dev_alloc(h, &h->Y, e * ldn * lam)) ||
+      (rc = dev_alloc(h, &h->Ysel, e * ldn * mu)) || (rc = dev_alloc(h, &h->partial, 8ull * row_tiles * lam)) ||
+      (rc = dev_alloc(h, &h->part_yw, 8ull * ceil_div(mu, 64) * n)) ||
+      (rc = dev_alloc(h, &h->part_zw, 8ull * ceil_div(mu, 64) * n)) || (rc = dev_alloc(h, &h->f, 8ull * lam)) ||
+      (rc = dev_alloc(h, &h->order, 4ull * lam)) || (rc = dev_alloc(h, &h->rank_work, 4ull * rank_work_elems(lam))) ||
+      (rc = dev_alloc(h, &h->w, 8ull * mu)) ||
+      (rc = dev_alloc(h, &h->sqrtw, 8ull * mu)) || (rc = dev_alloc(h, &h->hist, 8ull * hist_len_for(n, lam))))
     return rc;
   {
     int ntl, splits, kspan;
@@ -251,7 +284,7 @@ int alloc_pop(cmaes* h) {
       syrk_plan_f64(n, mu, &ntl, &splits, &kspan, &we);
     else
       we = syrk32_max_work(n, mu);
-    if ((rc = dev_alloc(&h->syrk_work, e * we))) return rc;
+    if ((rc = dev_alloc(h, &h->syrk_work, e * we))) return rc;
   }
   h->cap_lam = lam;
   h->cap_mu = mu;
@@ -266,36 +299,39 @@ int alloc_fixed(cmaes* h) {
   const int N = round_up(n, 32);
   h->ew.N = N;
   int rc = 0;
-  if ((rc = dev_alloc(&h->sc, sizeof(DevScalars))) || (rc = dev_alloc(&h->m, 8ull * ldn)) ||
-      (rc = dev_alloc(&h->ps, 8ull * ldn)) || (rc = dev_alloc(&h->pc, 8ull * ldn)) ||
-      (rc = dev_alloc(&h->C, 8 * nn)) || (rc = dev_alloc(&h->B, 8 * nn)) || (rc = dev_alloc(&h->D, 8ull * ldn)) ||
-      (rc = dev_alloc(&h->x_best, 8ull * ldn)) || (rc = dev_alloc(&h->d, 8ull * ldn)) ||
-      (rc = dev_alloc(&h->u, 8ull * ldn)) ||
-      (rc = dev_alloc(&h->xstar, 8ull * ldn)) || (rc = dev_alloc(&h->Rd, 8 * nn)) ||
-      (rc = dev_alloc(&h->yw, 8ull * ldn)) || (rc = dev_alloc(&h->zw, 8ull * ldn)) ||
-      (rc = dev_alloc(&h->part_bz, 8ull * ceil_div(n, 64) * n)) || (rc = dev_alloc(&h->BD, e * nn)) ||
-      (rc = dev_alloc(&h->Rt, e * nn)) || (rc = dev_alloc(&h->coef, e * ldn)) ||
-      (rc = dev_alloc(&h->ew.A, 8ull * N * N)) || (rc = dev_alloc(&h->ew.V, 8ull * N * N)) ||
-      (rc = dev_alloc(&h->ew.Q, 8ull * (N / 32) * 32 * 32)) || (rc = dev_alloc(&h->ew.T, 8 * nn)) ||
-      (rc = dev_alloc(&h->ew.A2, 8ull * N * N)) || (rc = dev_alloc(&h->ew.Q2, 8ull * (N / 32) * 32 * 32)) ||
-      (rc = dev_alloc(&h->ew.X1, 8ull * N * N)) || (rc = dev_alloc(&h->ew.X2, 8ull * N * N)) ||
-      (rc = dev_alloc(&h->ew.evals, 8ull * N)) || (rc = dev_alloc(&h->ew.perm, 4ull * N)) ||
-      (rc = dev_alloc(&h->ew.sign, 8ull * N)) || (rc = dev_alloc(&h->ew.scale, 16)) ||
-      (rc = dev_alloc(&h->ew.status, 16)))
+  if ((rc = dev_alloc(h, &h->sc, sizeof(DevScalars))) || (rc = dev_alloc(h, &h->m, 8ull * ldn)) ||
+      (rc = dev_alloc(h, &h->ps, 8ull * ldn)) || (rc = dev_alloc(h, &h->pc, 8ull * ldn)) ||
+      (rc = dev_alloc(h, &h->C, 8 * nn)) || (rc = dev_alloc(h, &h->B, 8 * nn)) || (rc = dev_alloc(h, &h->D, 8ull * ldn)) ||
+      (rc = dev_alloc(h, &h->x_best, 8ull * ldn)) || (rc = dev_alloc(h, &h->d, 8ull * ldn)) ||
+      (rc = dev_alloc(h, &h->u, 8ull * ldn)) ||
+      (rc = dev_alloc(h, &h->xstar, 8ull * ldn)) || (rc = dev_alloc(h, &h->Rd, 8 * nn)) ||
+      (rc = dev_alloc(h, &h->yw, 8ull * ldn)) || (rc = dev_alloc(h, &h->zw, 8ull * ldn)) ||
+      (rc = dev_alloc(h, &h->part_bz, 8ull * ceil_div(n, 64) * n)) || (rc = dev_alloc(h, &h->BD, e * nn)) ||
+      (rc = dev_alloc(h, &h->Rt, e * nn)) || (rc = dev_alloc(h, &h->coef, e * ldn)) ||
+      (rc = dev_alloc(h, &h->ew.A, 8ull * N * N)) || (rc = dev_alloc(h, &h->ew.V, 8ull * N * N)) ||
+      (rc = dev_alloc(h, &h->ew.Q, 8ull * (N / 32) * 32 * 32)) || (rc = dev_alloc(h, &h->ew.T, 8 * nn)) ||
+      (rc = dev_alloc(h, &h->ew.A2, 8ull * N * N)) || (rc = dev_alloc(h, &h->ew.Q2, 8ull * (N / 32) * 32 * 32)) ||
+      (rc = dev_alloc(h, &h->ew.X1, 8ull * N * N)) || (rc = dev_alloc(h, &h->ew.X2, 8ull * N * N)) ||
+      (rc = dev_alloc(h, &h->ew.evals, 8ull * N)) || (rc = dev_alloc(h, &h->ew.perm, 4ull * N)) ||
+      (rc = dev_alloc(h, &h->ew.sign, 8ull * N)) || (rc = dev_alloc(h, &h->ew.scale, 16)) ||
+      (rc = dev_alloc(h, &h->ew.status, 16)))
     return rc;
   {
     const int q = N / 32;
-    if ((rc = dev_alloc(&h->ew.part, 8ull * 3 * std::max(n, q * (q + 1) / 2)))) return rc;
+    if ((rc = dev_alloc(h, &h->ew.part, 8ull * 3 * std::max(n, q * (q + 1) / 2)))) return rc;
   }
-  // convergence flags: pinned, mapped host memory the device writes directly
+  // convergence flags (words 0-3) and the stop bits (word 4): pinned, mapped
+  // host memory the device writes directly
   void* hf = nullptr;
-  if (hipHostMalloc(&hf, 16, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+  if (hipHostMalloc(&hf, 32, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
     return fail(CMAES_ENOMEM, "hipHostMalloc failed");
   h->ew.hflags = static_cast<int*>(hf);
-  h->ew.hflags[0] = h->ew.hflags[1] = h->ew.hflags[2] = h->ew.hflags[3] = 0;
+  for (int i = 0; i < 8; ++i) h->ew.hflags[i] = 0;
   void* dp = nullptr;
   if (hipHostGetDevicePointer(&dp, hf, 0) != hipSuccess) return fail(CMAES_EDEVICE, "hipHostGetDevicePointer failed");
   h->ew.dflags = static_cast<int*>(dp);
+  h->hstop = reinterpret_cast<uint32_t*>(h->ew.hflags + 4);
+  h->dstop = reinterpret_cast<uint32_t*>(h->ew.dflags + 4);
   return 0;
 }
 
@@ -312,9 +348,11 @@ int upload_objective_derived(cmaes* h);
 int upload_objective(cmaes* h) {
   const int n = h->n;
   if (h->have_R)
-    CMX_HIP(hipMemcpy2D(h->Rd, 8ull * h->ldn, h->R_host.data(), 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
-  if (h->have_xstar) CMX_HIP(hipMemcpy(h->xstar, h->xstar_host.data(), 8ull * n, hipMemcpyHostToDevice));
-  return upload_objective_derived(h);
+    CMX_HIP(hipMemcpy2DAsync(h->Rd, 8ull * h->ldn, h->R_host.data(), 8ull * n, 8ull * n, n, hipMemcpyHostToDevice,
+                             h->st));
+  if (h->have_xstar)
+    CMX_HIP(hipMemcpyAsync(h->xstar, h->xstar_host.data(), 8ull * n, hipMemcpyHostToDevice, h->st));
+  return upload_objective_derived(h);  // synchronises the stream
 }
 
 int upload_objective_derived(cmaes* h) {
@@ -322,16 +360,13 @@ int upload_objective_derived(cmaes* h) {
   std::vector<double> coef(n, 1.0);
   if (n > 1)
     for (int i = 0; i < n; ++i) coef[i] = std::pow(10.0, 6.0 * i / (n - 1));
-  if (h->fp64) {
-    CMX_HIP(hipMemcpy(h->coef, coef.data(), 8ull * n, hipMemcpyHostToDevice));
-  } else {
-    std::vector<float> cf(coef.begin(), coef.end());
-    CMX_HIP(hipMemcpy(h->coef, cf.data(), 4ull * n, hipMemcpyHostToDevice));
-  }
-  if (h->have_R) {
-    CMX_HIP(launch_to_precision(h->st, h->fp64, h->Rd, h->ldn, h->Rt, h->ldn, n, n));
-    CMX_HIP(hipStreamSynchronize(h->st));
-  }
+  std::vector<float> cf(coef.begin(), coef.end());
+  if (h->fp64)
+    CMX_HIP(hipMemcpyAsync(h->coef, coef.data(), 8ull * n, hipMemcpyHostToDevice, h->st));
+  else
+    CMX_HIP(hipMemcpyAsync(h->coef, cf.data(), 4ull * n, hipMemcpyHostToDevice, h->st));
+  if (h->have_R) CMX_HIP(launch_to_precision(h->st, h->fp64, h->Rd, h->ldn, h->Rt, h->ldn, n, n));
+  CMX_HIP(hipStreamSynchronize(h->st));  // the host vectors are consumed before they go out of scope
   return 0;
 }
 
@@ -339,14 +374,15 @@ int upload_objective_derived(cmaes* h) {
 int init_descent(cmaes* h, bool fresh) {
   const int n = h->n;
   DevScalars s{};
-  CMX_HIP(hipMemcpy(&s, h->sc, sizeof(s), hipMemcpyDeviceToHost));
+  CMX_HIP(hipMemcpyAsync(&s, h->sc, sizeof(s), hipMemcpyDeviceToHost, h->st));
+  CMX_HIP(hipStreamSynchronize(h->st));
   const double f_best = fresh ? HUGE_VAL : s.f_best;
   std::memset(&s, 0, sizeof(s));
   s.sigma = h->sigma0;
   s.sigma0 = h->sigma0;
   s.f_best = f_best;
   s.eig_ok = 1;
-  CMX_HIP(hipMemcpy(h->sc, &s, sizeof(s), hipMemcpyHostToDevice));
+  CMX_HIP(hipMemcpyAsync(h->sc, &s, sizeof(s), hipMemcpyHostToDevice, h->st));
   CMX_HIP(launch_init_mean(h->st, h->m, n, h->opt.box_lo, h->opt.box_hi, h->seed, static_cast<uint32_t>(h->restart)));
   CMX_HIP(hipMemsetAsync(h->ps, 0, 8ull * h->ldn, h->st));
   CMX_HIP(hipMemsetAsync(h->pc, 0, 8ull * h->ldn, h->st));
@@ -355,7 +391,9 @@ int init_descent(cmaes* h, bool fresh) {
   std::vector<double> ones(n, 1.0);
   CMX_HIP(hipMemcpyAsync(h->D, ones.data(), 8ull * n, hipMemcpyHostToDevice, h->st));
   CMX_HIP(launch_to_precision(h->st, h->fp64, h->B, h->ldn, h->BD, h->ldn, n, n));
-  CMX_HIP(hipStreamSynchronize(h->st));
+  CMX_HIP(hipStreamSynchronize(h->st));  // s and ones are consumed
+  *h->hstop = 0;
+  h->stop_pending = false;
   h->gen = 0;
   h->evals = 0;
   h->ask_pending = false;
@@ -370,6 +408,9 @@ int init_descent(cmaes* h, bool fresh) {
 int ensure_ready(cmaes* h) {
   if (h->allocated) return alloc_pop(h);
   h->fp64 = (h->opt.precision == CMAES_FP64);
+  h->alloc_fn = h->opt.dev_malloc;
+  h->free_fn = h->opt.dev_free;
+  h->alloc_ctx = h->opt.alloc_ctx;
   int rc;
   if ((rc = alloc_fixed(h)) || (rc = alloc_pop(h))) {
     free_all(h);
@@ -392,6 +433,7 @@ int phase_sample(cmaes* h, const double* Zhost) {
     // caller-supplied z: stage as float64 then convert to the sampling precision
     if (h->fp64) {
       CMX_HIP(hipMemcpy2DAsync(h->Z, 8ull * ldn, Zhost, 8ull * n, 8ull * n, lam, hipMemcpyHostToDevice, h->st));
+      CMX_HIP(hipStreamSynchronize(h->st));  // the caller's buffer is consumed before the call returns
     } else {
       std::vector<float> zf(static_cast<size_t>(ldn) * lam, 0.0f);
       for (int k = 0; k < lam; ++k)
@@ -534,7 +576,10 @@ int eigen_run(cmaes* h) {
 
 // stop tests, then fold the optional timers
 int phase_update_post(cmaes* h) {
-  CMX_HIP(launch_stop(h->st, h->hp.kp, h->sp, h->m, h->C, h->ldn, h->B, h->ldn, h->D, h->pc, h->hist, h->sc));
+  CMX_HIP(launch_stop(h->st, h->hp.kp, h->sp, h->m, h->C, h->ldn, h->B, h->ldn, h->D, h->pc, h->hist, h->sc,
+                      h->dstop));
+  CMX_HIP(hipEventRecord(h->ev_stop, h->st));
+  h->stop_pending = true;
   rec(h, 6);
   if (h->kt.on && h->kt.used > 0) {
     CMX_HIP(hipEventSynchronize(h->kt.ev[2 * h->kt.used - 1]));
@@ -558,14 +603,47 @@ int phase_update_post(cmaes* h) {
   return 0;
 }
 
+// the generation's eigendecomposition met non-finite values: its stop tests
+// have run (NUMERIC / CONDITIONCOV set); the call reports CMAES_ENUMERIC
+int numeric_failure(const cmaes* h) {
+  return fail(CMAES_ENUMERIC, "the eigendecomposition met non-finite values; the descent has stopped");
+}
+
+// the rest of a generation after its front: the eigensolve if due, then the
+// stop tests
+int finish_generation(cmaes* h) {
+  bool nonfinite = false;
+  if (h->eig_due) {
+    if (int rc = eigen_run(h)) return rc;
+    nonfinite = h->ew.hflags[1] != 0;
+  }
+  if (int rc = phase_update_post(h)) return rc;
+  return nonfinite ? numeric_failure(h) : 0;
+}
+
 int phase_update(cmaes* h) {
   set_due(h);
   if (int rc = phase_update_pre(h)) return rc;
   advance_counters(h);
-  if (h->eig_due) {
-    if (int rc = eigen_run(h)) return rc;
+  return finish_generation(h);
+}
+
+// CMAES_ESTATE once a stop test of the descent has fired: waits for the stop
+// tests of the last generation (the end of its queued work) and reads their
+// bits from the mapped host word
+int check_running(cmaes* h) {
+  if (h->stop_pending) {
+    CMX_HIP(hipEventSynchronize(h->ev_stop));
+    h->stop_pending = false;
   }
-  return phase_update_post(h);
+  const uint32_t bits = __atomic_load_n(h->hstop, __ATOMIC_ACQUIRE);
+  if (bits != 0)
+    return fail(CMAES_ESTATE, "the descent has stopped (stop bits 0x" + [bits] {
+      char b[16];
+      std::snprintf(b, sizeof b, "%x", bits);
+      return std::string(b);
+    }() + "); restart it or reset its state");
+  return 0;
 }
 
 int check(const cmaes* h) {
@@ -708,6 +786,11 @@ cmaes_t* cmaes_create(int n, int lambda, double sigma0, uint64_t seed) {
       cmaes_destroy(h);
       return nullptr;
     }
+  if (hipEventCreateWithFlags(&h->ev_stop, hipEventDisableTiming) != hipSuccess) {
+    set_error("hipEventCreate failed");
+    cmaes_destroy(h);
+    return nullptr;
+  }
   h->hp = make_params(n, lambda, 0);
   refresh_stop_params(h);
   return h;
@@ -721,6 +804,7 @@ void cmaes_destroy(cmaes_t* h) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
+  if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
   if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
   delete h;
 }
@@ -733,6 +817,10 @@ int cmaes_set_options(cmaes_t* h, const cmaes_options_t* o) {
     return fail(CMAES_EINVAL, "unknown precision");
   if (o->k_max < 1 || !(o->box_hi > o->box_lo) || o->eigen_interval < 0 || o->max_gens < 0 || o->max_evals < 0)
     return fail(CMAES_EINVAL, "invalid option value");
+  if ((o->dev_malloc == nullptr) != (o->dev_free == nullptr))
+    return fail(CMAES_EINVAL, "dev_malloc and dev_free must both be set or both be NULL");
+  if (h->allocated && (o->dev_malloc != h->alloc_fn || o->dev_free != h->free_fn || o->alloc_ctx != h->alloc_ctx))
+    return fail(CMAES_ESTATE, "the allocator can only change before the handle's first allocation");
   const bool started = h->allocated && (h->gen > 0 || h->restart > 0);
   const bool prec_change = (o->precision == CMAES_FP64) != (h->opt.precision == CMAES_FP64);
   if (started && (prec_change || o->stream != h->opt.stream))
@@ -790,11 +878,9 @@ int cmaes_generation(cmaes_t* h) {
   if (int rc = check(h)) return rc;
   if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "no fused objective set (use ask/tell)");
   if (int rc = ensure_ready(h)) return rc;
+  if (int rc = check_running(h)) return rc;
   if (int rc = front(h)) return rc;
-  if (h->eig_due) {
-    if (int rc = eigen_run(h)) return rc;
-  }
-  return phase_update_post(h);
+  return finish_generation(h);
 }
 
 int cmaes_generation_with_z(cmaes_t* h, const double* Z) {
@@ -802,6 +888,7 @@ int cmaes_generation_with_z(cmaes_t* h, const double* Z) {
   if (!Z) return fail(CMAES_EINVAL, "null Z");
   if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "no fused objective set");
   if (int rc = ensure_ready(h)) return rc;
+  if (int rc = check_running(h)) return rc;
   if (int rc = phase_sample(h, Z)) return rc;
   if (int rc = phase_fitness(h)) return rc;
   return phase_update(h);
@@ -828,10 +915,11 @@ int cmaes_ask(cmaes_t* h, double* X) {
   if (int rc = check(h)) return rc;
   if (!X) return fail(CMAES_EINVAL, "null X");
   if (int rc = ensure_ready(h)) return rc;
+  if (int rc = check_running(h)) return rc;
   const int n = h->n, lam = h->lam;
   if (!h->X || h->cap_lam < lam) {
-    dev_free(h->X);
-    if (int rc = dev_alloc(&h->X, 8ull * n * h->cap_lam)) return rc;
+    dev_free(h, h->X);
+    if (int rc = dev_alloc(h, &h->X, 8ull * n * h->cap_lam)) return rc;
   }
   if (int rc = phase_sample(h, nullptr)) return rc;
   const int64_t total = static_cast<int64_t>(n) * lam;
@@ -852,6 +940,7 @@ int cmaes_tell(cmaes_t* h, const double* f) {
   if (!f) return fail(CMAES_EINVAL, "null f");
   if (!h->ask_pending) return fail(CMAES_ESTATE, "cmaes_tell without a pending cmaes_ask");
   CMX_HIP(hipMemcpyAsync(h->f, f, 8ull * h->lam, hipMemcpyHostToDevice, h->st));
+  CMX_HIP(hipStreamSynchronize(h->st));  // the caller's buffer is consumed before the call returns
   h->ask_pending = false;
   return phase_update(h);
 }
@@ -875,7 +964,8 @@ int cmaes_ipop_run(cmaes_t* h, int* descents) {
   if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "no fused objective set");
   int count = 1;
   for (;;) {
-    if (int rc = cmaes_generation(h)) return rc;
+    const int grc = cmaes_generation(h);
+    if (grc != CMAES_OK && grc != CMAES_ENUMERIC) return grc;  // ENUMERIC: stop bits are set
     DevScalars s;
     if (int rc = read_scalars(h, &s)) return rc;
     const bool budget = h->opt.max_evals > 0 && h->total_evals >= h->opt.max_evals;
@@ -913,11 +1003,11 @@ int cmaes_state(const cmaes_t* hc, cmaes_state_t* out) {
   out->eig_sweeps = s.jac_sweeps;
   out->eig_corrections = s.jac_corr;
   auto vec = [&](double* dst, const double* src) -> int {
-    if (dst) CMX_HIP(hipMemcpy(dst, src, 8ull * n, hipMemcpyDeviceToHost));
+    if (dst) CMX_HIP(hipMemcpyAsync(dst, src, 8ull * n, hipMemcpyDeviceToHost, h->st));
     return 0;
   };
   auto mat = [&](double* dst, const double* src) -> int {
-    if (dst) CMX_HIP(hipMemcpy2D(dst, 8ull * n, src, 8ull * ldn, 8ull * n, n, hipMemcpyDeviceToHost));
+    if (dst) CMX_HIP(hipMemcpy2DAsync(dst, 8ull * n, src, 8ull * ldn, 8ull * n, n, hipMemcpyDeviceToHost, h->st));
     return 0;
   };
   int rc;
@@ -925,8 +1015,9 @@ int cmaes_state(const cmaes_t* hc, cmaes_state_t* out) {
       (rc = vec(out->D, h->D)) || (rc = vec(out->x_best, h->x_best)) || (rc = mat(out->C, h->C)) ||
       (rc = mat(out->B, h->B)))
     return rc;
-  if (out->f) CMX_HIP(hipMemcpy(out->f, h->f, 8ull * h->lam, hipMemcpyDeviceToHost));
-  if (out->order) CMX_HIP(hipMemcpy(out->order, h->order, 4ull * h->lam, hipMemcpyDeviceToHost));
+  if (out->f) CMX_HIP(hipMemcpyAsync(out->f, h->f, 8ull * h->lam, hipMemcpyDeviceToHost, h->st));
+  if (out->order) CMX_HIP(hipMemcpyAsync(out->order, h->order, 4ull * h->lam, hipMemcpyDeviceToHost, h->st));
+  CMX_HIP(hipStreamSynchronize(h->st));
   return CMAES_OK;
 }
 
@@ -937,23 +1028,30 @@ int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in) {
   if (!(in->sigma > 0.0) || in->gen < 0) return fail(CMAES_EINVAL, "sigma must be > 0 and gen >= 0");
   if (int rc = ensure_ready(h)) return rc;
   const int n = h->n, ldn = h->ldn;
-  CMX_HIP(hipStreamSynchronize(h->st));
   DevScalars s;
-  CMX_HIP(hipMemcpy(&s, h->sc, sizeof(s), hipMemcpyDeviceToHost));
+  CMX_HIP(hipMemcpyAsync(&s, h->sc, sizeof(s), hipMemcpyDeviceToHost, h->st));
+  CMX_HIP(hipStreamSynchronize(h->st));  // also: nothing in flight still writes the state
   s.sigma = in->sigma;
   s.gen = in->gen;
   s.stop = 0;
   s.hist_count = 0;
   s.eig_ok = 1;
-  CMX_HIP(hipMemcpy(h->sc, &s, sizeof(s), hipMemcpyHostToDevice));
+  // every copy below is ordered on the handle's stream and has completed
+  // before the call returns (the caller's buffers are then no longer read)
+  CMX_HIP(hipMemcpyAsync(h->sc, &s, sizeof(s), hipMemcpyHostToDevice, h->st));
   h->gen = in->gen;
-  if (in->m) CMX_HIP(hipMemcpy(h->m, in->m, 8ull * n, hipMemcpyHostToDevice));
-  if (in->p_sigma) CMX_HIP(hipMemcpy(h->ps, in->p_sigma, 8ull * n, hipMemcpyHostToDevice));
-  if (in->p_c) CMX_HIP(hipMemcpy(h->pc, in->p_c, 8ull * n, hipMemcpyHostToDevice));
-  if (in->D) CMX_HIP(hipMemcpy(h->D, in->D, 8ull * n, hipMemcpyHostToDevice));
-  if (in->C) CMX_HIP(hipMemcpy2D(h->C, 8ull * ldn, in->C, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
+  auto vec_in = [&](double* dst, const double* src) -> int {
+    if (src) CMX_HIP(hipMemcpyAsync(dst, src, 8ull * n, hipMemcpyHostToDevice, h->st));
+    return 0;
+  };
+  int rc;
+  if ((rc = vec_in(h->m, in->m)) || (rc = vec_in(h->ps, in->p_sigma)) || (rc = vec_in(h->pc, in->p_c)) ||
+      (rc = vec_in(h->D, in->D)))
+    return rc;
+  if (in->C)
+    CMX_HIP(hipMemcpy2DAsync(h->C, 8ull * ldn, in->C, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice, h->st));
   if (in->B) {
-    CMX_HIP(hipMemcpy2D(h->B, 8ull * ldn, in->B, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
+    CMX_HIP(hipMemcpy2DAsync(h->B, 8ull * ldn, in->B, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice, h->st));
     h->reorth_sweeps = 0;  // taken as orthogonal
     h->eig_uncounted = false;
     h->ew.last_sweeps = 0;
@@ -962,14 +1060,17 @@ int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in) {
   if (in->B || in->D) {
     // B D in the sampling precision
     std::vector<double> Bh(static_cast<size_t>(n) * n), Dh(n);
-    CMX_HIP(hipMemcpy2D(Bh.data(), 8ull * n, h->B, 8ull * ldn, 8ull * n, n, hipMemcpyDeviceToHost));
-    CMX_HIP(hipMemcpy(Dh.data(), h->D, 8ull * n, hipMemcpyDeviceToHost));
+    CMX_HIP(hipMemcpy2DAsync(Bh.data(), 8ull * n, h->B, 8ull * ldn, 8ull * n, n, hipMemcpyDeviceToHost, h->st));
+    CMX_HIP(hipMemcpyAsync(Dh.data(), h->D, 8ull * n, hipMemcpyDeviceToHost, h->st));
+    CMX_HIP(hipStreamSynchronize(h->st));
     for (int c = 0; c < n; ++c)
       for (int r = 0; r < n; ++r) Bh[static_cast<size_t>(c) * n + r] *= Dh[c];
-    CMX_HIP(hipMemcpy2D(h->ew.T, 8ull * ldn, Bh.data(), 8ull * n, 8ull * n, n, hipMemcpyHostToDevice));
+    CMX_HIP(hipMemcpy2DAsync(h->ew.T, 8ull * ldn, Bh.data(), 8ull * n, 8ull * n, n, hipMemcpyHostToDevice, h->st));
     CMX_HIP(launch_to_precision(h->st, h->fp64, h->ew.T, ldn, h->BD, ldn, n, n));
-    CMX_HIP(hipStreamSynchronize(h->st));
   }
+  CMX_HIP(hipStreamSynchronize(h->st));
+  *h->hstop = 0;  // the stop bits were cleared
+  h->stop_pending = false;
   h->ask_pending = false;
   return CMAES_OK;
 }
@@ -1075,7 +1176,7 @@ int cmaes_autotune(cmaes_t* h, int reps, double* us, int32_t* chosen) {
     // the covariance site is timed with its epilogue, which then updates this
     // scratch matrix instead of C (tiles differ in how many partials it sums)
     double* cscratch = nullptr;
-    int rc = dev_alloc(&cscratch, 8ull * ldn * n);
+    int rc = dev_alloc(h, &cscratch, 8ull * ldn * n);
     for (int site = 0; site < G32_NUM_SITES && rc == CMAES_OK; ++site) {
       if (site == G32_SAMPLE && h->opt.precision == CMAES_MIXED_BF16X3) continue;
       if (site == G32_FITNESS && !(h->have_R && h->obj_kind != CMAES_OBJ_NONE)) continue;
@@ -1114,7 +1215,7 @@ int cmaes_autotune(cmaes_t* h, int reps, double* us, int32_t* chosen) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(h->st);
-    dev_free(cscratch);
+    dev_free(h, cscratch);
     if (rc) return rc;
   }
   if (chosen)

@@ -240,10 +240,11 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
 // release the captured sweep graphs (the stream or the buffers change)
 void eigen_drop_graphs(EigWork& w);
 
-// stop tests
+// stop tests; the bits go to sc->stop and, when hstop is not null, to that
+// word of pinned, mapped host memory (device address)
 hipError_t launch_stop(hipStream_t st, const KParams& kp, const StopParams& sp, const double* m,
                        const double* C, int ldc, const double* B, int ldb, const double* D,
-                       const double* pc, const double* hist, DevScalars* sc);
+                       const double* pc, const double* hist, DevScalars* sc, uint32_t* hstop);
 
 // misc
 // B <- (3 B - T) / 2 with T = B (B^T B) (Newton-Schulz step, rows < n)

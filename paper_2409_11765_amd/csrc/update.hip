@@ -229,7 +229,8 @@ __global__ void __launch_bounds__(256) k_stop(KParams kp, StopParams sp, const d
                                               const double* __restrict__ C, int ldc,
                                               const double* __restrict__ B, int ldb,
                                               const double* __restrict__ D, const double* __restrict__ pc,
-                                              const double* __restrict__ hist, DevScalars* __restrict__ sc) {
+                                              const double* __restrict__ hist, DevScalars* __restrict__ sc,
+                                              uint32_t* __restrict__ hstop) {
   __shared__ double red[256];
   __shared__ int ired;
   const int n = kp.n;
@@ -279,6 +280,9 @@ __global__ void __launch_bounds__(256) k_stop(KParams kp, StopParams sp, const d
   if (sp.max_evals > 0 && sc->evals >= sp.max_evals) bits |= 1u << 8;
   if (nonfinite || !isfinite(sigma)) bits |= 1u << 9;
   sc->stop = bits;
+  // the host's copy of the bits (pinned, mapped host memory): a system-scope
+  // store, read by the host after the end of this kernel
+  if (hstop) __hip_atomic_store(hstop, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // u = m - x* (x* may be null = origin)
@@ -378,8 +382,8 @@ hipError_t launch_best(hipStream_t st, bool fp64, int n, int lam, const double* 
 
 hipError_t launch_stop(hipStream_t st, const KParams& kp, const StopParams& sp, const double* m,
                        const double* C, int ldc, const double* B, int ldb, const double* D,
-                       const double* pc, const double* hist, DevScalars* sc) {
-  k_stop<<<1, 256, 0, st>>>(kp, sp, m, C, ldc, B, ldb, D, pc, hist, sc);
+                       const double* pc, const double* hist, DevScalars* sc, uint32_t* hstop) {
+  k_stop<<<1, 256, 0, st>>>(kp, sp, m, C, ldc, B, ldb, D, pc, hist, sc, hstop);
   return hipGetLastError();
 }
 

@@ -9,6 +9,11 @@ import numpy as np
 import oracle as O
 
 TOL = {"fp64": 1e-12, "mixed": 1e-5}
+# fitness values, element by element, relative to |f_i|
+FTOL = {"fp64": 1e-12, "mixed": 5e-6}
+# ranks must agree wherever neighbouring fitness gaps exceed tau * |f|
+# (at least twice the fitness tolerance: below that two values may swap)
+RANK_TAU = {"fp64": 1e-12, "mixed": 1e-5}
 
 
 def rel(a, b):

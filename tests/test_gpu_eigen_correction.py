@@ -160,8 +160,9 @@ def test_non_finite_covariance_after_warm_solves(P):
     """A non-finite C in the middle of a descent whose solves take several
     sweeps: the first batch of sweeps is then queued before the warm start's
     flags are read, runs on NaN, and the solve must still end with the
-    descent stopped (no hang, no error); a restart then decomposes correctly,
-    the solve's set-up having cleared what the NaN left in the A buffers."""
+    descent stopped (no hang; the generation reports CMAES_ENUMERIC); a
+    restart then decomposes correctly, the solve's set-up having cleared what
+    the NaN left in the A buffers."""
     n, lam = 64, 128
     print(f"case non-finite C n={n} lam={lam}", flush=True)
     R, xs = synth.problem(n, seed=1)
@@ -174,7 +175,9 @@ def test_non_finite_covariance_after_warm_solves(P):
         C = s["C"].copy()
         C[3, 5] = C[5, 3] = np.nan
         es.set_state({"n": n, "lambda": lam, "gen": s["gen"], "sigma": s["sigma"], "C": C})
-        es.generation()
+        with pytest.raises(P.CmaesError) as e:
+            es.generation()
+        assert e.value.code == P.binding.CMAES_ENUMERIC
         stop = es.state(arrays=False)["stop"]
         bits = {name: 1 << i for i, name in enumerate(P.STOP_BITS)}
         assert stop & (bits["numeric"] | bits["conditioncov"]), stop
