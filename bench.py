@@ -25,20 +25,39 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "bf16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0}
 
 
+def jacobi_round_work(n):
+    """Work of one block-Jacobi round launch at dimension n (padded N, 16-index
+    blocks, N/16 - 1 rounds per sweep).
+
+    flops: the algorithmic count of a cyclic Jacobi sweep's two-sided update
+    of A, 6 n^3 (each of the n(n-1)/2 rotations updates two rows and two
+    columns, 6 flops per entry pair), spread over the sweep's rounds -- the
+    unit in which the float64 eigensolve is priced against the float64 peak.
+    executed_flops: what one round's float64 MFMA products execute (the
+    lower 32 x 32 tiles Q1^T X Q2 of A and the 32-column pieces V Q of V).
+    bytes: the lower block-pair tiles of A in, all of A out, all of V in and
+    out (float64)."""
+    N = 32 * ((n + 31) // 32)
+    q = N // 32                      # block pairs per round
+    rounds = N // 16 - 1
+    flops = 6.0 * n ** 3 / rounds
+    executed = 2 * (2.0 * 32 ** 3) * (q * (q + 1) // 2) + 2.0 * 32 * 32 * N * q
+    nbytes = 8.0 * ((q * (q + 1) // 2) * 32 * 32 + 3 * N * N)
+    return {"flops": flops, "executed_flops": executed, "bytes": nbytes, "rounds_per_sweep": rounds}
+
+
 def kernel_work(n, lam, precision, sweeps, syrk_cfg=None):
     """Algorithmic work per launch of each timed kernel: (amount, unit, peak,
     bound)."""
     mu = lam // 2
-    N = 32 * ((n + 31) // 32)
-    q = N // 32                      # Jacobi block pairs per round
     f32 = precision != "fp64"
     mm = PEAK["fp32_mfma_tflops"] if f32 else PEAK["fp64_tflops"]
     esz = 4 if f32 else 8
-    # one Jacobi round launch moves, at the least, the lower block-pair tiles
-    # of A in (q(q+1)/2 tiles of 32 x 32), all of A out (tile and mirror) and
-    # all of V in and out, in float64; its arithmetic intensity (~4.7 flop/B)
-    # is below the float64 ridge, so it is priced against HBM
-    jac = 8.0 * ((q * (q + 1) // 2) * 32 * 32 + 3 * N * N)
+    # the Jacobi round runs its tile and V updates on the float64 matrix
+    # cores; it is priced in float64 flops against the float64 peak (its
+    # bytes, ~4.7 flop/B, stay within the caches' reach, and its time is set
+    # by the chain of dependent pair-solve steps)
+    jac = jacobi_round_work(n)["flops"]
     # the mixed covariance epilogue reads each split's float32 partial of every
     # lower 32 x 32 block (4 KiB), the lower triangle of C, and writes all of C
     epi = None
@@ -53,7 +72,7 @@ def kernel_work(n, lam, precision, sweeps, syrk_cfg=None):
         "fitness": (2.0 * n * n * lam, "TFLOP/s", mm, "mfma"),
         "syrk": (float(n) * (n + 1) * mu, "TFLOP/s", mm, "mfma"),
         "eig_gemm": (2.0 * n ** 3, "TFLOP/s", PEAK["fp64_tflops"], "mfma"),
-        "jacobi": (jac, "GB/s", PEAK["hbm_gbs"], "hbm"),
+        "jacobi": (jac, "TFLOP/s", PEAK["fp64_tflops"], "mfma"),
         "rank": (float(lam) * lam, "Gcmp/s", None, "alu"),
     }
     if epi is not None:
@@ -99,7 +118,8 @@ def parse():
     ap.add_argument("--n", type=int, default=1000)
     ap.add_argument("--lam", type=int, default=6144)
     ap.add_argument("--precision", default="mixed")
-    ap.add_argument("--fp64-steps", type=int, default=50)
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="timed generations of the float64 path (default: --steps, on the same window)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -232,27 +252,71 @@ def run_batch(P, torch, steps, warmup, seed):
             "ms_per_batch_generation": 1e3 * el / steps, "sum_lambda": sum(lams)}
 
 
-def cpu_baseline(n, lam, seed, R, xs, budget_s):
+def rel_err(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b))) / (nb if nb > 0 else 1.0)
+
+
+def cpu_baseline(P, n, lam, seed, R, xs, budget_s, precisions=("mixed", "fp64")):
+    """The FP64 oracle timed on the host, and each device path's error against
+    it at the same shape.
+
+    The oracle runs generations of the workload from a seeded synthetic
+    descent state (eigenvalues log-spaced over two decades, sigma = 0.5) for
+    about budget_s seconds; the first of them uses a seeded injected z.  The
+    device paths run that same first generation (same state, same z) through
+    cmaes_generation_with_z, and their results are compared with the
+    oracle's: normwise m, sigma, C, p_sigma, p_c, the fitness values element
+    by element, the eigenvalues, and the device's own reconstruction
+    C = B D^2 B^T and orthogonality."""
     import oracle as O
+    import synth
     try:
         from threadpoolctl import threadpool_info
         threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
     except Exception:
         threads = 1
-    st = O.new_descent(n, lam, 2.0, seed)
+    st = synth.random_state(n, lam, seed=seed + 100, cond=100.0, sigma=0.5, gen=20)
+    Z = synth.normal_matrix(n, lam, seed=seed + 200)
+    dev = {}
+    for prec in precisions:
+        with P.CMAES(n, lam, 2.0, seed=seed, precision=prec, objective="rastrigin", R=R, xstar=xs) as es:
+            es.set_state(st)
+            es.generation_with_z(Z)
+            dev[prec] = es.state()
+    o = O.new_descent(n, lam, 2.0, seed)
+    o.m, o.sigma, o.C, o.B, o.D = st["m"].copy(), st["sigma"], st["C"].copy(), st["B"].copy(), st["D"].copy()
+    o.ps, o.pc, o.gen = st["p_sigma"].copy(), st["p_c"].copy(), st["gen"]
     obj = O.Objective("rastrigin", R, xs)
     gens, t0 = 0, time.perf_counter()
+    info = O.generation(o, obj, Z=Z)
+    gens += 1
+    ref = {"m": o.m.copy(), "sigma": o.sigma, "C": o.C.copy(), "p_sigma": o.ps.copy(), "p_c": o.pc.copy(),
+           "D": o.D.copy(), "f": info["f"].copy()}
     while True:
-        O.generation(st, obj)
-        gens += 1
         el = time.perf_counter() - t0
         if el >= budget_s or el / gens * (gens + 1) > 2.0 * budget_s:
             break
+        O.generation(o, obj)
+        gens += 1
+    el = time.perf_counter() - t0
+    errors = {}
+    for prec, g in dev.items():
+        Cg, Bg, Dg = g["C"], g["B"], g["D"]
+        errors[prec] = {
+            "m": rel_err(g["m"], ref["m"]), "sigma": abs(g["sigma"] - ref["sigma"]) / ref["sigma"],
+            "C": rel_err(Cg, ref["C"]), "p_sigma": rel_err(g["p_sigma"], ref["p_sigma"]),
+            "p_c": rel_err(g["p_c"], ref["p_c"]),
+            "f_max_rel": float(np.max(np.abs(g["f"] - ref["f"]) / np.abs(ref["f"]))),
+            "eigenvalues_max_rel": float(np.max(np.abs(Dg ** 2 - ref["D"] ** 2)) / np.max(ref["D"] ** 2)),
+            "reconstruction": rel_err((Bg * Dg ** 2) @ Bg.T, Cg),
+            "orthogonality": float(np.max(np.abs(Bg.T @ Bg - np.eye(n)))),
+        }
     return {"value": lam * gens / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{gens} FP64 oracle generation(s) of the n={n}, lambda={lam} rotated-Rastrigin "
-                      f"descent from its initial state ({el:.1f} s, NumPy/OpenBLAS {threads} threads, "
+            "sample": f"{gens} FP64 oracle generation(s) of the n={n}, lambda={lam} rotated-Rastrigin workload "
+                      f"from a seeded synthetic descent state ({el:.1f} s, NumPy/OpenBLAS {threads} threads, "
                       f"eigendecomposition every generation)",
-            "gens_per_s": gens / el}
+            "gens_per_s": gens / el, "oracle_error": errors}
 
 
 def default_lambda(n):
@@ -484,7 +548,8 @@ def main():
                     tiles=tiles)
     fp64 = None
     if not a.no_fp64:
-        fp64 = run_gpu(P, torch, n, lam, "fp64", a.fp64_steps, 2, a.seed, R, xs)
+        # the same warm-up and timed window of the descent as the mixed path
+        fp64 = run_gpu(P, torch, n, lam, "fp64", a.fp64_steps or a.steps, a.warmup, a.seed, R, xs)
     gens = 1e3 / mixed["ms_per_step"]
     mu = lam // 2
     ph = mixed["phases_us"]
@@ -493,7 +558,9 @@ def main():
     flop_syrk = float(n) * (n + 1) * mu
     gemm_us = ph["sample"] + ph["fitness"] + ph["covariance"]
     frac = lambda fl, us: (fl / (us * 1e-6)) / 1e12 / PEAK["fp32_mfma_tflops"] if us > 0 else None
-    phase_share = {k: v / (1e3 * mixed["ms_per_step"]) for k, v in ph.items()}
+    # phase times come from one extra generation queued eagerly with an event
+    # between phases (serialised, no graph replay): shares of that pass's sum
+    phase_share = {k: v / sum(ph.values()) for k, v in ph.items()}
     dom = max(ph, key=ph.get)
     out = {
         "metric": METRIC,
@@ -514,8 +581,8 @@ def main():
         "gens_per_s": gens,
         "eig_sweeps_last": mixed["state"]["eig_sweeps"],
         "eig_corrections_last": mixed["state"]["eig_corrections"],
-        "phases_us": ph,
-        "phase_share": phase_share,
+        "phases_us_eager": ph,
+        "phase_share_eager": phase_share,
         "dominant_phase": dom,
         "gemm_mfma_frac": {"sample": frac(flop_sample, ph["sample"]), "fitness": frac(flop_fit, ph["fitness"]),
                            "syrk": frac(flop_syrk, ph["covariance"]),
@@ -533,13 +600,25 @@ def main():
     roof = dict(per_kernel[dom_k])
     roof["traffic"] = measured_traffic(dom_k)
     roof["share_of_step"] = kt[dom_k]["total_us"] / (1e3 * mixed["ms_per_step"])
+    if dom_k == "jacobi":
+        jw = jacobi_round_work(n)
+        roof["executed_flops_per_launch"] = jw["executed_flops"]
+        roof["executed_tflops"] = jw["executed_flops"] / (roof["avg_launch_us"] * 1e-6) / 1e12
+        roof["bytes_per_launch"] = jw["bytes"]
+        roof["achieved_gbs"] = jw["bytes"] / (roof["avg_launch_us"] * 1e-6) / 1e9
+        roof["limiter"] = ("latency: each round waits for the previous round's pair solves (a chain of "
+                           "dependent rotation steps) and for the launch before it")
     out["roofline"] = roof
     out["kernels"] = {k: {**kt[k], "roofline": per_kernel.get(k)} for k in kt}
     out["gemm_tiles"] = mixed["tiles"]
     if a.batch_steps > 0:
         out["batch"] = run_batch(P, torch, a.batch_steps, 3, a.seed)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, lam, a.seed, R, xs, a.cpu_seconds)
+        cb = cpu_baseline(P, n, lam, a.seed, R, xs, a.cpu_seconds)
+        # each result's error against the FP64 oracle, one generation from the
+        # same state and z at the headline shape
+        out["oracle_error"] = cb.pop("oracle_error")
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
