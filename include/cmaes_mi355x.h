@@ -181,6 +181,19 @@ int cmaes_generation_with_z(cmaes_t* h, const double* Z);
  * a stopped descent (as cmaes_generation). */
 int cmaes_ask(cmaes_t* h, double* X);
 
+/* Allocation-free variant of cmaes_ask(), for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): identical points, but staged in the library's
+ * static device array (8 MiB on each device, held until the process ends)
+ * instead of a buffer the handle allocates on its first ask.  It calls no
+ * hipMalloc, hipFree or other allocating routine.  Returns CMAES_EINVAL if
+ * n * lambda exceeds 1048576 (the array's doubles), CMAES_ESTATE if the
+ * handle's buffers do not exist yet (any earlier cmaes_state,
+ * cmaes_set_objective or generation call creates them) or the descent has
+ * stopped.  All calls on one device share the array: calls on one device
+ * that overlap in time (from different host threads) race. */
+int cmaes_ask_noalloc(cmaes_t* h, double* X);
+
 /* Host blackbox path, second half: supply the lambda fitness values of the
  * points returned by the last cmaes_ask() (NaN counts as +inf) and run the
  * rest of the generation.  CMAES_ESTATE without a pending ask;

@@ -123,6 +123,7 @@ def _load():
         "cmaes_generation": (C.c_int, [H]),
         "cmaes_generation_with_z": (C.c_int, [H, _PD]),
         "cmaes_ask": (C.c_int, [H, _PD]),
+        "cmaes_ask_noalloc": (C.c_int, [H, _PD]),
         "cmaes_tell": (C.c_int, [H, _PD]),
         "cmaes_restart_ipop": (C.c_int, [H]),
         "cmaes_ipop_run": (C.c_int, [H, C.POINTER(C.c_int)]),
@@ -169,7 +170,7 @@ def _load():
 _lib = _load()
 EXPORTED = ["cmaes_default_options", "cmaes_create", "cmaes_destroy", "cmaes_set_options",
             "cmaes_get_options", "cmaes_set_objective", "cmaes_generation", "cmaes_generation_with_z",
-            "cmaes_ask", "cmaes_tell", "cmaes_restart_ipop", "cmaes_ipop_run", "cmaes_state",
+            "cmaes_ask", "cmaes_ask_noalloc", "cmaes_tell", "cmaes_restart_ipop", "cmaes_ipop_run", "cmaes_state",
             "cmaes_set_state", "cmaes_enable_timing", "cmaes_phase_times", "cmaes_enable_kernel_timing",
             "cmaes_enable_graphs", "cmaes_batch_enable_graphs", "cmaes_set_eigen_correction",
             "cmaes_kernel_times", "cmaes_last_error", "cmaes_gemm_config_count", "cmaes_gemm_config_info",
@@ -254,6 +255,12 @@ def cmaes_generation_with_z(h, Z):
 def cmaes_ask(h, n: int, lam: int) -> np.ndarray:
     X = np.empty((n, lam), dtype=np.float64, order="F")
     _check(_lib.cmaes_ask(h, _dptr(X)))
+    return X
+
+
+def cmaes_ask_noalloc(h, n: int, lam: int) -> np.ndarray:
+    X = np.empty((n, lam), dtype=np.float64, order="F")
+    _check(_lib.cmaes_ask_noalloc(h, _dptr(X)))
     return X
 
 

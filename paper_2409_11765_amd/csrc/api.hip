@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -78,6 +79,7 @@ struct cmaes {
   cmaes_options_t opt{};
   hipStream_t st = nullptr;
   bool own_stream = false;
+  int dev = 0;  // the HIP device the handle was created on
   // device allocator of every buffer of the handle, fixed at its first
   // allocation (options.dev_malloc / dev_free / alloc_ctx; null = hipMalloc)
   void* (*alloc_fn)(size_t, void*) = nullptr;
@@ -768,6 +770,7 @@ cmaes_t* cmaes_create(int n, int lambda, double sigma0, uint64_t seed) {
     set_error("host allocation failed");
     return nullptr;
   }
+  h->dev = dev;
   h->n = n;
   h->lam = h->lam0 = lambda;
   h->sigma0 = sigma0;
@@ -911,28 +914,90 @@ __global__ void k_points(int n, int lam, const double* __restrict__ m, const T* 
 
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+
+// the sampling step of an ask, then x_k = m + sigma y_k staged in dX (n * lam
+// float64 device memory) and copied into the caller's X
+int ask_into(cmaes* h, double* X, double* dX) {
+  const int n = h->n, lam = h->lam;
+  if (int rc = phase_sample(h, nullptr)) return rc;
+  const int64_t total = static_cast<int64_t>(n) * lam;
+  const int blocks = static_cast<int>((total + 255) / 256);
+  if (h->fp64)
+    k_points<double><<<blocks, 256, 0, h->st>>>(n, lam, h->m, static_cast<const double*>(h->Y), h->ldn, h->sc, dX);
+  else
+    k_points<float><<<blocks, 256, 0, h->st>>>(n, lam, h->m, static_cast<const float*>(h->Y), h->ldn, h->sc, dX);
+  CMX_HIP(hipGetLastError());
+  CMX_HIP(hipMemcpyAsync(X, dX, 8ull * total, hipMemcpyDeviceToHost, h->st));
+  CMX_HIP(hipStreamSynchronize(h->st));
+  h->ask_pending = true;
+  return CMAES_OK;
+}
+
+// Staging memory of cmaes_ask_noalloc: a file-scope device array, one copy on
+// every device the library runs on, held until the process ends.  In host
+// code `scratch` names a host-side stand-in, not device memory: its device
+// address on each device comes from hipGetSymbolAddress (made current device
+// by device, once) and only that address is passed to kernels and copies.
+constexpr size_t kScratchDoubles = size_t{1} << 20;  // 8 MiB
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on device dev (resolved on first use, with
+// dev current; the caller's current device is restored)
+int scratch_on(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(CMAES_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    CMX_HIP(hipGetDevice(&cur));
+    if (cur != dev) CMX_HIP(hipSetDevice(dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || p == nullptr)
+      return fail(CMAES_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
 int cmaes_ask(cmaes_t* h, double* X) {
   if (int rc = check(h)) return rc;
   if (!X) return fail(CMAES_EINVAL, "null X");
   if (int rc = ensure_ready(h)) return rc;
   if (int rc = check_running(h)) return rc;
-  const int n = h->n, lam = h->lam;
-  if (!h->X || h->cap_lam < lam) {
+  if (!h->X || h->cap_lam < h->lam) {
     dev_free(h, h->X);
-    if (int rc = dev_alloc(h, &h->X, 8ull * n * h->cap_lam)) return rc;
+    if (int rc = dev_alloc(h, &h->X, 8ull * h->n * h->cap_lam)) return rc;
   }
-  if (int rc = phase_sample(h, nullptr)) return rc;
-  const int64_t total = static_cast<int64_t>(n) * lam;
-  const int blocks = static_cast<int>((total + 255) / 256);
-  if (h->fp64)
-    k_points<double><<<blocks, 256, 0, h->st>>>(n, lam, h->m, static_cast<const double*>(h->Y), h->ldn, h->sc, h->X);
-  else
-    k_points<float><<<blocks, 256, 0, h->st>>>(n, lam, h->m, static_cast<const float*>(h->Y), h->ldn, h->sc, h->X);
-  CMX_HIP(hipGetLastError());
-  CMX_HIP(hipMemcpyAsync(X, h->X, 8ull * total, hipMemcpyDeviceToHost, h->st));
-  CMX_HIP(hipStreamSynchronize(h->st));
-  h->ask_pending = true;
-  return CMAES_OK;
+  return ask_into(h, X, h->X);
+}
+
+int cmaes_ask_noalloc(cmaes_t* h, double* X) {
+  if (int rc = check(h)) return rc;
+  if (!X) return fail(CMAES_EINVAL, "null X");
+  if (!h->allocated)
+    return fail(CMAES_ESTATE, "cmaes_ask_noalloc needs a handle whose buffers exist (call cmaes_state, "
+                              "cmaes_set_objective or cmaes_generation once first)");
+  if (static_cast<size_t>(h->n) * static_cast<size_t>(h->lam) > kScratchDoubles)
+    return fail(CMAES_EINVAL, "cmaes_ask_noalloc: n * lambda = " +
+                                  std::to_string(static_cast<size_t>(h->n) * h->lam) + " exceeds the " +
+                                  std::to_string(kScratchDoubles) + " doubles of the static staging area");
+  if (int rc = check_running(h)) return rc;
+  double* dX = nullptr;
+  if (int rc = scratch_on(h->dev, &dX)) return rc;
+  return ask_into(h, X, dX);
 }
 
 int cmaes_tell(cmaes_t* h, const double* f) {
