@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -30,6 +31,10 @@ static_assert(CMAES_NUM_SITES == G32_NUM_SITES && CMAES_SITE_SYRK == G32_SYRK, "
 static_assert(CMAES_NUM_KERNELS == KID_COUNT, "kernel ids and header disagree");
 
 namespace {
+
+// buffer epochs, unique over all handles of the process (a handle created at
+// the address of a destroyed one never repeats its epoch)
+std::atomic<uint64_t> g_epoch{1};
 
 // tutorial default parameters (positive weights), identical to the oracle's reading
 struct HostParams {
@@ -200,7 +205,7 @@ void drop_graphs(cmaes* h) {
     h->gx[i] = nullptr;
     h->gkey[i] = 0;
   }
-  h->epoch += 1;
+  h->epoch = g_epoch.fetch_add(1);
 }
 
 void free_all(cmaes* h) {
@@ -239,6 +244,7 @@ void free_all(cmaes* h) {
   dev_free(h, h->ew.part);
   dev_free(h, h->ew.scale);
   dev_free(h, h->ew.status);
+  dev_free(h, h->ew.gctl);
   if (h->ew.hflags) (void)hipHostFree(h->ew.hflags);
   h->ew.hflags = nullptr;
   h->ew.dflags = nullptr;
@@ -316,7 +322,7 @@ int alloc_fixed(cmaes* h) {
       (rc = dev_alloc(h, &h->ew.X1, 8ull * N * N)) || (rc = dev_alloc(h, &h->ew.X2, 8ull * N * N)) ||
       (rc = dev_alloc(h, &h->ew.evals, 8ull * N)) || (rc = dev_alloc(h, &h->ew.perm, 4ull * N)) ||
       (rc = dev_alloc(h, &h->ew.sign, 8ull * N)) || (rc = dev_alloc(h, &h->ew.scale, 16)) ||
-      (rc = dev_alloc(h, &h->ew.status, 16)))
+      (rc = dev_alloc(h, &h->ew.status, 16)) || (rc = dev_alloc(h, &h->ew.gctl, 4ull * GC_WORDS)))
     return rc;
   {
     const int q = N / 32;
@@ -393,6 +399,7 @@ int init_descent(cmaes* h, bool fresh) {
   std::vector<double> ones(n, 1.0);
   CMX_HIP(hipMemcpyAsync(h->D, ones.data(), 8ull * n, hipMemcpyHostToDevice, h->st));
   CMX_HIP(launch_to_precision(h->st, h->fp64, h->B, h->ldn, h->BD, h->ldn, n, n));
+  CMX_HIP(hipMemsetAsync(h->ew.gctl, 0, 4ull * GC_WORDS, h->st));  // no previous solve
   CMX_HIP(hipStreamSynchronize(h->st));  // s and ones are consumed
   *h->hstop = 0;
   h->stop_pending = false;
@@ -771,6 +778,7 @@ cmaes_t* cmaes_create(int n, int lambda, double sigma0, uint64_t seed) {
     return nullptr;
   }
   h->dev = dev;
+  h->epoch = g_epoch.fetch_add(1);
   h->n = n;
   h->lam = h->lam0 = lambda;
   h->sigma0 = sigma0;
@@ -1117,6 +1125,7 @@ int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in) {
     CMX_HIP(hipMemcpy2DAsync(h->C, 8ull * ldn, in->C, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice, h->st));
   if (in->B) {
     CMX_HIP(hipMemcpy2DAsync(h->B, 8ull * ldn, in->B, 8ull * n, 8ull * n, n, hipMemcpyHostToDevice, h->st));
+    CMX_HIP(hipMemsetAsync(h->ew.gctl, 0, 4ull * GC_WORDS, h->st));  // no previous solve
     h->reorth_sweeps = 0;  // taken as orthogonal
     h->eig_uncounted = false;
     h->ew.last_sweeps = 0;
@@ -1320,9 +1329,72 @@ int cmaes_syrk_plan(int cfg, int n, int K, int32_t* tiles, int32_t* kspan, int32
 // synchronisation per sweep for the whole batch.  An instance whose stop
 // tests fire is restarted with the same population size (restart-on-finish).
 
+namespace {
+
+// The eigensolves of a set of descents stepped together (the batch of
+// concurrent descents, the K-Replicated tree): one grouped solve on a stream
+// of the set's own, which waits for every due descent's front and which the
+// descents' stop tests wait for.
+struct LockstepGroup {
+  hipStream_t st = nullptr;
+  hipEvent_t done = nullptr;
+  GroupEig ge;
+  std::vector<cmaes*> members;  // the descents the table was built for
+  std::vector<uint64_t> epochs;  // their buffer epochs then
+  std::vector<hipEvent_t> ev;    // per member: the end of its front
+  std::vector<int> sweeps;
+};
+
+int group_init(LockstepGroup& g) {
+  CMX_HIP(hipStreamCreateWithFlags(&g.st, hipStreamNonBlocking));
+  CMX_HIP(hipEventCreateWithFlags(&g.done, hipEventDisableTiming));
+  return 0;
+}
+
+void group_destroy(LockstepGroup& g) {
+  if (g.st) (void)hipStreamSynchronize(g.st);
+  group_eig_release(g.ge);
+  for (auto e : g.ev)
+    if (e) (void)hipEventDestroy(e);
+  g.ev.clear();
+  if (g.done) (void)hipEventDestroy(g.done);
+  if (g.st) (void)hipStreamDestroy(g.st);
+  g = LockstepGroup{};
+}
+
+GEigDesc eig_desc(cmaes* h) {
+  GEigDesc e{};
+  EigWork& w = h->ew;
+  e.A = w.A;
+  e.A2 = w.A2;
+  e.V = w.V;
+  e.Q = w.Q;
+  e.Q2 = w.Q2;
+  e.part = w.part;
+  e.scale = w.scale;
+  e.status = w.status;
+  e.ctl = w.gctl;
+  e.B = h->B;
+  e.ldb = h->ldn;
+  e.D = h->D;
+  e.BD = h->BD;
+  e.ldbd = h->ldn;
+  e.bd64 = h->fp64 ? 1 : 0;
+  e.evals = w.evals;
+  e.perm = w.perm;
+  e.sign = w.sign;
+  e.sc = h->sc;
+  e.n = h->n;
+  e.N = w.N;
+  return e;
+}
+
+}  // namespace
+
 struct cmaes_batch {
   std::vector<cmaes*> inst;
   std::vector<int32_t> restarts;
+  LockstepGroup grp;
 };
 
 namespace {
@@ -1334,31 +1406,63 @@ int restart_same_lambda(cmaes* h) {
 }
 
 // one generation of every handle: all fronts queued first (each on its own
-// stream), then the eigensolve sweeps of all handles advanced in lockstep with
-// one host synchronisation per sweep for the whole set, then the stop tests
-int lockstep_generation(const std::vector<cmaes*>& hs) {
+// stream, the warm start of a due eigensolve included), then one grouped
+// eigensolve of every due handle (one launch per round for all of them,
+// convergence decided on the device), then the stop tests
+int lockstep_generation(LockstepGroup& g, const std::vector<cmaes*>& hs) {
   for (cmaes* h : hs)
     if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "every instance needs a fused objective");
+  const int count = static_cast<int>(hs.size());
+  if (count > kGroupMax) return fail(CMAES_EINVAL, "too many descents in one lockstep group");
   for (cmaes* h : hs) {
     if (int rc = ensure_ready(h)) return rc;
     if (int rc = front(h)) return rc;
   }
-  std::vector<cmaes*> pending;
-  for (cmaes* h : hs)
-    if (h->eig_due) {
-      bool done = false;
-      if (int rc = eigen_advance(h, &done, true)) return rc;  // first batch, no wait
-      pending.push_back(h);
+  GroupDueMask due{};
+  int ahead = 0;
+  bool any = false;
+  for (int i = 0; i < count; ++i)
+    if (hs[i]->eig_due) {
+      due.w[i >> 5] |= 1u << (i & 31);
+      any = true;
+      // the run of sweeps a descent makes before its first convergence test
+      const int last = hs[i]->ew.last_sweeps;
+      ahead = std::max(ahead, last >= 2 ? last - 1 : 0);
     }
-  while (!pending.empty()) {
-    for (cmaes* h : pending) CMX_HIP(hipStreamSynchronize(h->st));
-    std::vector<cmaes*> still;
-    for (cmaes* h : pending) {
-      bool done = false;
-      if (int rc = eigen_advance(h, &done)) return rc;
-      if (!done) still.push_back(h);
+  if (any) {
+    bool same = g.members == hs && static_cast<int>(g.epochs.size()) == count;
+    for (int i = 0; same && i < count; ++i) same = g.epochs[i] == hs[i]->epoch;
+    if (!same) {
+      std::vector<GEigDesc> descs;
+      for (cmaes* h : hs) descs.push_back(eig_desc(h));
+      if (int rc = group_eig_build(g.st, g.ge, descs)) return rc;
+      g.members = hs;
+      g.epochs.clear();
+      for (cmaes* h : hs) g.epochs.push_back(h->epoch);
     }
-    pending.swap(still);
+    while (static_cast<int>(g.ev.size()) < count) {
+      hipEvent_t e = nullptr;
+      CMX_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      g.ev.push_back(e);
+    }
+    for (int i = 0; i < count; ++i)
+      if (hs[i]->eig_due) {
+        CMX_HIP(hipEventRecord(g.ev[i], hs[i]->st));
+        CMX_HIP(hipStreamWaitEvent(g.st, g.ev[i], 0));
+      }
+    g.sweeps.assign(count, 0);
+    if (int rc = group_eig_solve(g.st, g.ge, due, 40, ahead, g.sweeps.data())) return rc;
+    CMX_HIP(hipEventRecord(g.done, g.st));
+    for (int i = 0; i < count; ++i)
+      if (hs[i]->eig_due) {
+        cmaes* h = hs[i];
+        CMX_HIP(hipStreamWaitEvent(h->st, g.done, 0));
+        h->ew.sweeps = g.sweeps[i];
+        h->ew.corrections = 0;
+        h->ew.last_sweeps = g.sweeps[i];
+        h->ew.last_closed = false;
+        h->ew.pending = false;
+      }
   }
   for (cmaes* h : hs)
     if (int rc = phase_update_post(h)) return rc;
@@ -1386,6 +1490,12 @@ cmaes_batch_t* cmaes_batch_create(int count, const int* n, const int* lambda, co
     set_error("host allocation failed");
     return nullptr;
   }
+  if (group_init(b->grp)) {
+    const std::string why = g_err;
+    cmaes_batch_destroy(b);
+    set_error(why);
+    return nullptr;
+  }
   for (int k = 0; k < count; ++k) {
     cmaes* h = cmaes_create(n[k], lambda[k], sigma0[k], seed[k]);
     if (!h) {
@@ -1402,6 +1512,7 @@ cmaes_batch_t* cmaes_batch_create(int count, const int* n, const int* lambda, co
 
 void cmaes_batch_destroy(cmaes_batch_t* b) {
   if (!b) return;
+  group_destroy(b->grp);
   for (cmaes* h : b->inst) cmaes_destroy(h);
   delete b;
 }
@@ -1436,7 +1547,7 @@ int cmaes_batch_set_objective(cmaes_batch_t* b, int k, int kind, const double* R
 
 int cmaes_batch_generation(cmaes_batch_t* b) {
   if (!b) return fail(CMAES_EINVAL, "null batch");
-  if (int rc = lockstep_generation(b->inst)) return rc;
+  if (int rc = lockstep_generation(b->grp, b->inst)) return rc;
   // restart-on-finish with the same population size
   for (size_t k = 0; k < b->inst.size(); ++k) {
     cmaes* h = b->inst[k];
@@ -1502,6 +1613,7 @@ struct cmaes_krep {
   double released_best = HUGE_VAL; // best f of released handles
   int64_t lockstep_gens = 0;
   bool done = false;
+  LockstepGroup grp;
 };
 
 namespace {
@@ -1540,6 +1652,12 @@ cmaes_krep_t* cmaes_krep_create(int n, int lambda_start, int k_max, double sigma
     set_error("host allocation failed");
     return nullptr;
   }
+  if (group_init(r->grp)) {
+    const std::string why = g_err;
+    cmaes_krep_destroy(r);
+    set_error(why);
+    return nullptr;
+  }
   r->n = n;
   r->k_max = k_max;
   while ((1 << r->levels) < k_max) ++r->levels;
@@ -1571,6 +1689,7 @@ cmaes_krep_t* cmaes_krep_create(int n, int lambda_start, int k_max, double sigma
 
 void cmaes_krep_destroy(cmaes_krep_t* r) {
   if (!r) return;
+  group_destroy(r->grp);
   for (cmaes* h : r->handle) cmaes_destroy(h);
   delete r;
 }
@@ -1613,7 +1732,7 @@ int cmaes_krep_generation(cmaes_krep_t* r) {
         slot.push_back(s);
       }
     }
-  if (int rc = lockstep_generation(run)) return rc;
+  if (int rc = lockstep_generation(r->grp, run)) return rc;
   r->lockstep_gens += 1;
   double best = r->released_best;
   for (size_t i = 0; i < run.size(); ++i) {

@@ -33,6 +33,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <cstring>
 #include <functional>
 #include <vector>
 
@@ -293,13 +294,12 @@ __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, doubl
 
 // First pair solves of a descent's eigensolve: round 0 (with the intra-block
 // rotations) straight from A.
-__global__ void __launch_bounds__(256) k_jac_first(const double* __restrict__ A, int N, int p,
-                                                   const double* __restrict__ scale, double* __restrict__ Qg) {
-  __shared__ double lds[3 * kS * kLD];
+__device__ __forceinline__ void jac_first_body(int P, const double* __restrict__ A, int N, int p,
+                                               const double* __restrict__ scale, double* __restrict__ Qg,
+                                               double* lds) {
   double* S0 = lds;
   double* S1 = lds + kS * kLD;
   double* Q = lds + 2 * kS * kLD;
-  const int P = blockIdx.x;
   int I, J;
   block_pair(p, 0, P, I, J);
   for (int idx = threadIdx.x; idx < kS * kS; idx += 256) {
@@ -309,6 +309,12 @@ __global__ void __launch_bounds__(256) k_jac_first(const double* __restrict__ A,
   __syncthreads();
   const double sc = *scale;
   rotate_pair(S0, S1, Q, 2.2e-16 * sc, sc > 0.0 ? 1.0 / sc : 0.0, true, Qg + static_cast<int64_t>(P) * kS * kS);
+}
+
+__global__ void __launch_bounds__(256) k_jac_first(const double* __restrict__ A, int N, int p,
+                                                   const double* __restrict__ scale, double* __restrict__ Qg) {
+  __shared__ double lds[3 * kS * kLD];
+  jac_first_body(blockIdx.x, A, N, p, scale, Qg, lds);
 }
 
 // One outer round r: workgroups [0, q) run the pair solves of the next round
@@ -331,16 +337,15 @@ __device__ __forceinline__ void store_through(double* p, double v) {
 constexpr int kLU = kNB + 1;                           // row stride of the 32 x 16 stage-1 products
 constexpr int kRoundLds = 3 * kS * kLD + 3 * kS * kLU;  // doubles of LDS per workgroup
 
-__global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Acur, double* __restrict__ Anext,
-                                                   double* __restrict__ V, const double* __restrict__ Qcur,
-                                                   double* __restrict__ Qnext, int N, int r,
-                                                   const double* __restrict__ scale, double* __restrict__ tilepart) {
-  __shared__ double lds[kRoundLds];
+__device__ __forceinline__ void jac_round_body(int b, const double* __restrict__ Acur, double* __restrict__ Anext,
+                                               double* __restrict__ V, const double* __restrict__ Qcur,
+                                               double* __restrict__ Qnext, int N, int r,
+                                               const double* __restrict__ scale, double* __restrict__ tilepart,
+                                               double* lds) {
   const int p = N / kNB, q = p / 2;
   const int ntiles = q * (q + 1) / 2;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  int b = blockIdx.x;
   if (b < q) {
     // ---- pair solve of the next round.  Its 32 x 32 problem S is made of
     // three 16 x 16 blocks of the round-r output, recomputed here from A_cur
@@ -539,6 +544,14 @@ __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Ac
     store_through(&V[static_cast<int64_t>(gidx(I, J, bm * kNB + lk + 4 * rr)) * N + rc * kS + bn * kNB + li], acc[rr]);
 }
 
+__global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Acur, double* __restrict__ Anext,
+                                                   double* __restrict__ V, const double* __restrict__ Qcur,
+                                                   double* __restrict__ Qnext, int N, int r,
+                                                   const double* __restrict__ scale, double* __restrict__ tilepart) {
+  __shared__ double lds[kRoundLds];
+  jac_round_body(blockIdx.x, Acur, Anext, V, Qcur, Qnext, N, r, scale, tilepart, lds);
+}
+
 // off-diagonal / total squared norms and max |diagonal| of A, per column
 __global__ void __launch_bounds__(256) k_offnorm_cols(const double* __restrict__ A, int N, int n,
                                                       double* __restrict__ part) {
@@ -573,9 +586,9 @@ __global__ void __launch_bounds__(256) k_offnorm_cols(const double* __restrict__
 // flags is the device address of pinned host memory: the host reads it once
 // the stream has drained, so the stores are system-scope (written through to
 // host memory) and no copy is queued for them.
-__global__ void __launch_bounds__(256) k_offnorm_final(const double* __restrict__ part, int count,
-                                                       int* __restrict__ flags, double* __restrict__ scale) {
-  __shared__ double red[3][256];
+// (off, tot, dmax) over count partial triples, summed in a fixed order by the
+// 256 threads of the workgroup; the totals are in red[.][0] afterwards
+__device__ __forceinline__ void offnorm_reduce(const double* __restrict__ part, int count, double (*red)[256]) {
   const int t = threadIdx.x;
   double off = 0.0, tot = 0.0, dmax = 0.0;
   for (int c = t; c < count; c += 256) {
@@ -595,14 +608,34 @@ __global__ void __launch_bounds__(256) k_offnorm_final(const double* __restrict_
     }
     __syncthreads();
   }
-  if (t == 0) {
-    const bool finite = isfinite(red[1][0]);
-    __hip_atomic_store(&flags[0], (finite && red[0][0] > kOffTol * kOffTol * red[1][0]) ? 1 : 0, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&flags[1], finite ? 0 : 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&flags[2], (finite && red[0][0] <= kCorrOff * kCorrOff * red[1][0]) ? 1 : 0,
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// flags: more sweeps needed, non-finite, small enough for a closing correction
+__device__ __forceinline__ void offnorm_flags(double off, double tot, int& more, int& nonfinite, int& small) {
+  const bool finite = isfinite(tot);
+  more = (finite && off > kOffTol * kOffTol * tot) ? 1 : 0;
+  nonfinite = finite ? 0 : 1;
+  small = (finite && off <= kCorrOff * kCorrOff * tot) ? 1 : 0;
+}
+
+// dctl (device memory, may be null): words 4 and 5 of a grouped solve's
+// control block receive the first two flags as well
+__global__ void __launch_bounds__(256) k_offnorm_final(const double* __restrict__ part, int count,
+                                                       int* __restrict__ flags, double* __restrict__ scale,
+                                                       int* __restrict__ dctl) {
+  __shared__ double red[3][256];
+  offnorm_reduce(part, count, red);
+  if (threadIdx.x == 0) {
+    int more, nonfinite, small;
+    offnorm_flags(red[0][0], red[1][0], more, nonfinite, small);
+    __hip_atomic_store(&flags[0], more, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&flags[1], nonfinite, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&flags[2], small, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     scale[0] = red[2][0];
+    if (dctl) {
+      dctl[4] = more;
+      dctl[5] = nonfinite;
+    }
   }
 }
 
@@ -768,12 +801,12 @@ __global__ void k_copy_block(const double* __restrict__ src, int lds, int n, dou
 // the diagonal is staged through LDS in chunks, kRankTPI threads count for one
 // eigenvalue (every kRankTPI-th entry each) and sum their integer counts
 constexpr int kRankTPI = 8;
-__global__ void __launch_bounds__(256) k_eig_rank(const double* __restrict__ A, int N, int n,
-                                                  int32_t* __restrict__ perm, double* __restrict__ ev,
-                                                  const int* __restrict__ status, DevScalars* __restrict__ sc) {
-  __shared__ double dg[1024];
+__device__ __forceinline__ void eig_rank_body(int bx, const double* __restrict__ A, int N, int n,
+                                              int32_t* __restrict__ perm, double* __restrict__ ev,
+                                              const int* __restrict__ status, DevScalars* __restrict__ sc,
+                                              double* dg) {
   const int sub = threadIdx.x % kRankTPI;
-  const int i = blockIdx.x * (256 / kRankTPI) + threadIdx.x / kRankTPI;
+  const int i = bx * (256 / kRankTPI) + threadIdx.x / kRankTPI;
   const double vi = i < n ? A[static_cast<int64_t>(i) * N + i] : 0.0;
   int cnt = 0;
   for (int base = 0; base < n; base += 1024) {
@@ -800,12 +833,16 @@ __global__ void __launch_bounds__(256) k_eig_rank(const double* __restrict__ A, 
   }
 }
 
+__global__ void __launch_bounds__(256) k_eig_rank(const double* __restrict__ A, int N, int n,
+                                                  int32_t* __restrict__ perm, double* __restrict__ ev,
+                                                  const int* __restrict__ status, DevScalars* __restrict__ sc) {
+  __shared__ double dg[1024];
+  eig_rank_body(blockIdx.x, A, N, n, perm, ev, status, sc, dg);
+}
+
 // sign of each column: the entry of largest magnitude (first on ties) made positive
-__global__ void __launch_bounds__(256) k_colsign(const double* __restrict__ Bn, int ld, int n,
-                                                 double* __restrict__ sign) {
-  __shared__ double bv[256];
-  __shared__ int bi[256];
-  const int c = blockIdx.x;
+__device__ __forceinline__ void colsign_body(int c, const double* __restrict__ Bn, int ld, int n,
+                                             double* __restrict__ sign, double* bv, int* bi) {
   double best = -1.0;
   int arg = 0;
   for (int r = threadIdx.x; r < n; r += 256) {
@@ -832,13 +869,19 @@ __global__ void __launch_bounds__(256) k_colsign(const double* __restrict__ Bn, 
   if (threadIdx.x == 0) sign[c] = Bn[static_cast<int64_t>(c) * ld + bi[0]] < 0.0 ? -1.0 : 1.0;
 }
 
+__global__ void __launch_bounds__(256) k_colsign(const double* __restrict__ Bn, int ld, int n,
+                                                 double* __restrict__ sign) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  colsign_body(blockIdx.x, Bn, ld, n, sign, bv, bi);
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_permute(const double* __restrict__ Bn, int ldt, int n,
-                                                 const int32_t* __restrict__ perm, const double* __restrict__ ev,
-                                                 const double* __restrict__ sign, double* __restrict__ B, int ldb,
-                                                 double* __restrict__ D, T* __restrict__ BD, int ldbd) {
-  const int r = blockIdx.y;  // output column
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void permute_body(int bx, int r, const double* __restrict__ Bn, int ldt, int n,
+                                             const int32_t* __restrict__ perm, const double* __restrict__ ev,
+                                             const double* __restrict__ sign, double* __restrict__ B, int ldb,
+                                             double* __restrict__ D, T* __restrict__ BD, int ldbd) {
+  const int row = bx * blockDim.x + threadIdx.x;  // r: output column
   const int c = perm[r];
   const double d = sqrt(fmax(ev[c], 0.0));
   if (row == 0) D[r] = d;
@@ -846,6 +889,166 @@ __global__ void __launch_bounds__(256) k_permute(const double* __restrict__ Bn, 
   const double v = sign[c] * Bn[static_cast<int64_t>(c) * ldt + row];
   B[static_cast<int64_t>(r) * ldb + row] = v;
   BD[static_cast<int64_t>(r) * ldbd + row] = static_cast<T>(v * d);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_permute(const double* __restrict__ Bn, int ldt, int n,
+                                                 const int32_t* __restrict__ perm, const double* __restrict__ ev,
+                                                 const double* __restrict__ sign, double* __restrict__ B, int ldb,
+                                                 double* __restrict__ D, T* __restrict__ BD, int ldbd) {
+  permute_body<T>(blockIdx.x, blockIdx.y, Bn, ldt, n, perm, ev, sign, B, ldb, D, BD, ldbd);
+}
+
+// ---- grouped eigensolve: the sweeps of many descents (one per entry of a
+// descriptor table, uneven n allowed) advance together, one launch per round
+// for all of them.  Each launch's workgroups are split over the descents by a
+// prefix-sum table (workgroup w belongs to descent i with off[i] <= w <
+// off[i + 1]); a descent's convergence is decided on the device, at the end
+// of each of its sweeps, by the last of its tile workgroups to finish (a
+// counter in its control block), so the host only waits for the whole group.
+// The arithmetic of every step is that of the single-descent solve (the same
+// bodies, the same reduction order), without the closing correction.
+
+__device__ __forceinline__ int group_find(const int* __restrict__ off, int count, int w) {
+  int lo = 0, hi = count;  // off[lo] <= w < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= w)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool due_bit(const GroupDueMask& m, int i) { return (m.w[i >> 5] >> (i & 31)) & 1u; }
+
+// one workgroup per descent: whether its solve sweeps at all (from the warm
+// start's flags and the previous solve's sweep count, as the single-descent
+// solve decides), and the control words of the solve
+__global__ void __launch_bounds__(64) kg_start(const GEigDesc* __restrict__ g, int count, GroupDueMask due,
+                                                int max_sweeps, int* __restrict__ hactive,
+                                                int* __restrict__ hsweeps) {
+  const int i = blockIdx.x;
+  if (i >= count || threadIdx.x != 0) return;
+  int* c = g[i].ctl;
+  const int d = due_bit(due, i) ? 1 : 0;
+  c[GC_DUE] = d;
+  if (!d) return;
+  const int last = c[GC_LAST];
+  const int mins = last >= 2 ? min(last - 1, max_sweeps) : 0;
+  const int more = c[GC_MORE], nonfin = c[GC_NONFIN];
+  const bool active = mins > 0 || (more && !nonfin);
+  c[GC_MIN] = mins;
+  c[GC_CNT] = 0;
+  if (active) {
+    c[GC_STOPR] = 0x7fffffff;
+    __hip_atomic_fetch_add(hactive, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  } else {
+    c[GC_STOPR] = 0;
+    c[GC_LAST] = 0;
+    int* st = g[i].status;
+    st[0] = nonfin ? 3 : (more ? 2 : 1);
+    st[1] = 0;
+    st[2] = 0;
+    __hip_atomic_store(&hsweeps[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// the first pair solves (round 0 with the intra-block rotations) of every
+// sweeping descent, from its warm-started A
+__global__ void __launch_bounds__(256) kg_first(const GEigDesc* __restrict__ g, const int* __restrict__ off,
+                                                int count) {
+  __shared__ double lds[3 * kS * kLD];
+  const int i = group_find(off, count, blockIdx.x);
+  const GEigDesc& e = g[i];
+  if (!e.ctl[GC_DUE] || e.ctl[GC_STOPR] == 0) return;
+  jac_first_body(blockIdx.x - off[i], e.A, e.N, e.N / kNB, e.scale, e.Q, lds);
+}
+
+// global round rg of the group: descent i runs its round rg mod (p_i - 1)
+// (every descent starts its first sweep at rg = 0) until the round after the
+// one in which it stopped; A and Q ping-pong with the parity of rg.  The
+// scale that sets the rotation threshold is double buffered by sweep parity:
+// sweep s reads scale[s & 1], its closing workgroup writes scale[(s + 1) & 1].
+__global__ void __launch_bounds__(256) kg_round(const GEigDesc* __restrict__ g, const int* __restrict__ off,
+                                                int count, int rg, int max_sweeps, int* __restrict__ hactive,
+                                                int* __restrict__ hsweeps) {
+  __shared__ double lds[kRoundLds];
+  __shared__ double red[3][256];
+  __shared__ int last;
+  const int i = group_find(off, count, blockIdx.x);
+  const GEigDesc& e = g[i];
+  int* c = e.ctl;
+  if (!c[GC_DUE] || rg >= c[GC_STOPR]) return;
+  const int N = e.N, p = N / kNB, q = p / 2, ntiles = q * (q + 1) / 2;
+  const int rl = rg % (p - 1), sw = rg / (p - 1);
+  const bool odd = rg & 1;
+  const int b = blockIdx.x - off[i];
+  jac_round_body(b, odd ? e.A2 : e.A, odd ? e.A : e.A2, e.V, odd ? e.Q2 : e.Q, odd ? e.Q : e.Q2, N, rl,
+                 e.scale + (sw & 1), e.part, lds);
+  if (rl != p - 2 || b < q || b >= q + ntiles) return;
+  // the end of sweep sw: the last tile workgroup to finish decides
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last = (atomicAdd(reinterpret_cast<unsigned int*>(&c[GC_CNT]), 1u) == static_cast<unsigned int>(ntiles - 1));
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  offnorm_reduce(e.part, ntiles, red);
+  if (threadIdx.x != 0) return;
+  c[GC_CNT] = 0;
+  e.scale[(sw + 1) & 1] = red[2][0];
+  int more, nonfin, small;
+  offnorm_flags(red[0][0], red[1][0], more, nonfin, small);
+  const int done = sw + 1;
+  const bool cont = done < max_sweeps && (done < c[GC_MIN] || (more && !nonfin));
+  if (cont) return;
+  c[GC_STOPR] = rg + 1;
+  c[GC_LAST] = done;
+  int* st = e.status;
+  st[0] = nonfin ? 3 : (more ? 2 : 1);
+  st[1] = done;
+  st[2] = 0;
+  __hip_atomic_store(&hsweeps[i], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_fetch_add(hactive, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// the finishing steps of every descent that solved: eigenvalue ranks, column
+// signs, then the canonical B, D and B D (A and V as left by its last round)
+__global__ void __launch_bounds__(256) kg_rank(const GEigDesc* __restrict__ g, const int* __restrict__ off,
+                                               int count) {
+  __shared__ double dg[1024];
+  const int i = group_find(off, count, blockIdx.x);
+  const GEigDesc& e = g[i];
+  if (!e.ctl[GC_DUE]) return;
+  const double* A = (e.status[1] & 1) ? e.A2 : e.A;
+  eig_rank_body(blockIdx.x - off[i], A, e.N, e.n, e.perm, e.evals, e.status, e.sc, dg);
+}
+
+__global__ void __launch_bounds__(256) kg_colsign(const GEigDesc* __restrict__ g, const int* __restrict__ off,
+                                                  int count) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  const int i = group_find(off, count, blockIdx.x);
+  const GEigDesc& e = g[i];
+  if (!e.ctl[GC_DUE]) return;
+  colsign_body(blockIdx.x - off[i], e.V, e.N, e.n, e.sign, bv, bi);
+}
+
+__global__ void __launch_bounds__(256) kg_permute(const GEigDesc* __restrict__ g, const int* __restrict__ off,
+                                                  int count) {
+  const int i = group_find(off, count, blockIdx.x);
+  const GEigDesc& e = g[i];
+  if (!e.ctl[GC_DUE]) return;
+  const int nb = (e.n + 255) / 256, w = blockIdx.x - off[i];
+  if (e.bd64)
+    permute_body<double>(w % nb, w / nb, e.V, e.N, e.n, e.perm, e.evals, e.sign, e.B, e.ldb, e.D,
+                         static_cast<double*>(e.BD), e.ldbd);
+  else
+    permute_body<float>(w % nb, w / nb, e.V, e.N, e.n, e.perm, e.evals, e.sign, e.B, e.ldb, e.D,
+                        static_cast<float*>(e.BD), e.ldbd);
 }
 
 }  // namespace
@@ -882,7 +1085,7 @@ int eigen_begin(hipStream_t st, int n, const double* C, int ldc, const double* B
   CMX_HIP(launch_dgemm_ksplit(st, true, false, n, n, n, B, ldb, w.T, ldb, w.Acur, N, w.X2, N));   // A = B^T T
   kt_end(kt);
   k_offnorm_cols<<<n, 256, 0, st>>>(w.Acur, N, n, w.part);
-  k_offnorm_final<<<1, 256, 0, st>>>(w.part, n, w.dflags, w.scale);
+  k_offnorm_final<<<1, 256, 0, st>>>(w.part, n, w.dflags, w.scale, w.gctl);
   CMX_HIP(hipGetLastError());
   w.pending = true;
   return 0;
@@ -940,7 +1143,7 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
         std::swap(a0, a1);
         std::swap(q0, q1);
       }
-      k_offnorm_final<<<1, 256, 0, st>>>(w.part, ntiles, w.dflags, w.scale);
+      k_offnorm_final<<<1, 256, 0, st>>>(w.part, ntiles, w.dflags, w.scale, nullptr);
       return hipGetLastError();
     };
     // one closing correction from a0 into a1 (X1: Theta, then Q; X2: S, then
@@ -972,7 +1175,7 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
       if (e != hipSuccess) return e;
       k_sym_lower<<<ntl, 256, 0, st>>>(w.T, ldb, n, a1, N);
       k_offnorm_cols<<<n, 256, 0, st>>>(a1, N, n, w.part);
-      k_offnorm_final<<<1, 256, 0, st>>>(w.part, n, w.dflags, w.scale);
+      k_offnorm_final<<<1, 256, 0, st>>>(w.part, n, w.dflags, w.scale, nullptr);
       return hipGetLastError();
     };
     // replay step `slot` from a graph captured on first use (queue() queues
@@ -1055,6 +1258,101 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
   w.last_sweeps = w.sweeps - w.corrections;
   w.last_closed = w.corrections > 0;
   *done = true;
+  return 0;
+}
+
+
+// ---- host side of the grouped eigensolve
+
+void group_eig_release(GroupEig& ge) {
+  if (ge.dtab) (void)hipFree(ge.dtab);
+  if (ge.hflags) (void)hipHostFree(ge.hflags);
+  ge = GroupEig{};
+}
+
+int group_eig_build(hipStream_t st, GroupEig& ge, const std::vector<GEigDesc>& descs) {
+  const int count = static_cast<int>(descs.size());
+  if (count < 1 || count > kGroupMax) return fail(-1, "grouped eigensolve: 1 to 1024 descents");
+  // workgroups per descent of each kind: first, round, rank, colsign, permute
+  std::vector<int> off(kGroupKinds * (count + 1), 0);
+  for (int i = 0; i < count; ++i) {
+    const GEigDesc& e = descs[i];
+    const int N = e.N, p = N / kNB, q = p / 2, ntiles = q * (q + 1) / 2;
+    const int wgs[kGroupKinds] = {q, q + ntiles + (N / kS) * q, ceil_div(e.n, 256 / kRankTPI), e.n,
+                                  ceil_div(e.n, 256) * e.n};
+    for (int k = 0; k < kGroupKinds; ++k) off[k * (count + 1) + i + 1] = off[k * (count + 1) + i] + wgs[k];
+  }
+  int pmax = 2;
+  for (const auto& e : descs) pmax = std::max(pmax, e.N / kNB);
+  const size_t tab_bytes = sizeof(GEigDesc) * count, off_bytes = sizeof(int) * off.size();
+  if (ge.cap < count) {
+    group_eig_release(ge);
+    void* d = nullptr;
+    if (hipMalloc(&d, sizeof(GEigDesc) * kGroupMax + sizeof(int) * kGroupKinds * (kGroupMax + 1)) != hipSuccess)
+      return fail(-2, "grouped eigensolve: hipMalloc failed");
+    ge.dtab = d;
+    void* hf = nullptr;
+    if (hipHostMalloc(&hf, sizeof(int) * (kGroupMax + 1), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+      return fail(-2, "grouped eigensolve: hipHostMalloc failed");
+    ge.hflags = static_cast<int*>(hf);
+    void* dp = nullptr;
+    CMX_HIP(hipHostGetDevicePointer(&dp, hf, 0));
+    ge.dflags = static_cast<int*>(dp);
+    ge.cap = kGroupMax;
+  }
+  ge.count = count;
+  ge.pmax = pmax;
+  ge.off = off;
+  // the table and the offsets, on the group's stream; consumed before return
+  CMX_HIP(hipMemcpyAsync(ge.dtab, descs.data(), tab_bytes, hipMemcpyHostToDevice, st));
+  CMX_HIP(hipMemcpyAsync(static_cast<char*>(ge.dtab) + sizeof(GEigDesc) * kGroupMax, off.data(), off_bytes,
+                         hipMemcpyHostToDevice, st));
+  CMX_HIP(hipStreamSynchronize(st));
+  return 0;
+}
+
+int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int max_sweeps, int ahead,
+                    int* sweeps_out) {
+  const int count = ge.count;
+  const GEigDesc* tab = static_cast<const GEigDesc*>(ge.dtab);
+  const int* offs = reinterpret_cast<const int*>(static_cast<const char*>(ge.dtab) + sizeof(GEigDesc) * kGroupMax);
+  auto off_of = [&](int kind) { return offs + kind * (count + 1); };
+  auto wgs_of = [&](int kind) { return ge.off[kind * (count + 1) + count]; };
+  int* hactive = ge.dflags;            // [0]: descents still sweeping
+  int* hsweeps = ge.dflags + 1;        // [1 + i]: sweeps of descent i
+  ge.hflags[0] = 0;
+  kg_start<<<count, 64, 0, st>>>(tab, count, due, max_sweeps, hactive, hsweeps);
+  kg_first<<<wgs_of(0), 256, 0, st>>>(tab, off_of(0), count);
+  CMX_HIP(hipGetLastError());
+  // sweeps: every batch is one sweep of the largest descent (p_max - 1
+  // rounds; smaller descents complete at least one sweep in it).  `ahead`
+  // batches (the longest run any descent makes before its first convergence
+  // test) are queued before the host first waits; then one batch per wait
+  // until no descent sweeps any more.  Rounds of descents that have stopped
+  // return at once.
+  const int rounds = ge.pmax - 1;
+  int rg = 0;
+  auto queue_batch = [&]() -> int {
+    for (int r = 0; r < rounds; ++r, ++rg)
+      kg_round<<<wgs_of(1), 256, 0, st>>>(tab, off_of(1), count, rg, max_sweeps, hactive, hsweeps);
+    CMX_HIP(hipGetLastError());
+    return 0;
+  };
+  for (int b = 0; b < std::min(ahead, max_sweeps); ++b)
+    if (int rc = queue_batch()) return rc;
+  for (int batch = ahead;; ++batch) {
+    CMX_HIP(hipStreamSynchronize(st));
+    if (__atomic_load_n(&ge.hflags[0], __ATOMIC_ACQUIRE) <= 0) break;
+    if (batch >= max_sweeps + 1) return fail(-3, "grouped eigensolve: descents still sweeping past the sweep limit");
+    if (int rc = queue_batch()) return rc;
+  }
+  kg_rank<<<wgs_of(2), 256, 0, st>>>(tab, off_of(2), count);
+  kg_colsign<<<wgs_of(3), 256, 0, st>>>(tab, off_of(3), count);
+  kg_permute<<<wgs_of(4), 256, 0, st>>>(tab, off_of(4), count);
+  CMX_HIP(hipGetLastError());
+  for (int i = 0; i < count; ++i)
+    if (due_mask_bit(due, i)) sweeps_out[i] = __atomic_load_n(&ge.hflags[1 + i], __ATOMIC_ACQUIRE);
   return 0;
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 namespace cmx {
 
@@ -192,6 +193,7 @@ hipError_t launch_dgemm2(hipStream_t st, int M, int N, int K, const double* A0, 
 // eigensolver
 struct EigWork {
   int N = 0;      // padded size (multiple of 32)
+  int* gctl = nullptr;   // control block of a grouped solve (GC_WORDS ints, device memory)
   double* A = nullptr;   // N*N, ping-pong with A2
   double* A2 = nullptr;  // N*N
   double* V = nullptr;   // N*N
@@ -239,6 +241,50 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
                DevScalars* sc, int max_sweeps, KTimer* kt, bool use_graph, bool* done, bool ahead = false);
 // release the captured sweep graphs (the stream or the buffers change)
 void eigen_drop_graphs(EigWork& w);
+
+// ---- grouped eigensolve: the sweeps of many descents in one launch per
+// round, convergence decided per descent on the device (see eigen.hip)
+constexpr int kGroupMax = 1024;  // descents per group
+constexpr int kGroupKinds = 5;   // launch kinds with per-descent workgroups
+// words of a descent's control block (EigWork::gctl); k_offnorm_final of the
+// warm start writes GC_MORE and GC_NONFIN
+enum GroupCtl { GC_STOPR = 0, GC_MIN = 1, GC_LAST = 2, GC_CNT = 3, GC_MORE = 4, GC_NONFIN = 5, GC_DUE = 6,
+                GC_WORDS = 8 };
+struct GEigDesc {  // one descent of a grouped solve (device table entry)
+  double *A, *A2, *V, *Q, *Q2, *part, *scale;
+  int* status;
+  int* ctl;
+  double* B;
+  int ldb;
+  double* D;
+  void* BD;
+  int ldbd;
+  int bd64;  // B D stored in float64
+  double* evals;
+  int32_t* perm;
+  double* sign;
+  DevScalars* sc;
+  int n, N;
+};
+struct GroupDueMask {  // bit i: descent i solves in this call
+  uint32_t w[kGroupMax / 32];
+};
+inline bool due_mask_bit(const GroupDueMask& m, int i) { return (m.w[i >> 5] >> (i & 31)) & 1u; }
+struct GroupEig {
+  void* dtab = nullptr;   // device: GEigDesc[kGroupMax], then the workgroup offsets
+  int* hflags = nullptr;  // pinned, mapped: [0] descents still sweeping, [1 + i] sweeps of descent i
+  int* dflags = nullptr;  // device address of hflags
+  int cap = 0, count = 0, pmax = 2;
+  std::vector<int> off;   // host copy of the offsets (kGroupKinds x (count + 1))
+};
+// (re)load the table of descents (their buffers must stay allocated while in use)
+int group_eig_build(hipStream_t st, GroupEig& ge, const std::vector<GEigDesc>& descs);
+// Solve the due descents, whose warm starts (eigen_begin) are already queued
+// on `st` or ordered before it; ahead: sweeps to queue before the first wait.
+// sweeps_out[i] receives the sweeps of due descent i.
+int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int max_sweeps, int ahead,
+                    int* sweeps_out);
+void group_eig_release(GroupEig& ge);
 
 // stop tests; the bits go to sc->stop and, when hstop is not null, to that
 // word of pinned, mapped host memory (device address)

@@ -36,6 +36,8 @@ def test_batch_instance_equals_solo_run(P, precision):
         R, xs = synth.problem(n, 100 + k)
         with P.CMAES(n, lams[k], sig[k], seed=seeds[k], precision=precision, objective="rastrigin", R=R,
                      xstar=xs, eigen_interval=1) as es:
+            # the batch's grouped eigensolve closes with sweeps only
+            es.set_eigen_correction(False)
             for _ in range(gens):
                 es.generation()
             want = es.state()
