@@ -1335,6 +1335,21 @@ namespace {
 // concurrent descents, the K-Replicated tree): one grouped solve on a stream
 // of the set's own, which waits for every due descent's front and which the
 // descents' stop tests wait for.
+// the grouped front's tables (see GFront): the descents, the four float64
+// products per descent (re-orthogonalisation B^T B and B G, warm start C B
+// and B^T T), and the workgroup offsets of every step
+constexpr int kFrontMM = 4;  // products: RO_G, RO_T, CB, BT
+struct FrontTables {
+  void* dmem = nullptr;  // device copy: GFront[cap], GDgemm[kFrontMM][cap], offsets
+  int cap = 0, count = 0;
+  std::vector<GFront> tab;
+  std::vector<GDgemm> mm;   // kFrontMM x count
+  std::vector<int> off;     // GF_KINDS x (count + 1)
+  std::vector<int> offmm;   // kFrontMM x 2 x (count + 1): products, adds
+  std::vector<uint64_t> keys;
+  int cfg[G32_NUM_SITES] = {0, 0, 0};
+};
+
 struct LockstepGroup {
   hipStream_t st = nullptr;
   hipEvent_t done = nullptr;
@@ -1343,6 +1358,8 @@ struct LockstepGroup {
   std::vector<uint64_t> epochs;  // their buffer epochs then
   std::vector<hipEvent_t> ev;    // per member: the end of its front
   std::vector<int> sweeps;
+  FrontTables ft;
+  std::vector<cmaes*> fmembers;  // the descents the front tables were built for
 };
 
 int group_init(LockstepGroup& g) {
@@ -1354,6 +1371,7 @@ int group_init(LockstepGroup& g) {
 void group_destroy(LockstepGroup& g) {
   if (g.st) (void)hipStreamSynchronize(g.st);
   group_eig_release(g.ge);
+  if (g.ft.dmem) (void)hipFree(g.ft.dmem);
   for (auto e : g.ev)
     if (e) (void)hipEventDestroy(e);
   g.ev.clear();
@@ -1405,6 +1423,220 @@ int restart_same_lambda(cmaes* h) {
   return init_descent(h, false);
 }
 
+// whether a set of descents can run the grouped front: mixed precision with
+// float32 sampling, a rotated fused objective, the same GEMM tiles, no timers
+bool front_groupable(const std::vector<cmaes*>& hs) {
+  for (cmaes* h : hs) {
+    if (h->fp64 || h->opt.precision != CMAES_MIXED || !h->have_R || h->obj_kind == CMAES_OBJ_NONE || h->timing ||
+        h->kt.on)
+      return false;
+    for (int s = 0; s < G32_NUM_SITES; ++s)
+      if (h->gcfg[s] != hs[0]->gcfg[s]) return false;
+  }
+  return !hs.empty();
+}
+
+uint64_t front_member_key(const cmaes* h) {
+  uint64_t k = h->epoch;
+  k = k * 0x100000001B3ull + static_cast<uint64_t>(h->lam);
+  k = k * 0x100000001B3ull + static_cast<uint64_t>(h->restart);
+  return k;
+}
+
+GDgemm dgemm_desc(const double* A, int lda, const double* B, int ldb, double* C, int ldc, double* W, int ldw, int n) {
+  // launch_dgemm_ksplit's plan: two half-k products while the product has at
+  // most one 64 x 64 tile per CU
+  const int tiles = ceil_div(n, 64) * ceil_div(n, 64);
+  const int K0 = round_up(ceil_div(n, 2), 16);
+  GDgemm d{A, lda, B, ldb, C, ldc, W, ldw, n, K0, (K0 < n && tiles <= 256) ? 1 : 0};
+  return d;
+}
+
+int build_front_tables(LockstepGroup& g, const std::vector<cmaes*>& hs) {
+  FrontTables& ft = g.ft;
+  const int count = static_cast<int>(hs.size());
+  bool same = g.fmembers == hs && static_cast<int>(ft.keys.size()) == count;
+  for (int i = 0; same && i < count; ++i) same = ft.keys[i] == front_member_key(hs[i]);
+  for (int s = 0; same && s < G32_NUM_SITES; ++s) same = ft.cfg[s] == hs[0]->gcfg[s];
+  if (same) return 0;
+  ft.tab.assign(count, GFront{});
+  ft.mm.assign(static_cast<size_t>(kFrontMM) * count, GDgemm{});
+  ft.off.assign(static_cast<size_t>(GF_KINDS) * (count + 1), 0);
+  ft.offmm.assign(static_cast<size_t>(kFrontMM) * 2 * (count + 1), 0);
+  for (int s = 0; s < G32_NUM_SITES; ++s) ft.cfg[s] = hs[0]->gcfg[s];
+  for (int i = 0; i < count; ++i) {
+    cmaes* h = hs[i];
+    const int n = h->n, lam = h->lam, mu = h->hp.kp.mu, ldn = h->ldn, N = h->ew.N;
+    GFront& e = ft.tab[i];
+    e.n = n;
+    e.lam = lam;
+    e.mu = mu;
+    e.ldn = ldn;
+    e.N = N;
+    e.k0 = static_cast<uint32_t>(h->seed);
+    e.k1 = static_cast<uint32_t>(h->seed >> 32);
+    e.restart = static_cast<uint32_t>(h->restart);
+    e.sc = h->sc;
+    e.BD = static_cast<const float*>(h->BD);
+    e.Z = static_cast<float*>(h->Z);
+    e.Y = static_cast<float*>(h->Y);
+    e.Rd = h->Rd;
+    e.m = h->m;
+    e.xstar = h->have_xstar ? h->xstar : nullptr;
+    e.u = h->u;
+    e.part_bz = h->part_bz;
+    e.d = h->d;
+    e.kind = h->obj_kind;
+    e.fit_tiles = g32_row_tiles(ft.cfg[G32_FITNESS], n);
+    e.Rt = static_cast<const float*>(h->Rt);
+    e.coef = static_cast<const float*>(h->coef);
+    e.partial = static_cast<float*>(h->partial);
+    e.f = h->f;
+    e.rank_work = h->rank_work;
+    e.order = h->order;
+    e.rank_span = rank_span_of(lam);
+    e.rank_splits = ceil_div(lam, e.rank_span);
+    e.x_best = h->x_best;
+    e.hist = h->hist;
+    e.hist_len = h->sp.hist_len;
+    e.w = h->w;
+    e.sqrtw = h->sqrtw;
+    e.Ysel = static_cast<float*>(h->Ysel);
+    e.part_yw = h->part_yw;
+    e.part_zw = h->part_zw;
+    e.yw = h->yw;
+    e.zw = h->zw;
+    e.B = h->B;
+    e.D = h->D;
+    e.ps = h->ps;
+    e.pc = h->pc;
+    e.kp = h->hp.kp;
+    e.syrk_work = static_cast<float*>(h->syrk_work);
+    e.C = h->C;
+    {
+      size_t we;
+      syrk32_plan(ft.cfg[G32_SYRK], n, mu, &e.syrk_ntl, &e.syrk_splits, &e.syrk_kspan, &we);
+    }
+    e.V = h->ew.V;
+    e.A = h->ew.A;
+    e.A2 = h->ew.A2;
+    e.T = h->ew.T;
+    e.epart = h->ew.part;
+    e.scale = h->ew.scale;
+    e.dflags = h->ew.dflags;
+    e.gctl = h->ew.gctl;
+    e.sp = h->sp;
+    // the products of the re-orthogonalisation and of the warm start
+    ft.mm[0 * count + i] = dgemm_desc(h->B, ldn, h->B, ldn, h->ew.A2, N, h->ew.X2, N, n);      // G = B^T B
+    ft.mm[1 * count + i] = dgemm_desc(h->B, ldn, h->ew.A2, N, h->ew.T, ldn, h->ew.X2, N, n);   // T = B G
+    ft.mm[2 * count + i] = dgemm_desc(h->C, ldn, h->B, ldn, h->ew.T, ldn, h->ew.X2, N, n);     // T = C B
+    ft.mm[3 * count + i] = dgemm_desc(h->B, ldn, h->ew.T, ldn, h->ew.A, N, h->ew.X2, N, n);    // A = B^T T
+    // workgroups per descent of every step
+    int wgs[GF_KINDS] = {};
+    const int nb256 = ceil_div(n, 256);
+    wgs[GF_NORMALS] = static_cast<int>((static_cast<int64_t>((n + 3) / 4) * lam + 255) / 256);
+    wgs[GF_SAMPLE] = g32_tiles(ft.cfg[G32_SAMPLE], n, lam);
+    wgs[GF_SUB] = nb256;
+    wgs[GF_RMATVEC] = nb256 * ceil_div(n, 64);
+    wgs[GF_RVEC] = nb256;
+    wgs[GF_FITNESS] = g32_tiles(ft.cfg[G32_FITNESS], n, lam);
+    wgs[GF_FREDUCE] = ceil_div(lam, 256);
+    wgs[GF_RANK] = ceil_div(lam, 1024) * e.rank_splits;
+    wgs[GF_SCATTER] = ceil_div(lam, 256);
+    wgs[GF_BEST] = 1;
+    wgs[GF_RECOMB] = nb256 * ceil_div(mu, 64);
+    wgs[GF_REDYZ] = nb256;
+    wgs[GF_BMATVEC] = nb256 * ceil_div(n, 64);
+    wgs[GF_VECUPD] = 1;
+    syrk32_group_wgs(ft.cfg[G32_SYRK], n, mu, &wgs[GF_SYRK], &wgs[GF_SYRKEPI]);
+    wgs[GF_INIT] = static_cast<int>((static_cast<int64_t>(N) * N + 255) / 256);
+    wgs[GF_OFFCOLS] = n;
+    wgs[GF_OFFFIN] = 1;
+    wgs[GF_POLAR] = static_cast<int>((static_cast<int64_t>(n) * n + 255) / 256);
+    wgs[GF_STOP] = 1;
+    for (int k = 0; k < GF_KINDS; ++k) ft.off[k * (count + 1) + i + 1] = ft.off[k * (count + 1) + i] + wgs[k];
+    for (int q = 0; q < kFrontMM; ++q) {
+      const GDgemm& d = ft.mm[q * count + i];
+      const int tiles = ceil_div(n, 64) * ceil_div(n, 64);
+      const int prod = d.split ? 2 * tiles : tiles, add = d.split ? nb256 * n : 0;
+      int* o = ft.offmm.data() + static_cast<size_t>(q) * 2 * (count + 1);
+      o[i + 1] = o[i] + prod;
+      o[(count + 1) + i + 1] = o[(count + 1) + i] + add;
+    }
+  }
+  if (ft.cap < count) {
+    if (ft.dmem) (void)hipFree(ft.dmem);
+    ft.dmem = nullptr;
+    const size_t bytes = sizeof(GFront) * kGroupMax + sizeof(GDgemm) * kFrontMM * kGroupMax +
+                         sizeof(int) * (GF_KINDS + 2 * kFrontMM) * (kGroupMax + 1);
+    if (hipMalloc(&ft.dmem, bytes) != hipSuccess) return fail(CMAES_ENOMEM, "grouped front: hipMalloc failed");
+    ft.cap = kGroupMax;
+  }
+  char* base = static_cast<char*>(ft.dmem);
+  CMX_HIP(hipMemcpyAsync(base, ft.tab.data(), sizeof(GFront) * count, hipMemcpyHostToDevice, g.st));
+  for (int q = 0; q < kFrontMM; ++q)
+    CMX_HIP(hipMemcpyAsync(base + sizeof(GFront) * kGroupMax + sizeof(GDgemm) * q * kGroupMax,
+                           ft.mm.data() + static_cast<size_t>(q) * count, sizeof(GDgemm) * count,
+                           hipMemcpyHostToDevice, g.st));
+  char* offb = base + sizeof(GFront) * kGroupMax + sizeof(GDgemm) * kFrontMM * kGroupMax;
+  CMX_HIP(hipMemcpyAsync(offb, ft.off.data(), sizeof(int) * ft.off.size(), hipMemcpyHostToDevice, g.st));
+  CMX_HIP(hipMemcpyAsync(offb + sizeof(int) * GF_KINDS * (count + 1), ft.offmm.data(),
+                         sizeof(int) * ft.offmm.size(), hipMemcpyHostToDevice, g.st));
+  CMX_HIP(hipStreamSynchronize(g.st));  // the host vectors are consumed
+  ft.count = count;
+  ft.keys.clear();
+  for (cmaes* h : hs) ft.keys.push_back(front_member_key(h));
+  g.fmembers = hs;
+  return 0;
+}
+
+// the fixed part of one generation of every descent, one launch per step for
+// all of them, on the group's stream (the per-descent equivalent is front())
+int grouped_front(LockstepGroup& g, const std::vector<cmaes*>& hs, const GroupDueMask& due,
+                  const GroupDueMask& reorth, bool any_due, bool any_reorth) {
+  FrontTables& ft = g.ft;
+  const int count = ft.count;
+  const char* base = static_cast<const char*>(ft.dmem);
+  const GFront* tab = reinterpret_cast<const GFront*>(base);
+  const GDgemm* mm = reinterpret_cast<const GDgemm*>(base + sizeof(GFront) * kGroupMax);
+  const int* offd = reinterpret_cast<const int*>(base + sizeof(GFront) * kGroupMax +
+                                                 sizeof(GDgemm) * kFrontMM * kGroupMax);
+  auto off = [&](int k) { return offd + k * (count + 1); };
+  auto wgs = [&](int k) { return ft.off[k * (count + 1) + count]; };
+  const int* offmm = offd + GF_KINDS * (count + 1);
+  auto moff = [&](int q, int a) { return offmm + (q * 2 + a) * (count + 1); };
+  auto mwgs = [&](int q, int a) { return ft.offmm[(q * 2 + a) * (count + 1) + count]; };
+  hipStream_t st = g.st;
+  (void)hs;
+  CMX_HIP(launch_group_normals(st, tab, off(GF_NORMALS), count, wgs(GF_NORMALS)));
+  CMX_HIP(launch_group_g32(st, ft.cfg[G32_SAMPLE], G32_SAMPLE, tab, off(GF_SAMPLE), count, wgs(GF_SAMPLE)));
+  for (int k : {GF_SUB, GF_RMATVEC, GF_RVEC})
+    CMX_HIP(launch_group_update(st, k, tab, off(k), count, wgs(k), nullptr));
+  CMX_HIP(launch_group_g32(st, ft.cfg[G32_FITNESS], G32_FITNESS, tab, off(GF_FITNESS), count, wgs(GF_FITNESS)));
+  CMX_HIP(launch_group_fitness_reduce(st, tab, off(GF_FREDUCE), count, wgs(GF_FREDUCE)));
+  for (int k : {GF_RANK, GF_SCATTER, GF_BEST, GF_RECOMB, GF_REDYZ, GF_BMATVEC, GF_VECUPD})
+    CMX_HIP(launch_group_update(st, k, tab, off(k), count, wgs(k), nullptr));
+  CMX_HIP(launch_group_syrk(st, ft.cfg[G32_SYRK], tab, off(GF_SYRK), wgs(GF_SYRK), off(GF_SYRKEPI), wgs(GF_SYRKEPI),
+                            count));
+  if (any_reorth) {
+    CMX_HIP(launch_group_dgemm(st, true, mm + 0 * kGroupMax, moff(0, 0), mwgs(0, 0), moff(0, 1), mwgs(0, 1), count,
+                               reorth));
+    CMX_HIP(launch_group_dgemm(st, false, mm + 1 * kGroupMax, moff(1, 0), mwgs(1, 0), moff(1, 1), mwgs(1, 1), count,
+                               reorth));
+    CMX_HIP(launch_group_update(st, GF_POLAR, tab, off(GF_POLAR), count, wgs(GF_POLAR), &reorth));
+  }
+  if (any_due) {
+    CMX_HIP(launch_group_eigen_begin(st, GF_INIT, tab, off(GF_INIT), count, wgs(GF_INIT), due));
+    CMX_HIP(launch_group_dgemm(st, false, mm + 2 * kGroupMax, moff(2, 0), mwgs(2, 0), moff(2, 1), mwgs(2, 1), count,
+                               due));
+    CMX_HIP(launch_group_dgemm(st, true, mm + 3 * kGroupMax, moff(3, 0), mwgs(3, 0), moff(3, 1), mwgs(3, 1), count,
+                               due));
+    CMX_HIP(launch_group_eigen_begin(st, GF_OFFCOLS, tab, off(GF_OFFCOLS), count, wgs(GF_OFFCOLS), due));
+    CMX_HIP(launch_group_eigen_begin(st, GF_OFFFIN, tab, off(GF_OFFFIN), count, wgs(GF_OFFFIN), due));
+  }
+  return 0;
+}
+
 // one generation of every handle: all fronts queued first (each on its own
 // stream, the warm start of a due eigensolve included), then one grouped
 // eigensolve of every due handle (one launch per round for all of them,
@@ -1414,11 +1646,36 @@ int lockstep_generation(LockstepGroup& g, const std::vector<cmaes*>& hs) {
     if (h->obj_kind == CMAES_OBJ_NONE) return fail(CMAES_ESTATE, "every instance needs a fused objective");
   const int count = static_cast<int>(hs.size());
   if (count > kGroupMax) return fail(CMAES_EINVAL, "too many descents in one lockstep group");
-  for (cmaes* h : hs) {
+  for (cmaes* h : hs)
     if (int rc = ensure_ready(h)) return rc;
-    if (int rc = front(h)) return rc;
+  const bool grouped = front_groupable(hs);
+  GroupDueMask due{}, reorth{};
+  bool any_reorth = false;
+  if (grouped) {
+    if (int rc = build_front_tables(g, hs)) return rc;
+    // every descent's earlier work (a restart, a state upload) is ordered
+    // before the grouped launches
+    while (static_cast<int>(g.ev.size()) < count) {
+      hipEvent_t e = nullptr;
+      CMX_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      g.ev.push_back(e);
+    }
+    for (int i = 0; i < count; ++i) {
+      CMX_HIP(hipEventRecord(g.ev[i], hs[i]->st));
+      CMX_HIP(hipStreamWaitEvent(g.st, g.ev[i], 0));
+    }
+    for (int i = 0; i < count; ++i) {
+      set_due(hs[i]);
+      if (hs[i]->eig_due) due.w[i >> 5] |= 1u << (i & 31);
+      if (hs[i]->reorth_due) {
+        reorth.w[i >> 5] |= 1u << (i & 31);
+        any_reorth = true;
+      }
+    }
+  } else {
+    for (cmaes* h : hs)
+      if (int rc = front(h)) return rc;
   }
-  GroupDueMask due{};
   int ahead = 0;
   bool any = false;
   for (int i = 0; i < count; ++i)
@@ -1429,6 +1686,13 @@ int lockstep_generation(LockstepGroup& g, const std::vector<cmaes*>& hs) {
       const int last = hs[i]->ew.last_sweeps;
       ahead = std::max(ahead, last >= 2 ? last - 1 : 0);
     }
+  if (grouped) {
+    if (int rc = grouped_front(g, hs, due, reorth, any, any_reorth)) return rc;
+    for (cmaes* h : hs) {
+      advance_counters(h);
+      if (h->eig_due) eigen_begin_host(h->ew);
+    }
+  }
   if (any) {
     bool same = g.members == hs && static_cast<int>(g.epochs.size()) == count;
     for (int i = 0; same && i < count; ++i) same = g.epochs[i] == hs[i]->epoch;
@@ -1445,24 +1709,41 @@ int lockstep_generation(LockstepGroup& g, const std::vector<cmaes*>& hs) {
       CMX_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       g.ev.push_back(e);
     }
-    for (int i = 0; i < count; ++i)
-      if (hs[i]->eig_due) {
-        CMX_HIP(hipEventRecord(g.ev[i], hs[i]->st));
-        CMX_HIP(hipStreamWaitEvent(g.st, g.ev[i], 0));
-      }
+    if (!grouped)
+      for (int i = 0; i < count; ++i)
+        if (hs[i]->eig_due) {
+          CMX_HIP(hipEventRecord(g.ev[i], hs[i]->st));
+          CMX_HIP(hipStreamWaitEvent(g.st, g.ev[i], 0));
+        }
     g.sweeps.assign(count, 0);
     if (int rc = group_eig_solve(g.st, g.ge, due, 40, ahead, g.sweeps.data())) return rc;
-    CMX_HIP(hipEventRecord(g.done, g.st));
+    if (!grouped) CMX_HIP(hipEventRecord(g.done, g.st));
     for (int i = 0; i < count; ++i)
       if (hs[i]->eig_due) {
         cmaes* h = hs[i];
-        CMX_HIP(hipStreamWaitEvent(h->st, g.done, 0));
+        if (!grouped) CMX_HIP(hipStreamWaitEvent(h->st, g.done, 0));
         h->ew.sweeps = g.sweeps[i];
         h->ew.corrections = 0;
         h->ew.last_sweeps = g.sweeps[i];
         h->ew.last_closed = false;
         h->ew.pending = false;
       }
+  }
+  if (grouped) {
+    // the stop tests of every descent, then each descent's stream waits for
+    // the group (its state is read there)
+    const FrontTables& ft = g.ft;
+    const char* base = static_cast<const char*>(ft.dmem);
+    const int* offd = reinterpret_cast<const int*>(base + sizeof(GFront) * kGroupMax +
+                                                   sizeof(GDgemm) * kFrontMM * kGroupMax);
+    CMX_HIP(launch_group_update(g.st, GF_STOP, reinterpret_cast<const GFront*>(base), offd + GF_STOP * (count + 1),
+                                count, ft.off[GF_STOP * (count + 1) + count], nullptr));
+    CMX_HIP(hipEventRecord(g.done, g.st));
+    for (cmaes* h : hs) {
+      CMX_HIP(hipStreamWaitEvent(h->st, g.done, 0));
+      h->stop_pending = false;
+    }
+    return 0;
   }
   for (cmaes* h : hs)
     if (int rc = phase_update_post(h)) return rc;

@@ -553,10 +553,10 @@ __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Ac
 }
 
 // off-diagonal / total squared norms and max |diagonal| of A, per column
-__global__ void __launch_bounds__(256) k_offnorm_cols(const double* __restrict__ A, int N, int n,
-                                                      double* __restrict__ part) {
+__device__ __forceinline__ void offnorm_cols_body(int c, const double* __restrict__ A, int N, int n,
+                                                  double* __restrict__ part) {
   __shared__ double red[3][256];
-  const int c = blockIdx.x, t = threadIdx.x;
+  const int t = threadIdx.x;
   double off = 0.0, tot = 0.0;
   for (int rr = t; rr < n; rr += 256) {
     const double v = A[static_cast<int64_t>(c) * N + rr];
@@ -578,6 +578,11 @@ __global__ void __launch_bounds__(256) k_offnorm_cols(const double* __restrict__
     part[3 * c + 1] = red[1][0];
     part[3 * c + 2] = fabs(A[static_cast<int64_t>(c) * N + c]);
   }
+}
+
+__global__ void __launch_bounds__(256) k_offnorm_cols(const double* __restrict__ A, int N, int n,
+                                                      double* __restrict__ part) {
+  offnorm_cols_body(blockIdx.x, A, N, n, part);
 }
 
 // reduce count (off, tot, dmax) triples in a fixed order: flags[0] = 1 if more
@@ -620,9 +625,9 @@ __device__ __forceinline__ void offnorm_flags(double off, double tot, int& more,
 
 // dctl (device memory, may be null): words 4 and 5 of a grouped solve's
 // control block receive the first two flags as well
-__global__ void __launch_bounds__(256) k_offnorm_final(const double* __restrict__ part, int count,
-                                                       int* __restrict__ flags, double* __restrict__ scale,
-                                                       int* __restrict__ dctl) {
+__device__ __forceinline__ void offnorm_final_body(const double* __restrict__ part, int count,
+                                                   int* __restrict__ flags, double* __restrict__ scale,
+                                                   int* __restrict__ dctl) {
   __shared__ double red[3][256];
   offnorm_reduce(part, count, red);
   if (threadIdx.x == 0) {
@@ -639,19 +644,48 @@ __global__ void __launch_bounds__(256) k_offnorm_final(const double* __restrict_
   }
 }
 
+__global__ void __launch_bounds__(256) k_offnorm_final(const double* __restrict__ part, int count,
+                                                       int* __restrict__ flags, double* __restrict__ scale,
+                                                       int* __restrict__ dctl) {
+  offnorm_final_body(part, count, flags, scale, dctl);
+}
+
 // Set-up of a solve, one pass over N x N: both A buffers cleared (their
 // padded rows and columns must be zero; a solve that met non-finite values
 // can leave NaN there) and V = [B_old 0; 0 I]: the rotations are accumulated
 // straight into the previous eigenvectors, so the new ones need no final
 // product B_old V
-__global__ void k_init_solve(double* __restrict__ V, double* __restrict__ A0, double* __restrict__ A1, int N, int n,
-                             const double* __restrict__ B, int ldb) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void init_solve_body(int bx, double* __restrict__ V, double* __restrict__ A0,
+                                                double* __restrict__ A1, int N, int n, const double* __restrict__ B,
+                                                int ldb) {
+  const int64_t i = static_cast<int64_t>(bx) * blockDim.x + threadIdx.x;
   if (i >= static_cast<int64_t>(N) * N) return;
   const int r = static_cast<int>(i % N), c = static_cast<int>(i / N);
   V[i] = (r < n && c < n) ? B[static_cast<int64_t>(c) * ldb + r] : (r == c ? 1.0 : 0.0);
   A0[i] = 0.0;
   A1[i] = 0.0;
+}
+
+__global__ void k_init_solve(double* __restrict__ V, double* __restrict__ A0, double* __restrict__ A1, int N, int n,
+                             const double* __restrict__ B, int ldb) {
+  init_solve_body(blockIdx.x, V, A0, A1, N, n, B, ldb);
+}
+
+// the set-up steps of the due descents of a grouped front (their warm start:
+// kind GF_INIT clears A, A2 and sets V = B_old; the products are grouped
+// dgemms; GF_OFFCOLS / GF_OFFFIN test the warm start as eigen_begin does)
+__global__ void __launch_bounds__(256) kg_eigen_begin(int kind, const GFront* __restrict__ g,
+                                                      const int* __restrict__ off, int count, GroupDueMask mask) {
+  const int i = group_find(off, count, blockIdx.x);
+  if (!due_mask_bit(mask, i)) return;
+  const GFront& e = g[i];
+  const int w = blockIdx.x - off[i];
+  if (kind == GF_INIT)
+    init_solve_body(w, e.V, e.A, e.A2, e.N, e.n, e.B, e.ldn);
+  else if (kind == GF_OFFCOLS)
+    offnorm_cols_body(w, e.A, e.N, e.n, e.epart);
+  else
+    offnorm_final_body(e.epart, e.n, e.dflags, e.scale, e.gctl);
 }
 
 // ---- closing correction.  Once the sweeps have made A nearly diagonal,
@@ -908,18 +942,6 @@ __global__ void __launch_bounds__(256) k_permute(const double* __restrict__ Bn, 
 // counter in its control block), so the host only waits for the whole group.
 // The arithmetic of every step is that of the single-descent solve (the same
 // bodies, the same reduction order), without the closing correction.
-
-__device__ __forceinline__ int group_find(const int* __restrict__ off, int count, int w) {
-  int lo = 0, hi = count;  // off[lo] <= w < off[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (off[mid] <= w)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
 
 __device__ __forceinline__ bool due_bit(const GroupDueMask& m, int i) { return (m.w[i >> 5] >> (i & 31)) & 1u; }
 
@@ -1261,6 +1283,12 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
   return 0;
 }
 
+
+hipError_t launch_group_eigen_begin(hipStream_t st, int kind, const GFront* g, const int* off, int count, int wgs,
+                                    const GroupDueMask& mask) {
+  if (wgs > 0) kg_eigen_begin<<<wgs, 256, 0, st>>>(kind, g, off, count, mask);
+  return hipGetLastError();
+}
 
 // ---- host side of the grouped eigensolve
 

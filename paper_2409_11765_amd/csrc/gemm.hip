@@ -388,6 +388,74 @@ __global__ void k_add_block(double* __restrict__ Cm, int ldc, const double* __re
   if (r < M) Cm[static_cast<int64_t>(c) * ldc + r] += W[static_cast<int64_t>(c) * ldw + r];
 }
 
+// the n x n product of every due descent of a group, tile for tile as
+// launch_dgemm_ksplit computes it: with split, workgroups [0, tiles) the
+// first K0 of k into C, [tiles, 2 tiles) the rest into W (k_dgemm_kg2);
+// without, k_dgemm_kg over all of k
+template <bool TA>
+__global__ void __launch_bounds__(512) kg_dgemm(const GDgemm* __restrict__ g, const int* __restrict__ off, int count,
+                                                GroupDueMask mask) {
+  using C = Cfg<double>;
+  __shared__ double As[C::BK * (C::BM + C::PAD)];
+  __shared__ double Bs[C::BK * (C::BN + C::PAD)];
+  __shared__ double fold[4 * 4 * C::NACC * 64];
+  const int i = group_find(off, count, blockIdx.x);
+  if (!due_mask_bit(mask, i)) return;
+  const GDgemm& e = g[i];
+  const int n = e.n, tiles_m = (n + C::BM - 1) / C::BM, tiles = tiles_m * tiles_m;
+  const int w = blockIdx.x - off[i];
+  const int t = w % tiles;
+  const bool second = e.split && w >= tiles;
+  const double* A = e.A;
+  const double* B = e.B;
+  int K = n;
+  double* out = e.C;
+  int ldo = e.ldc;
+  if (e.split) {
+    if (second) {
+      A = TA ? e.A + e.K0 : e.A + static_cast<int64_t>(e.K0) * e.lda;
+      B = e.B + e.K0;
+      K = n - e.K0;
+      out = e.W;
+      ldo = e.ldw;
+    } else {
+      K = e.K0;
+    }
+  }
+  const int m0 = (t % tiles_m) * C::BM, n0 = (t / tiles_m) * C::BN;
+  typename C::acc_t acc[2][2];
+  gemm_mainloop<double, TA, false, 512>(n, n, K, A, e.lda, B, e.ldb, m0, n0, As, Bs, acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wq = wave & 3;
+  if (wave >= 4) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < C::NACC; ++r) fold[(((r * 4 + wq) * 2 + a) * 2 + b) * 64 + lane] = acc[a][b][r];
+  }
+  __syncthreads();
+  if (wave >= 4) return;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < C::NACC; ++r) acc[a][b][r] += fold[(((r * 4 + wq) * 2 + a) * 2 + b) * 64 + lane];
+  EpiStore<double>{out, ldo}(acc, n, n, m0, n0, As);
+}
+
+// C += W for the split products of a group (ceil(n / 256) x n workgroups each)
+__global__ void __launch_bounds__(256) kg_add(const GDgemm* __restrict__ g, const int* __restrict__ off, int count,
+                                              GroupDueMask mask) {
+  const int i = group_find(off, count, blockIdx.x);
+  if (!due_mask_bit(mask, i)) return;
+  const GDgemm& e = g[i];
+  const int nb = (e.n + 255) / 256, w = blockIdx.x - off[i];
+  const int r = (w % nb) * 256 + threadIdx.x, c = w / nb;
+  if (r < e.n) e.C[static_cast<int64_t>(c) * e.ldc + r] += e.W[static_cast<int64_t>(c) * e.ldw + r];
+}
+
 __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
   tm = static_cast<int>((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
   while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
@@ -491,14 +559,27 @@ __global__ void __launch_bounds__(256) k_fitness_direct(int n, int lam, const T*
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_fitness_reduce(int lam, const T* __restrict__ partial, int ldp,
-                                                        int tiles, double add, double* __restrict__ f) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fitness_reduce_body(int bx, int lam, const T* __restrict__ partial, int ldp,
+                                                    int tiles, double add, double* __restrict__ f) {
+  const int k = bx * blockDim.x + threadIdx.x;
   if (k >= lam) return;
   double s = 0.0;
 #pragma unroll 16
   for (int t = 0; t < tiles; ++t) s += static_cast<double>(partial[static_cast<int64_t>(t) * ldp + k]);
   f[k] = s + add;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fitness_reduce(int lam, const T* __restrict__ partial, int ldp,
+                                                        int tiles, double add, double* __restrict__ f) {
+  fitness_reduce_body<T>(blockIdx.x, lam, partial, ldp, tiles, add, f);
+}
+
+__global__ void __launch_bounds__(256) kg_fitness_reduce(const GFront* __restrict__ g, const int* __restrict__ off,
+                                                         int count) {
+  const int i = group_find(off, count, blockIdx.x);
+  const GFront& e = g[i];
+  fitness_reduce_body<float>(blockIdx.x - off[i], e.lam, e.partial, e.lam, e.fit_tiles, 0.0, e.f);
 }
 
 // ---------------------------------------------------------- bf16 x 3 sampling
@@ -713,6 +794,23 @@ hipError_t launch_dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, c
   else if (ta && !tb) k_dgemm_kg<true, false><<<tiles, 512, 0, st>>>(M, N, K, A, lda, B, ldb, e);
   else if (!ta && tb) k_dgemm_kg<false, true><<<tiles, 512, 0, st>>>(M, N, K, A, lda, B, ldb, e);
   else k_dgemm_kg<true, true><<<tiles, 512, 0, st>>>(M, N, K, A, lda, B, ldb, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_fitness_reduce(hipStream_t st, const GFront* g, const int* off, int count, int wgs) {
+  if (wgs > 0) kg_fitness_reduce<<<wgs, 256, 0, st>>>(g, off, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_dgemm(hipStream_t st, bool ta, const GDgemm* gd, const int* off_mm, int wgs_mm,
+                              const int* off_add, int wgs_add, int count, const GroupDueMask& mask) {
+  if (wgs_mm > 0) {
+    if (ta)
+      kg_dgemm<true><<<wgs_mm, 512, 0, st>>>(gd, off_mm, count, mask);
+    else
+      kg_dgemm<false><<<wgs_mm, 512, 0, st>>>(gd, off_mm, count, mask);
+  }
+  if (wgs_add > 0) kg_add<<<wgs_add, 256, 0, st>>>(gd, off_add, count, mask);
   return hipGetLastError();
 }
 

@@ -247,18 +247,45 @@ struct Epi32Fitness {
 };
 
 template <int BM, int BN, int BK, bool TB, class Epi>
-__global__ void __launch_bounds__(256) k_g32(int M, int N, int K, const float* __restrict__ A, int lda,
-                                             const float* __restrict__ B, int ldb, Epi epi) {
+__device__ __forceinline__ void g32_body(int bid, int M, int N, int K, const float* __restrict__ A, int lda,
+                                         const float* __restrict__ B, int ldb, const Epi& epi, float* As,
+                                         float* Bs) {
   using G = G32<BM, BN, BK, TB>;
-  __shared__ float As[2 * BK * G::LDA];
-  __shared__ float Bs[2 * BK * G::LDB];
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
-  const int tile = xcd_swizzle(blockIdx.x, tiles_m * tiles_n);
+  const int tile = xcd_swizzle(bid, tiles_m * tiles_n);
   const int m0 = (tile % tiles_m) * BM, n0 = (tile / tiles_m) * BN;
   floatx16 acc[G::TMB][G::TNB];
   G g;
   g.mainloop(M, N, K, A, lda, B, ldb, m0, n0, As, Bs, acc);
   epi(acc, M, N, m0, n0, As);
+}
+
+template <int BM, int BN, int BK, bool TB, class Epi>
+__global__ void __launch_bounds__(256) k_g32(int M, int N, int K, const float* __restrict__ A, int lda,
+                                             const float* __restrict__ B, int ldb, Epi epi) {
+  using G = G32<BM, BN, BK, TB>;
+  __shared__ float As[2 * BK * G::LDA];
+  __shared__ float Bs[2 * BK * G::LDB];
+  g32_body<BM, BN, BK, TB, Epi>(blockIdx.x, M, N, K, A, lda, B, ldb, epi, As, Bs);
+}
+
+// the sampling product (SITE = G32_SAMPLE: Y = (B D) Z) or the fitness product
+// with its objective epilogue (G32_FITNESS: R Y) of every descent of a group
+template <int BM, int BN, int BK, int SITE>
+__global__ void __launch_bounds__(256) kg_g32(const GFront* __restrict__ g, const int* __restrict__ off, int count) {
+  using G = G32<BM, BN, BK, false>;
+  __shared__ float As[2 * BK * G::LDA];
+  __shared__ float Bs[2 * BK * G::LDB];
+  const int i = group_find(off, count, blockIdx.x);
+  const GFront& e = g[i];
+  const int bid = blockIdx.x - off[i];
+  if constexpr (SITE == G32_SAMPLE) {
+    g32_body<BM, BN, BK, false>(bid, e.n, e.lam, e.n, e.BD, e.ldn, e.Z, e.ldn, Epi32Store<BM, BN>{e.Y, e.ldn}, As,
+                                Bs);
+  } else {
+    const Epi32Fitness<BM, BN> epi{e.kind, e.d, e.coef, e.sc, e.partial, e.lam};
+    g32_body<BM, BN, BK, false>(bid, e.n, e.lam, e.n, e.Rt, e.ldn, e.Y, e.ldn, epi, As, Bs);
+  }
 }
 
 __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
@@ -273,13 +300,12 @@ __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
 // NT = 512 the two k-groups of waves are folded through LDS first, so a
 // workgroup covers twice the k-range per partial tile written.
 template <int BM, int BK, int NT>
-__global__ void __launch_bounds__(NT) k_syrk32(int n, int K, int kspan, const float* __restrict__ Y, int ldy,
-                                               float* __restrict__ work, int ntl) {
+__device__ __forceinline__ void syrk32_body(int bid, int nwg, int n, int K, int kspan, const float* __restrict__ Y,
+                                            int ldy, float* __restrict__ work, int ntl, float* smem) {
   using G = G32<BM, BM, BK, true, NT>;
-  __shared__ float smem[2 * BK * G::LDA + 2 * BK * G::LDB];
   float* As = smem;
   float* Bs = smem + 2 * BK * G::LDA;
-  const int item = xcd_swizzle(blockIdx.x, static_cast<int>(gridDim.x));
+  const int item = xcd_swizzle(bid, nwg);
   const int t = item % ntl, s = item / ntl;
   int tm, tn;
   lower_tile(t, tm, tn);
@@ -324,6 +350,24 @@ __global__ void __launch_bounds__(NT) k_syrk32(int n, int K, int kspan, const fl
     }
 }
 
+template <int BM, int BK, int NT>
+__global__ void __launch_bounds__(NT) k_syrk32(int n, int K, int kspan, const float* __restrict__ Y, int ldy,
+                                               float* __restrict__ work, int ntl) {
+  using G = G32<BM, BM, BK, true, NT>;
+  __shared__ float smem[2 * BK * G::LDA + 2 * BK * G::LDB];
+  syrk32_body<BM, BK, NT>(blockIdx.x, static_cast<int>(gridDim.x), n, K, kspan, Y, ldy, work, ntl, smem);
+}
+
+template <int BM, int BK, int NT>
+__global__ void __launch_bounds__(NT) kg_syrk32(const GFront* __restrict__ g, const int* __restrict__ off, int count) {
+  using G = G32<BM, BM, BK, true, NT>;
+  __shared__ float smem[2 * BK * G::LDA + 2 * BK * G::LDB];
+  const int i = group_find(off, count, blockIdx.x);
+  const GFront& e = g[i];
+  syrk32_body<BM, BK, NT>(blockIdx.x - off[i], e.syrk_ntl * e.syrk_splits, e.n, e.mu, e.syrk_kspan, e.Ysel, e.ldn,
+                          e.syrk_work, e.syrk_ntl, smem);
+}
+
 // C <- a C + c1 pc pc^T + cmu * sum_s partial_s, one workgroup per 32 x 32
 // block (R, Q) of the lower block triangle (R >= Q, in units of 32 rows).  The
 // block is one contiguous 4 KiB run of every split's partial tile (fragment-
@@ -333,14 +377,13 @@ __global__ void __launch_bounds__(NT) k_syrk32(int n, int K, int kspan, const fl
 // ascending split order.  The sums pass through LDS so that both the block and
 // its mirror are written as whole columns of C.
 template <int BM>
-__global__ void __launch_bounds__(256) k_syrk32_epi(int n, int ntl, int splits, const float* __restrict__ work,
-                                                    double* __restrict__ C, int ldc, const double* __restrict__ pc,
-                                                    double c1, double cmu, const DevScalars* __restrict__ sc) {
+__device__ __forceinline__ void syrk32_epi_body(int bid, int n, int ntl, int splits, const float* __restrict__ work,
+                                                double* __restrict__ C, int ldc, const double* __restrict__ pc,
+                                                double c1, double cmu, const DevScalars* __restrict__ sc, double* T) {
   constexpr int H = BM / 2, TB = BM / 64, PB = BM / 32;
   constexpr int U = 8;  // splits per batch of loads
-  __shared__ double T[32 * 33];
   int R, Q;
-  lower_tile(blockIdx.x, R, Q);
+  lower_tile(bid, R, Q);
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int tm = R / PB, tn = Q / PB;
   const int t = tm * (tm + 1) / 2 + tn;
@@ -398,6 +441,42 @@ __global__ void __launch_bounds__(256) k_syrk32_epi(int n, int ntl, int splits, 
     if (gr < n && gc < n && (R != Q || brow > bcol))
       C[static_cast<int64_t>(gr) * ldc + gc] = T[bcol * 33 + brow];
   }
+}
+
+template <int BM>
+__global__ void __launch_bounds__(256) k_syrk32_epi(int n, int ntl, int splits, const float* __restrict__ work,
+                                                    double* __restrict__ C, int ldc, const double* __restrict__ pc,
+                                                    double c1, double cmu, const DevScalars* __restrict__ sc) {
+  __shared__ double T[32 * 33];
+  syrk32_epi_body<BM>(blockIdx.x, n, ntl, splits, work, C, ldc, pc, c1, cmu, sc, T);
+}
+
+template <int BM>
+__global__ void __launch_bounds__(256) kg_syrk32_epi(const GFront* __restrict__ g, const int* __restrict__ off,
+                                                     int count) {
+  __shared__ double T[32 * 33];
+  const int i = group_find(off, count, blockIdx.x);
+  const GFront& e = g[i];
+  syrk32_epi_body<BM>(blockIdx.x - off[i], e.n, e.syrk_ntl, e.syrk_splits, e.syrk_work, e.C, e.ldn, e.pc, e.kp.c1,
+                      e.kp.cmu, e.sc, T);
+}
+
+template <int BM, int BN, int BK>
+hipError_t launch_group_cfg(hipStream_t st, int site, const GFront* g, const int* off, int count, int wgs) {
+  if (wgs == 0) return hipSuccess;
+  if (site == G32_SAMPLE)
+    kg_g32<BM, BN, BK, G32_SAMPLE><<<wgs, 256, 0, st>>>(g, off, count);
+  else
+    kg_g32<BM, BN, BK, G32_FITNESS><<<wgs, 256, 0, st>>>(g, off, count);
+  return hipGetLastError();
+}
+
+template <int BM, int BK, int NT>
+hipError_t launch_group_syrk_cfg(hipStream_t st, const GFront* g, const int* off_syrk, int wgs_syrk,
+                                 const int* off_epi, int wgs_epi, int count) {
+  if (wgs_syrk > 0) kg_syrk32<BM, BK, NT><<<wgs_syrk, NT, 0, st>>>(g, off_syrk, count);
+  if (wgs_epi > 0) kg_syrk32_epi<BM><<<wgs_epi, 256, 0, st>>>(g, off_epi, count);
+  return hipGetLastError();
 }
 
 template <int BM, int BN, int BK>
@@ -490,6 +569,41 @@ hipError_t g32_gemm(hipStream_t st, int cfg, int site, int M, int N, int K, cons
     case 4: return launch_cfg<128, 128, 32>(st, site, M, N, K, A, lda, B, ldb, out, ldo, fa);
     case 5: return launch_cfg<64, 64, 32>(st, site, M, N, K, A, lda, B, ldb, out, ldo, fa);
     case 6: return launch_cfg<64, 64, 16>(st, site, M, N, K, A, lda, B, ldb, out, ldo, fa);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int g32_tiles(int cfg, int M, int N) { return ceil_div(M, kG32Configs[cfg].bm) * ceil_div(N, kG32Configs[cfg].bn); }
+
+void syrk32_group_wgs(int cfg, int n, int K, int* wgs_products, int* wgs_epi) {
+  int ntl, splits, kspan;
+  size_t we;
+  syrk32_plan(cfg, n, K, &ntl, &splits, &kspan, &we);
+  const int nb = (n + 31) / 32;
+  *wgs_products = ntl * splits;
+  *wgs_epi = nb * (nb + 1) / 2;
+}
+
+hipError_t launch_group_g32(hipStream_t st, int cfg, int site, const GFront* g, const int* off, int count, int wgs) {
+  switch (cfg) {
+    case 0: return launch_group_cfg<128, 128, 16>(st, site, g, off, count, wgs);
+    case 1: return launch_group_cfg<128, 64, 16>(st, site, g, off, count, wgs);
+    case 2: return launch_group_cfg<64, 128, 16>(st, site, g, off, count, wgs);
+    case 3: return launch_group_cfg<256, 128, 16>(st, site, g, off, count, wgs);
+    case 4: return launch_group_cfg<128, 128, 32>(st, site, g, off, count, wgs);
+    case 5: return launch_group_cfg<64, 64, 32>(st, site, g, off, count, wgs);
+    case 6: return launch_group_cfg<64, 64, 16>(st, site, g, off, count, wgs);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_group_syrk(hipStream_t st, int cfg, const GFront* g, const int* off_syrk, int wgs_syrk,
+                             const int* off_epi, int wgs_epi, int count) {
+  switch (cfg) {
+    case 0: return launch_group_syrk_cfg<128, 16, 256>(st, g, off_syrk, wgs_syrk, off_epi, wgs_epi, count);
+    case 4: return launch_group_syrk_cfg<128, 32, 512>(st, g, off_syrk, wgs_syrk, off_epi, wgs_epi, count);
+    case 5: return launch_group_syrk_cfg<64, 32, 256>(st, g, off_syrk, wgs_syrk, off_epi, wgs_epi, count);
+    case 6: return launch_group_syrk_cfg<64, 16, 256>(st, g, off_syrk, wgs_syrk, off_epi, wgs_epi, count);
     default: return hipErrorInvalidValue;
   }
 }

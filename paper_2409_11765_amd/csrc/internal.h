@@ -269,7 +269,7 @@ struct GEigDesc {  // one descent of a grouped solve (device table entry)
 struct GroupDueMask {  // bit i: descent i solves in this call
   uint32_t w[kGroupMax / 32];
 };
-inline bool due_mask_bit(const GroupDueMask& m, int i) { return (m.w[i >> 5] >> (i & 31)) & 1u; }
+__host__ __device__ inline bool due_mask_bit(const GroupDueMask& m, int i) { return (m.w[i >> 5] >> (i & 31)) & 1u; }
 struct GroupEig {
   void* dtab = nullptr;   // device: GEigDesc[kGroupMax], then the workgroup offsets
   int* hflags = nullptr;  // pinned, mapped: [0] descents still sweeping, [1 + i] sweeps of descent i
@@ -285,6 +285,111 @@ int group_eig_build(hipStream_t st, GroupEig& ge, const std::vector<GEigDesc>& d
 int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int max_sweeps, int ahead,
                     int* sweeps_out);
 void group_eig_release(GroupEig& ge);
+
+// workgroup w of a grouped launch belongs to entry i with off[i] <= w < off[i + 1]
+__device__ __forceinline__ int group_find(const int* __restrict__ off, int count, int w) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= w)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// ---- grouped front: the fixed launches of a generation -- sampling to the
+// eigensolve's warm start, and the stop tests -- for many descents of the
+// mixed precision with a rotated fused objective, one launch per step for all
+// of them (workgroups split over the descents by prefix sums, kind by kind)
+enum GroupFrontKind {
+  GF_NORMALS = 0, GF_SAMPLE, GF_SUB, GF_RMATVEC, GF_RVEC, GF_FITNESS, GF_FREDUCE, GF_RANK, GF_SCATTER, GF_BEST,
+  GF_RECOMB, GF_REDYZ, GF_BMATVEC, GF_VECUPD, GF_SYRK, GF_SYRKEPI, GF_INIT, GF_OFFCOLS, GF_OFFFIN, GF_POLAR,
+  GF_STOP, GF_KINDS
+};
+struct GFront {  // one descent (device table entry)
+  int n, lam, mu, ldn, N;
+  uint32_t k0, k1, restart;
+  DevScalars* sc;
+  const float* BD;
+  float* Z;
+  float* Y;
+  // d = R (m - x*)
+  const double* Rd;
+  double* m;
+  const double* xstar;
+  double* u;
+  double* part_bz;
+  double* d;
+  // fitness
+  int kind;
+  int fit_tiles;
+  const float* Rt;
+  const float* coef;
+  float* partial;
+  double* f;
+  // ranking, best point
+  int32_t* rank_work;
+  int32_t* order;
+  int rank_span, rank_splits;
+  double* x_best;
+  double* hist;
+  int hist_len;
+  // recombination, paths, sigma
+  const double* w;
+  const double* sqrtw;
+  float* Ysel;
+  double* part_yw;
+  double* part_zw;
+  double* yw;
+  double* zw;
+  double* B;
+  double* D;
+  double* ps;
+  double* pc;
+  KParams kp;
+  // covariance
+  float* syrk_work;
+  double* C;
+  int syrk_ntl, syrk_splits, syrk_kspan;
+  // eigensolve set-up and the re-orthogonalisation of B
+  double *V, *A, *A2, *T, *epart, *scale;
+  int* dflags;
+  int* gctl;
+  StopParams sp;
+};
+// one product C = op(A) op(B) per descent, n x n, as launch_dgemm_ksplit
+// plans it (split: two half-k products into C and W, then C += W)
+struct GDgemm {
+  const double* A;
+  int lda;
+  const double* B;
+  int ldb;
+  double* C;
+  int ldc;
+  double* W;
+  int ldw;
+  int n, K0, split;
+};
+// launchers of the grouped steps; g / off: device table and this kind's
+// offsets, wgs: this kind's total workgroups, mask: the descents that take
+// part (the others' workgroups return at once)
+hipError_t launch_group_normals(hipStream_t st, const GFront* g, const int* off, int count, int wgs);
+hipError_t launch_group_g32(hipStream_t st, int cfg, int site, const GFront* g, const int* off, int count, int wgs);
+hipError_t launch_group_syrk(hipStream_t st, int cfg, const GFront* g, const int* off_syrk, int wgs_syrk,
+                             const int* off_epi, int wgs_epi, int count);
+hipError_t launch_group_fitness_reduce(hipStream_t st, const GFront* g, const int* off, int count, int wgs);
+hipError_t launch_group_update(hipStream_t st, int kind, const GFront* g, const int* off, int count, int wgs,
+                               const GroupDueMask* mask);
+hipError_t launch_group_dgemm(hipStream_t st, bool ta, const GDgemm* gd, const int* off_mm, int wgs_mm,
+                              const int* off_add, int wgs_add, int count, const GroupDueMask& mask);
+hipError_t launch_group_eigen_begin(hipStream_t st, int kind, const GFront* g, const int* off, int count, int wgs,
+                                    const GroupDueMask& mask);
+// syrk workgroups per descent (products, epilogue) for tile configuration cfg
+void syrk32_group_wgs(int cfg, int n, int K, int* wgs_products, int* wgs_epi);
+int g32_tiles(int cfg, int M, int N);
+int rank_span_of(int lam);
 
 // stop tests; the bits go to sc->stop and, when hstop is not null, to that
 // word of pinned, mapped host memory (device address)

@@ -45,11 +45,10 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, d
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_normals(T* __restrict__ Z, int ldz, int n, int lam,
-                                                 uint32_t k0, uint32_t k1, uint32_t restart,
-                                                 const DevScalars* __restrict__ sc) {
+__device__ __forceinline__ void normals_body(int bx, T* __restrict__ Z, int ldz, int n, int lam, uint32_t k0,
+                                             uint32_t k1, uint32_t restart, const DevScalars* __restrict__ sc) {
   const int nb = (n + 3) >> 2;
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t idx = static_cast<int64_t>(bx) * blockDim.x + threadIdx.x;
   if (idx >= static_cast<int64_t>(nb) * lam) return;
   const int k = static_cast<int>(idx / nb);
   const int j = static_cast<int>(idx - static_cast<int64_t>(k) * nb);
@@ -72,6 +71,21 @@ __global__ void __launch_bounds__(256) k_normals(T* __restrict__ Z, int ldz, int
   } else {
     for (int q = 0; q < 4 && 4 * j + q < n; ++q) dst[q] = static_cast<T>(z[q]);
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_normals(T* __restrict__ Z, int ldz, int n, int lam,
+                                                 uint32_t k0, uint32_t k1, uint32_t restart,
+                                                 const DevScalars* __restrict__ sc) {
+  normals_body<T>(blockIdx.x, Z, ldz, n, lam, k0, k1, restart, sc);
+}
+
+// the normals of every descent of a group (float32)
+__global__ void __launch_bounds__(256) kg_normals(const GFront* __restrict__ g, const int* __restrict__ off,
+                                                  int count) {
+  const int i = group_find(off, count, blockIdx.x);
+  const GFront& e = g[i];
+  normals_body<float>(blockIdx.x - off[i], e.Z, e.ldn, e.n, e.lam, e.k0, e.k1, e.restart, e.sc);
 }
 
 // Initial mean of a descent: uniform in [lo, hi]^n (Sec. 4.1); coordinate i
@@ -98,6 +112,11 @@ hipError_t launch_normals(hipStream_t st, void* Z, bool fp64, int ldz, int n, in
     k_normals<double><<<blocks, 256, 0, st>>>(static_cast<double*>(Z), ldz, n, lam, k0, k1, restart, sc);
   else
     k_normals<float><<<blocks, 256, 0, st>>>(static_cast<float*>(Z), ldz, n, lam, k0, k1, restart, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_normals(hipStream_t st, const GFront* g, const int* off, int count, int wgs) {
+  if (wgs > 0) kg_normals<<<wgs, 256, 0, st>>>(g, off, count);
   return hipGetLastError();
 }
 

@@ -23,19 +23,19 @@ __device__ __forceinline__ double rank_key(double v) { return v != v ? __builtin
 // its partial count to part[y][i] (summed by k_scatter_order; integers, so
 // the sum is order independent).
 constexpr int kRankChunk = 128, kRankPer = 4, kRankMaxSplits = 64;
-__global__ void __launch_bounds__(256) k_rank_count(const double* __restrict__ f, int lam, int span,
-                                                    int32_t* __restrict__ part) {
+__device__ __forceinline__ void rank_count_body(int bx, int by, const double* __restrict__ f, int lam, int span,
+                                                int32_t* __restrict__ part) {
   __shared__ double sf[kRankChunk];
   int idx[kRankPer], cnt[kRankPer];
   double fi[kRankPer];
 #pragma unroll
   for (int r = 0; r < kRankPer; ++r) {
-    idx[r] = (blockIdx.x * kRankPer + r) * 256 + threadIdx.x;
+    idx[r] = (bx * kRankPer + r) * 256 + threadIdx.x;
     fi[r] = idx[r] < lam ? rank_key(f[idx[r]]) : 0.0;
     cnt[r] = 0;
   }
-  const int j1 = min(lam, (blockIdx.y + 1) * span);
-  for (int j0 = blockIdx.y * span; j0 < j1; j0 += kRankChunk) {
+  const int j1 = min(lam, (by + 1) * span);
+  for (int j0 = by * span; j0 < j1; j0 += kRankChunk) {
     const int lim = min(kRankChunk, j1 - j0);
     __syncthreads();
     if (threadIdx.x < lim) sf[threadIdx.x] = rank_key(f[j0 + threadIdx.x]);
@@ -57,12 +57,17 @@ __global__ void __launch_bounds__(256) k_rank_count(const double* __restrict__ f
   }
 #pragma unroll
   for (int r = 0; r < kRankPer; ++r)
-    if (idx[r] < lam) part[static_cast<int64_t>(blockIdx.y) * lam + idx[r]] = cnt[r];
+    if (idx[r] < lam) part[static_cast<int64_t>(by) * lam + idx[r]] = cnt[r];
 }
 
-__global__ void k_scatter_order(const int32_t* __restrict__ part, int splits, int lam,
-                                int32_t* __restrict__ order) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_rank_count(const double* __restrict__ f, int lam, int span,
+                                                    int32_t* __restrict__ part) {
+  rank_count_body(blockIdx.x, blockIdx.y, f, lam, span, part);
+}
+
+__device__ __forceinline__ void scatter_order_body(int bx, const int32_t* __restrict__ part, int splits, int lam,
+                                                   int32_t* __restrict__ order) {
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= lam) return;
   int rank = 0;
 #pragma unroll 16
@@ -70,20 +75,23 @@ __global__ void k_scatter_order(const int32_t* __restrict__ part, int splits, in
   order[rank] = i;
 }
 
+__global__ void k_scatter_order(const int32_t* __restrict__ part, int splits, int lam,
+                                int32_t* __restrict__ order) {
+  scatter_order_body(blockIdx.x, part, splits, lam, order);
+}
+
 // y_w = sum_{r<mu} w_r y_{order[r]}, z_w likewise (float64 accumulation), and
 // Yhat[:, r] = sqrt(w_r) y_{order[r]} for the rank-mu SYRK.  Grid: rows x
 // chunks of 64 ranks; each chunk writes its own partial sums.
 template <typename T>
-__global__ void __launch_bounds__(256) k_recombine(int n, int mu, const T* __restrict__ Y,
-                                                   const T* __restrict__ Z, int ld,
-                                                   const int32_t* __restrict__ order,
-                                                   const double* __restrict__ w,
-                                                   const double* __restrict__ sqrtw, T* __restrict__ Ysel,
-                                                   int ldsel, double* __restrict__ part_yw,
-                                                   double* __restrict__ part_zw) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void recombine_body(int bx, int by, int n, int mu, const T* __restrict__ Y,
+                                               const T* __restrict__ Z, int ld, const int32_t* __restrict__ order,
+                                               const double* __restrict__ w, const double* __restrict__ sqrtw,
+                                               T* __restrict__ Ysel, int ldsel, double* __restrict__ part_yw,
+                                               double* __restrict__ part_zw) {
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int r0 = blockIdx.y * 64, r1 = min(mu, r0 + 64);
+  const int r0 = by * 64, r1 = min(mu, r0 + 64);
   double ay = 0.0, az = 0.0;
   // unrolled so that many loads are in flight; the sums keep rank order
 #pragma unroll 16
@@ -95,13 +103,25 @@ __global__ void __launch_bounds__(256) k_recombine(int n, int mu, const T* __res
     az += w[r] * static_cast<double>(z);
     Ysel[static_cast<int64_t>(r) * ldsel + i] = static_cast<T>(sqrtw[r] * static_cast<double>(y));
   }
-  part_yw[static_cast<int64_t>(blockIdx.y) * n + i] = ay;
-  part_zw[static_cast<int64_t>(blockIdx.y) * n + i] = az;
+  part_yw[static_cast<int64_t>(by) * n + i] = ay;
+  part_zw[static_cast<int64_t>(by) * n + i] = az;
 }
 
-__global__ void k_reduce_yz(int n, int nchunks, const double* __restrict__ py, const double* __restrict__ pz,
-                            double* __restrict__ yw, double* __restrict__ zw) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+template <typename T>
+__global__ void __launch_bounds__(256) k_recombine(int n, int mu, const T* __restrict__ Y,
+                                                   const T* __restrict__ Z, int ld,
+                                                   const int32_t* __restrict__ order,
+                                                   const double* __restrict__ w,
+                                                   const double* __restrict__ sqrtw, T* __restrict__ Ysel,
+                                                   int ldsel, double* __restrict__ part_yw,
+                                                   double* __restrict__ part_zw) {
+  recombine_body<T>(blockIdx.x, blockIdx.y, n, mu, Y, Z, ld, order, w, sqrtw, Ysel, ldsel, part_yw, part_zw);
+}
+
+__device__ __forceinline__ void reduce_yz_body(int bx, int n, int nchunks, const double* __restrict__ py,
+                                               const double* __restrict__ pz, double* __restrict__ yw,
+                                               double* __restrict__ zw) {
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double a = 0.0, b = 0.0;
 #pragma unroll 16
@@ -113,16 +133,26 @@ __global__ void k_reduce_yz(int n, int nchunks, const double* __restrict__ py, c
   zw[i] = b;
 }
 
+__global__ void k_reduce_yz(int n, int nchunks, const double* __restrict__ py, const double* __restrict__ pz,
+                            double* __restrict__ yw, double* __restrict__ zw) {
+  reduce_yz_body(blockIdx.x, n, nchunks, py, pz, yw, zw);
+}
+
 // part[c][i] = sum_{j in chunk c} B[i + j ld] x[j]
-__global__ void __launch_bounds__(256) k_matvec(int n, const double* __restrict__ B, int ldb,
-                                                const double* __restrict__ x, double* __restrict__ part) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void matvec_body(int bx, int by, int n, const double* __restrict__ B, int ldb,
+                                            const double* __restrict__ x, double* __restrict__ part) {
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int j0 = blockIdx.y * 64, j1 = min(n, j0 + 64);
+  const int j0 = by * 64, j1 = min(n, j0 + 64);
   double s = 0.0;
 #pragma unroll 16
   for (int j = j0; j < j1; ++j) s += B[static_cast<int64_t>(j) * ldb + i] * x[j];
-  part[static_cast<int64_t>(blockIdx.y) * n + i] = s;
+  part[static_cast<int64_t>(by) * n + i] = s;
+}
+
+__global__ void __launch_bounds__(256) k_matvec(int n, const double* __restrict__ B, int ldb,
+                                                const double* __restrict__ x, double* __restrict__ part) {
+  matvec_body(blockIdx.x, blockIdx.y, n, B, ldb, x, part);
 }
 
 template <int NT>
@@ -140,10 +170,10 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // p_sigma, h_sigma, p_c, m, sigma and the covariance coefficient a.
-__global__ void __launch_bounds__(1024) k_vec_update(KParams kp, int nchunks, const double* __restrict__ part_bz,
-                                                     const double* __restrict__ yw, double* __restrict__ m,
-                                                     double* __restrict__ ps, double* __restrict__ pc,
-                                                     DevScalars* __restrict__ sc) {
+__device__ __forceinline__ void vec_update_body(const KParams& kp, int nchunks, const double* __restrict__ part_bz,
+                                                const double* __restrict__ yw, double* __restrict__ m,
+                                                double* __restrict__ ps, double* __restrict__ pc,
+                                                DevScalars* __restrict__ sc) {
   __shared__ double red[1024];
   const int n = kp.n;
   const double sigma = sc->sigma;
@@ -176,13 +206,19 @@ __global__ void __launch_bounds__(1024) k_vec_update(KParams kp, int nchunks, co
   }
 }
 
+__global__ void __launch_bounds__(1024) k_vec_update(KParams kp, int nchunks, const double* __restrict__ part_bz,
+                                                     const double* __restrict__ yw, double* __restrict__ m,
+                                                     double* __restrict__ ps, double* __restrict__ pc,
+                                                     DevScalars* __restrict__ sc) {
+  vec_update_body(kp, nchunks, part_bz, yw, m, ps, pc, sc);
+}
+
 // Best-so-far point and the f-history ring; runs before m and sigma move.
 template <typename T>
-__global__ void __launch_bounds__(256) k_best(int n, int lam, const double* __restrict__ f,
-                                              const int32_t* __restrict__ order, const T* __restrict__ Y,
-                                              int ldy, const double* __restrict__ m, double* __restrict__ x_best,
-                                              double* __restrict__ hist, int hist_len,
-                                              DevScalars* __restrict__ sc) {
+__device__ __forceinline__ void best_body(int n, int lam, const double* __restrict__ f,
+                                          const int32_t* __restrict__ order, const T* __restrict__ Y, int ldy,
+                                          const double* __restrict__ m, double* __restrict__ x_best,
+                                          double* __restrict__ hist, int hist_len, DevScalars* __restrict__ sc) {
   const int i0 = order[0];
   const double f0 = rank_key(f[i0]);
   const double flast = rank_key(f[order[lam - 1]]);
@@ -200,6 +236,15 @@ __global__ void __launch_bounds__(256) k_best(int n, int lam, const double* __re
     sc->f_gen_max = flast;
     if (better) sc->f_best = f0;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_best(int n, int lam, const double* __restrict__ f,
+                                              const int32_t* __restrict__ order, const T* __restrict__ Y,
+                                              int ldy, const double* __restrict__ m, double* __restrict__ x_best,
+                                              double* __restrict__ hist, int hist_len,
+                                              DevScalars* __restrict__ sc) {
+  best_body<T>(n, lam, f, order, Y, ldy, m, x_best, hist, hist_len, sc);
 }
 
 __device__ __forceinline__ int block_or(int v, int* red) {
@@ -225,12 +270,11 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 
 // Stopping tests evaluated after the update (reading of Sec. 2.2; thresholds
 // of the original IPOP-CMA-ES paper).
-__global__ void __launch_bounds__(256) k_stop(KParams kp, StopParams sp, const double* __restrict__ m,
-                                              const double* __restrict__ C, int ldc,
-                                              const double* __restrict__ B, int ldb,
-                                              const double* __restrict__ D, const double* __restrict__ pc,
-                                              const double* __restrict__ hist, DevScalars* __restrict__ sc,
-                                              uint32_t* __restrict__ hstop) {
+__device__ __forceinline__ void stop_body(const KParams& kp, const StopParams& sp, const double* __restrict__ m,
+                                          const double* __restrict__ C, int ldc, const double* __restrict__ B,
+                                          int ldb, const double* __restrict__ D, const double* __restrict__ pc,
+                                          const double* __restrict__ hist, DevScalars* __restrict__ sc,
+                                          uint32_t* __restrict__ hstop) {
   __shared__ double red[256];
   __shared__ int ired;
   const int n = kp.n;
@@ -285,19 +329,38 @@ __global__ void __launch_bounds__(256) k_stop(KParams kp, StopParams sp, const d
   if (hstop) __hip_atomic_store(hstop, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+__global__ void __launch_bounds__(256) k_stop(KParams kp, StopParams sp, const double* __restrict__ m,
+                                              const double* __restrict__ C, int ldc,
+                                              const double* __restrict__ B, int ldb,
+                                              const double* __restrict__ D, const double* __restrict__ pc,
+                                              const double* __restrict__ hist, DevScalars* __restrict__ sc,
+                                              uint32_t* __restrict__ hstop) {
+  stop_body(kp, sp, m, C, ldc, B, ldb, D, pc, hist, sc, hstop);
+}
+
 // u = m - x* (x* may be null = origin)
-__global__ void k_sub(int n, const double* __restrict__ m, const double* __restrict__ xs, double* __restrict__ u) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sub_body(int bx, int n, const double* __restrict__ m, const double* __restrict__ xs,
+                                         double* __restrict__ u) {
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i < n) u[i] = m[i] - (xs ? xs[i] : 0.0);
 }
 
-__global__ void k_reduce_vec(int n, int nchunks, const double* __restrict__ part, double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_sub(int n, const double* __restrict__ m, const double* __restrict__ xs, double* __restrict__ u) {
+  sub_body(blockIdx.x, n, m, xs, u);
+}
+
+__device__ __forceinline__ void reduce_vec_body(int bx, int n, int nchunks, const double* __restrict__ part,
+                                                double* __restrict__ out) {
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double a = 0.0;
 #pragma unroll 16
   for (int c = 0; c < nchunks; ++c) a += part[static_cast<int64_t>(c) * n + i];
   out[i] = a;
+}
+
+__global__ void k_reduce_vec(int n, int nchunks, const double* __restrict__ part, double* __restrict__ out) {
+  reduce_vec_body(blockIdx.x, n, nchunks, part, out);
 }
 
 __global__ void k_set_identity(double* A, int n, int ld) {
@@ -401,14 +464,75 @@ hipError_t launch_shift(hipStream_t st, int n, const double* R, int ldr, const d
 
 // B <- (3 B - B (B^T B)) / 2 from T = B (B^T B): one Newton-Schulz step
 // towards the orthogonal polar factor of B (rows < n only)
-__global__ void k_polar_step(int n, double* __restrict__ B, int ldb, const double* __restrict__ T, int ldt) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void polar_body(int bx, int n, double* __restrict__ B, int ldb, const double* __restrict__ T,
+                                           int ldt) {
+  const int64_t idx = static_cast<int64_t>(bx) * blockDim.x + threadIdx.x;
   const int64_t total = static_cast<int64_t>(n) * n;
   if (idx >= total) return;
   const int col = static_cast<int>(idx / n), row = static_cast<int>(idx % n);
   double& b = B[static_cast<int64_t>(col) * ldb + row];
   b = 1.5 * b - 0.5 * T[static_cast<int64_t>(col) * ldt + row];
 }
+
+__global__ void k_polar_step(int n, double* __restrict__ B, int ldb, const double* __restrict__ T, int ldt) {
+  polar_body(blockIdx.x, n, B, ldb, T, ldt);
+}
+
+// ---- the update steps of a grouped front (one launch per step for all
+// descents; workgroup w of descent i is local block w - off[i], split into
+// (bx, by) by the descent's own grid width)
+__global__ void __launch_bounds__(256) kg_update256(int kind, const GFront* __restrict__ g, const int* __restrict__ off,
+                                                    int count, GroupDueMask mask) {
+  const int i = group_find(off, count, blockIdx.x);
+  const GFront& e = g[i];
+  const int w = blockIdx.x - off[i];
+  const int gx = (e.n + 255) / 256;
+  switch (kind) {
+    case GF_SUB: sub_body(w, e.n, e.m, e.xstar, e.u); break;
+    case GF_RMATVEC: matvec_body(w % gx, w / gx, e.n, e.Rd, e.ldn, e.u, e.part_bz); break;
+    case GF_RVEC: reduce_vec_body(w, e.n, (e.n + 63) / 64, e.part_bz, e.d); break;
+    case GF_RANK: {
+      const int rx = (e.lam + 256 * kRankPer - 1) / (256 * kRankPer);
+      rank_count_body(w % rx, w / rx, e.f, e.lam, e.rank_span, e.rank_work);
+      break;
+    }
+    case GF_SCATTER: scatter_order_body(w, e.rank_work, e.rank_splits, e.lam, e.order); break;
+    case GF_BEST: best_body<float>(e.n, e.lam, e.f, e.order, e.Y, e.ldn, e.m, e.x_best, e.hist, e.hist_len, e.sc); break;
+    case GF_RECOMB:
+      recombine_body<float>(w % gx, w / gx, e.n, e.mu, e.Y, e.Z, e.ldn, e.order, e.w, e.sqrtw, e.Ysel, e.ldn,
+                            e.part_yw, e.part_zw);
+      break;
+    case GF_REDYZ: reduce_yz_body(w, e.n, (e.mu + 63) / 64, e.part_yw, e.part_zw, e.yw, e.zw); break;
+    case GF_BMATVEC: matvec_body(w % gx, w / gx, e.n, e.B, e.ldn, e.zw, e.part_bz); break;
+    case GF_POLAR:
+      if (due_mask_bit(mask, i)) polar_body(w, e.n, e.B, e.ldn, e.T, e.ldn);
+      break;
+    case GF_STOP: stop_body(e.kp, e.sp, e.m, e.C, e.ldn, e.B, e.ldn, e.D, e.pc, e.hist, e.sc, nullptr); break;
+    default: break;
+  }
+}
+
+__global__ void __launch_bounds__(1024) kg_vec_update(const GFront* __restrict__ g, const int* __restrict__ off,
+                                                      int count) {
+  const int i = group_find(off, count, blockIdx.x);
+  const GFront& e = g[i];
+  vec_update_body(e.kp, (e.n + 63) / 64, e.part_bz, e.yw, e.m, e.ps, e.pc, e.sc);
+}
+
+hipError_t launch_group_update(hipStream_t st, int kind, const GFront* g, const int* off, int count, int wgs,
+                               const GroupDueMask* mask) {
+  if (wgs == 0) return hipSuccess;
+  if (kind == GF_VECUPD) {
+    kg_vec_update<<<wgs, 1024, 0, st>>>(g, off, count);
+  } else {
+    GroupDueMask m{};
+    if (mask) m = *mask;
+    kg_update256<<<wgs, 256, 0, st>>>(kind, g, off, count, m);
+  }
+  return hipGetLastError();
+}
+
+int rank_span_of(int lam) { return rank_span(lam); }
 
 hipError_t launch_polar_step(hipStream_t st, int n, double* B, int ldb, const double* T, int ldt) {
   const int64_t total = static_cast<int64_t>(n) * n;
