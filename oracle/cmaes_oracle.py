@@ -40,6 +40,12 @@ Pins (tests under ``tests/`` that tie this file to something other than itself):
   covariance, sample covariance of y, CSA drift under random selection,
   linear convergence on the sphere.
 * ``ipop``           - lambda sequence lambda_start * 2^k and K_max stop.
+* ``params`` / ``covariance_update`` variants - active: C stays positive
+  definite against the worst negative-rank steps (the alpha_posdef bound),
+  the update written out entry by entry with C^{-1/2} from eigh, zero
+  negative weights give the standard update; separable: n = 1 equals the
+  standard variant, C stays diagonal and equals the diagonal of the standard
+  update with the separable rates; both converge on the ellipsoid.
 * ``sphere``, ``rot_ellipsoid``, ``rot_rastrigin`` - zero at x* under any
   rotation, the ellipsoid's axis scales 10^(6 (i-1)/(n-1)) along R^T e_i,
   Rastrigin = sum u^2 at integer u and 20.25 n at u = 1/2, n = 1 edge case.
@@ -57,7 +63,7 @@ __all__ = [
     "philox4x32_10", "u32_to_unit", "box_muller", "normals", "init_mean",
     "Objective", "sphere", "rot_ellipsoid", "rot_rastrigin",
     "State", "new_descent", "sample", "rank_order", "covariance_update",
-    "eigen_canonical", "generation", "StopOptions", "stop_bits", "ipop",
+    "eigen_canonical", "generation", "StopOptions", "stop_bits", "ipop", "VARIANTS",
     "STOP_TOLHISTFUN", "STOP_TOLFUN", "STOP_TOLX", "STOP_NOEFFECTAXIS",
     "STOP_NOEFFECTCOORD", "STOP_CONDITIONCOV", "STOP_FTARGET", "STOP_MAXGEN",
     "STOP_MAXEVALS", "STOP_NUMERIC",
@@ -88,18 +94,39 @@ class Params:
     cmu: float
     chin: float
     kappa: int             # eigendecomposition interval in generations
+    variant: str = "standard"
+    # weights of all lambda ranks: w_1..w_mu as above, then 0 (standard,
+    # separable) or the negative weights of the active update
+    w_all: np.ndarray | None = None
+    sumw: float = 1.0      # sum of w_all (< 1 with negative weights)
 
 
-def params(n: int, lam: int, kappa: int = 0) -> Params:
+VARIANTS = ("standard", "active", "separable")
+
+
+def params(n: int, lam: int, kappa: int = 0, variant: str = "standard") -> Params:
     """Default strategy parameters for dimension n and population lam.
 
     The weights are the rank weights w_rk(i) of eq. (2): better points get
     larger weights and the weights sum to one (Sec. 2.1).  Points ranked
     beyond mu get weight zero (reading: no negative weights).
     kappa = 0 selects the automatic interval max(1, ceil(1/(10 n (c1+cmu)))).
+
+    variant (the paper's future work, Sec. 5; readings of the CMA-ES tutorial,
+    Hansen arXiv:1604.00772, and of Ros & Hansen, PPSN 2008):
+    * "active": ranks beyond mu get negative weights in the covariance update
+      only, w'_i = ln((lam+1)/2) - ln i scaled so that they sum to
+      -min(1 + c1/cmu, 1 + 2 mueff^-/(mueff + 2), (1 - c1 - cmu)/(n cmu)),
+      mueff^- = (sum w'^-)^2 / sum (w'^-)^2; mean, paths and the other
+      rates are those of the standard variant;
+    * "separable": C is kept diagonal (the large-scale variant sep-CMA-ES),
+      c1 and cmu multiplied by (n + 2)/3 (cmu at most 1 - c1), B = I and
+      D = sqrt(diag C) after every generation (kappa = 1).
     """
     if n < 1 or lam < 2:
         raise ValueError("need n >= 1 and lambda >= 2")
+    if variant not in VARIANTS:
+        raise ValueError(f"variant must be one of {VARIANTS}")
     mu = lam // 2
     i = np.arange(1, mu + 1, dtype=np.float64)
     wp = math.log((lam + 1) / 2.0) - np.log(i)
@@ -111,9 +138,24 @@ def params(n: int, lam: int, kappa: int = 0) -> Params:
     c1 = 2.0 / ((n + 1.3) ** 2 + mueff)
     cmu = min(1.0 - c1, 2.0 * (mueff - 2.0 + 1.0 / mueff) / ((n + 2.0) ** 2 + mueff))
     chin = math.sqrt(n) * (1.0 - 1.0 / (4.0 * n) + 1.0 / (21.0 * n * n))
+    w_all = np.concatenate([w, np.zeros(lam - mu)])
+    sumw = 1.0
+    if variant == "separable":
+        c1 = min(1.0, c1 * (n + 2.0) / 3.0)
+        cmu = min(1.0 - c1, cmu * (n + 2.0) / 3.0)
+        kappa = 1
+    if variant == "active":
+        wn = math.log((lam + 1) / 2.0) - np.log(np.arange(mu + 1, lam + 1, dtype=np.float64))
+        wn = np.minimum(wn, 0.0)          # an odd lam leaves w'_{mu+1} = 0
+        if np.any(wn < 0.0) and cmu > 0.0:   # (cmu = 0, e.g. lam = 2: no rank-mu term at all)
+            mueff_neg = float(wn.sum() ** 2 / np.sum(wn * wn))
+            alpha = min(1.0 + c1 / cmu, 1.0 + 2.0 * mueff_neg / (mueff + 2.0),
+                        (1.0 - c1 - cmu) / (n * cmu))
+            w_all[mu:] = alpha * wn / np.sum(np.abs(wn))
+            sumw = float(np.sum(w_all))
     if kappa <= 0:
         kappa = max(1, int(math.ceil(1.0 / (10.0 * n * (c1 + cmu)))))
-    return Params(n, lam, mu, w, mueff, cs, ds, cc, c1, cmu, chin, kappa)
+    return Params(n, lam, mu, w, mueff, cs, ds, cc, c1, cmu, chin, kappa, variant, w_all, sumw)
 
 
 # ---------------------------------------------------------------------------
@@ -309,10 +351,10 @@ class State:
     stop: int = 0
 
 
-def new_descent(n, lam, sigma0, seed, restart=0, box=(-4.0, 4.0), kappa=0) -> State:
+def new_descent(n, lam, sigma0, seed, restart=0, box=(-4.0, 4.0), kappa=0, variant="standard") -> State:
     """Initialisation line of Alg. 1 / Alg. 2: m uniform in the box (Sec. 4.1),
     sigma = sigma0, C = B = D = I, both evolution paths zero."""
-    p = params(n, lam, kappa)
+    p = params(n, lam, kappa, variant)
     m = init_mean(seed, restart, n, box[0], box[1])
     I = np.eye(n)
     return State(p=p, m=m, sigma=float(sigma0), C=I.copy(), B=I.copy(), D=np.ones(n),
@@ -334,13 +376,32 @@ def rank_order(f) -> np.ndarray:
     return np.argsort(fk, kind="stable")
 
 
-def covariance_update(C, pc, Y, order, p: Params, hsig: float):
+def covariance_update(C, pc, Y, order, p: Params, hsig: float, B=None, D=None):
     """Rank-one plus rank-mu update in the eq. (3) form:
     C <- a C + c1 pc pc^T + cmu * sum_{i<=mu} w_i y_{i:lam} y_{i:lam}^T,
     a = 1 - c1 - cmu + (1 - hsig) c1 cc (2 - cc).  With hsig = 1 this is
-    exactly eq. (3) (and eq. (2), since the weights sum to one)."""
-    a = 1.0 - p.c1 - p.cmu + (1.0 - hsig) * p.c1 * p.cc * (2.0 - p.cc)
+    exactly eq. (3) (and eq. (2), since the weights sum to one).
+
+    active: the sum runs over all lam ranks with the signed weights, a uses
+    sum_i w_i instead of 1, and a negative weight is scaled by
+    n / ||C^{-1/2} y_{i:lam}||^2 with C^{-1/2} = B D^{-1} B^T of the C that
+    sampled y (B, D given).  separable: the diagonal of the standard update."""
+    delta = (1.0 - hsig) * p.c1 * p.cc * (2.0 - p.cc)
+    if p.variant == "active":
+        a = 1.0 - p.c1 - p.cmu * p.sumw + delta
+        Ys = Y[:, order]
+        wo = p.w_all.copy()
+        neg = wo < 0.0
+        if np.any(neg):
+            Ci = B @ ((B.T @ Ys[:, neg]) / D[:, None])
+            wo[neg] = wo[neg] * p.n / np.sum(Ci * Ci, axis=0)
+        Cn = a * C + p.c1 * np.outer(pc, pc) + p.cmu * ((Ys * wo[None, :]) @ Ys.T)
+        return 0.5 * (Cn + Cn.T)
+    a = 1.0 - p.c1 - p.cmu + delta
     Ys = Y[:, order[:p.mu]]
+    if p.variant == "separable":
+        dn = a * np.diag(C) + p.c1 * pc * pc + p.cmu * ((Ys * Ys) @ p.w)
+        return np.diag(dn)
     Cn = a * C + p.c1 * np.outer(pc, pc) + p.cmu * ((Ys * p.w[None, :]) @ Ys.T)
     return 0.5 * (Cn + Cn.T)
 
@@ -420,12 +481,15 @@ def generation(st: State, objective, Z=None, so: StopOptions | None = None, fval
     hsig = 1.0 if nps / math.sqrt(1.0 - (1.0 - p.cs) ** (2 * (st.gen + 1))) \
         < (1.4 + 2.0 / (n + 1.0)) * p.chin else 0.0
     st.pc = (1.0 - p.cc) * st.pc + hsig * math.sqrt(p.cc * (2.0 - p.cc) * p.mueff) * yw
-    st.C = covariance_update(st.C, st.pc, Y, order, p, hsig)      # eq. (2)/(3)
+    st.C = covariance_update(st.C, st.pc, Y, order, p, hsig, st.B, st.D)  # eq. (2)/(3)
     st.sigma = sigma_old * math.exp((p.cs / p.ds) * (nps / p.chin - 1.0))
     st.gen += 1
     st.evals += p.lam
     eig_ok = True
-    if st.gen % p.kappa == 0:
+    if p.variant == "separable":
+        dc = np.diag(st.C)
+        st.B, st.D, eig_ok = np.eye(n), np.sqrt(np.maximum(dc, 0.0)), bool(np.all(dc > 0.0))
+    elif st.gen % p.kappa == 0:
         st.B, st.D, eig_ok = eigen_canonical(st.C)
     fin = np.where(np.isnan(f), np.inf, f)
     i0 = int(order[0])
@@ -443,7 +507,8 @@ def generation(st: State, objective, Z=None, so: StopOptions | None = None, fval
 
 
 def ipop(n, lam_start, sigma0, seed, objective, k_max=2 ** 9, box=(-4.0, 4.0),
-         so: StopOptions | None = None, kappa=0, max_total_evals=0, max_gens_per_descent=0):
+         so: StopOptions | None = None, kappa=0, max_total_evals=0, max_gens_per_descent=0,
+         variant="standard"):
     """Alg. 2: K = 1; while K <= K_max and budget left: fresh descent with
     lambda = K * lambda_start until a stopping test fires; K <- 2K.
     Returns (best f, best x, list of per-descent records)."""
@@ -451,7 +516,7 @@ def ipop(n, lam_start, sigma0, seed, objective, k_max=2 ** 9, box=(-4.0, 4.0),
     K, restart = 1, 0
     best_f, best_x, evals, log = math.inf, None, 0, []
     while K <= k_max and (max_total_evals <= 0 or evals < max_total_evals):
-        st = new_descent(n, K * lam_start, sigma0, seed, restart, box, kappa)
+        st = new_descent(n, K * lam_start, sigma0, seed, restart, box, kappa, variant)
         so_d = StopOptions(**{**so.__dict__, "max_gens": max_gens_per_descent or so.max_gens})
         while True:
             generation(st, objective, so=so_d)
