@@ -974,6 +974,7 @@ __global__ void __launch_bounds__(64) kg_start(const GEigDesc* __restrict__ g, i
     st[1] = 0;
     st[2] = 0;
     __hip_atomic_store(&hsweeps[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&hsweeps[kGroupMax + i], st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -1034,6 +1035,7 @@ __global__ void __launch_bounds__(256) kg_round(const GEigDesc* __restrict__ g, 
   st[1] = done;
   st[2] = 0;
   __hip_atomic_store(&hsweeps[i], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&hsweeps[kGroupMax + i], st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   __hip_atomic_fetch_add(hactive, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -1320,7 +1322,7 @@ int group_eig_build(hipStream_t st, GroupEig& ge, const std::vector<GEigDesc>& d
       return fail(-2, "grouped eigensolve: hipMalloc failed");
     ge.dtab = d;
     void* hf = nullptr;
-    if (hipHostMalloc(&hf, sizeof(int) * (kGroupMax + 1), hipHostMallocMapped | hipHostMallocCoherent) !=
+    if (hipHostMalloc(&hf, sizeof(int) * (2 * kGroupMax + 1), hipHostMallocMapped | hipHostMallocCoherent) !=
         hipSuccess)
       return fail(-2, "grouped eigensolve: hipHostMalloc failed");
     ge.hflags = static_cast<int*>(hf);
@@ -1341,7 +1343,7 @@ int group_eig_build(hipStream_t st, GroupEig& ge, const std::vector<GEigDesc>& d
 }
 
 int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int max_sweeps, int ahead,
-                    int* sweeps_out) {
+                    int* sweeps_out, int* code_out) {
   const int count = ge.count;
   const GEigDesc* tab = static_cast<const GEigDesc*>(ge.dtab);
   const int* offs = reinterpret_cast<const int*>(static_cast<const char*>(ge.dtab) + sizeof(GEigDesc) * kGroupMax);
@@ -1359,7 +1361,11 @@ int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int m
   // test) are queued before the host first waits; then one batch per wait
   // until no descent sweeps any more.  Rounds of descents that have stopped
   // return at once.
+  // With short sweeps (small n) several are queued per wait, about kWaitRounds
+  // rounds, since a round of stopped descents costs little and a wait much.
+  constexpr int kWaitRounds = 8;
   const int rounds = ge.pmax - 1;
+  const int per_wait = std::max(1, kWaitRounds / rounds);
   int rg = 0;
   auto queue_batch = [&]() -> int {
     for (int r = 0; r < rounds; ++r, ++rg)
@@ -1367,20 +1373,26 @@ int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int m
     CMX_HIP(hipGetLastError());
     return 0;
   };
-  for (int b = 0; b < std::min(ahead, max_sweeps); ++b)
+  int queued = 0;
+  for (; queued < std::min(std::max(ahead, per_wait), max_sweeps); ++queued)
     if (int rc = queue_batch()) return rc;
-  for (int batch = ahead;; ++batch) {
+  for (;;) {
     CMX_HIP(hipStreamSynchronize(st));
     if (__atomic_load_n(&ge.hflags[0], __ATOMIC_ACQUIRE) <= 0) break;
-    if (batch >= max_sweeps + 1) return fail(-3, "grouped eigensolve: descents still sweeping past the sweep limit");
-    if (int rc = queue_batch()) return rc;
+    if (queued >= max_sweeps + per_wait)
+      return fail(-3, "grouped eigensolve: descents still sweeping past the sweep limit");
+    for (int b = 0; b < per_wait; ++b, ++queued)
+      if (int rc = queue_batch()) return rc;
   }
   kg_rank<<<wgs_of(2), 256, 0, st>>>(tab, off_of(2), count);
   kg_colsign<<<wgs_of(3), 256, 0, st>>>(tab, off_of(3), count);
   kg_permute<<<wgs_of(4), 256, 0, st>>>(tab, off_of(4), count);
   CMX_HIP(hipGetLastError());
   for (int i = 0; i < count; ++i)
-    if (due_mask_bit(due, i)) sweeps_out[i] = __atomic_load_n(&ge.hflags[1 + i], __ATOMIC_ACQUIRE);
+    if (due_mask_bit(due, i)) {
+      sweeps_out[i] = __atomic_load_n(&ge.hflags[1 + i], __ATOMIC_ACQUIRE);
+      if (code_out) code_out[i] = __atomic_load_n(&ge.hflags[1 + kGroupMax + i], __ATOMIC_ACQUIRE);
+    }
   return 0;
 }
 

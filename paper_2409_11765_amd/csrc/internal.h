@@ -35,6 +35,8 @@ struct DevScalars {
 struct KParams {
   int n, lam, mu, kappa;
   double mueff, cs, ds, cc, c1, cmu, chin;
+  double sumw;  // sum of the weights of all ranks (1, or less with active negative weights)
+  int variant;  // cmaes_variant_t
 };
 
 struct StopParams {
@@ -147,8 +149,10 @@ hipError_t launch_best(hipStream_t st, bool fp64, int n, int lam, const double* 
 // FP64 path covariance update C <- a C + c1 pc pc^T + cmu Ysel Ysel^T (lower
 // tiles + mirror); the mixed paths use g32_syrk
 void syrk_plan_f64(int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems);
-hipError_t launch_syrk_update_f64(hipStream_t st, int n, int mu, const double* Ysel, int ldsel, double* C, int ldc,
-                                  const double* pc, double c1, double cmu, const DevScalars* sc, double* work);
+// Ysel2: null, or the second operand (Ysel with signed columns)
+hipError_t launch_syrk_update_f64(hipStream_t st, int n, int mu, const double* Ysel, const double* Ysel2, int ldsel,
+                                  double* C, int ldc, const double* pc, double c1, double cmu, const DevScalars* sc,
+                                  double* work);
 
 // ---- tunable float32 MFMA GEMMs (mixed precisions) -------------------------
 enum G32Site { G32_SAMPLE = 0, G32_FITNESS = 1, G32_SYRK = 2, G32_NUM_SITES = 3 };
@@ -175,8 +179,9 @@ size_t syrk32_max_work(int n, int K);
 // C <- a C + c1 pc pc^T + cmu Y Y^T; partial_only stops after the split-k
 // products (the tuner times that part alone, C is left untouched); kt (or
 // null) times the products and the epilogue as KID_SYRK and KID_SYRK_EPI
-hipError_t g32_syrk(hipStream_t st, int cfg, int n, int K, const float* Y, int ldy, float* work, double* C, int ldc,
-                    const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only, KTimer* kt);
+hipError_t g32_syrk(hipStream_t st, int cfg, int n, int K, const float* Y, const float* Y2, int ldy, float* work,
+                    double* C, int ldc, const double* pc, double c1, double cmu, const DevScalars* sc,
+                    bool partial_only, KTimer* kt);
 
 // generic FP64 GEMM: C = op(A) * op(B), column-major
 hipError_t launch_dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
@@ -272,7 +277,8 @@ struct GroupDueMask {  // bit i: descent i solves in this call
 __host__ __device__ inline bool due_mask_bit(const GroupDueMask& m, int i) { return (m.w[i >> 5] >> (i & 31)) & 1u; }
 struct GroupEig {
   void* dtab = nullptr;   // device: GEigDesc[kGroupMax], then the workgroup offsets
-  int* hflags = nullptr;  // pinned, mapped: [0] descents still sweeping, [1 + i] sweeps of descent i
+  int* hflags = nullptr;  // pinned, mapped: [0] descents still sweeping, [1 + i] sweeps of descent i,
+                          // [1 + kGroupMax + i] its status (1 converged, 2 sweep limit, 3 non-finite)
   int* dflags = nullptr;  // device address of hflags
   int cap = 0, count = 0, pmax = 2;
   std::vector<int> off;   // host copy of the offsets (kGroupKinds x (count + 1))
@@ -281,9 +287,10 @@ struct GroupEig {
 int group_eig_build(hipStream_t st, GroupEig& ge, const std::vector<GEigDesc>& descs);
 // Solve the due descents, whose warm starts (eigen_begin) are already queued
 // on `st` or ordered before it; ahead: sweeps to queue before the first wait.
-// sweeps_out[i] receives the sweeps of due descent i.
+// sweeps_out[i] receives the sweeps of due descent i, code_out[i] (may be
+// null) its status: 1 converged, 2 sweep limit, 3 non-finite values.
 int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int max_sweeps, int ahead,
-                    int* sweeps_out);
+                    int* sweeps_out, int* code_out);
 void group_eig_release(GroupEig& ge);
 
 // workgroup w of a grouped launch belongs to entry i with off[i] <= w < off[i + 1]
@@ -396,6 +403,24 @@ int rank_span_of(int lam);
 hipError_t launch_stop(hipStream_t st, const KParams& kp, const StopParams& sp, const double* m,
                        const double* C, int ldc, const double* B, int ldb, const double* D,
                        const double* pc, const double* hist, DevScalars* sc, uint32_t* hstop);
+
+// variants (cmaes_variant_t)
+// active: Ysel[:, r] = s_r y_{order[r]} and Ysig[:, r] = sign(w_r) Ysel[:, r]
+// for the ranks r >= mu, s_r = sqrt(|w_r| n / ||z_{order[r]}||^2) (w_r = 0:
+// zero columns), and Ysig[:, r] = Ysel[:, r] for r < mu
+hipError_t launch_active_cols(hipStream_t st, bool fp64, int n, int lam, int mu, const void* Y, const void* Z, int ld,
+                              const int32_t* order, const double* w_all, void* Ysel, void* Ysig, int ldsel);
+// separable: Y = D z column by column (no product)
+hipError_t launch_sep_sample(hipStream_t st, bool fp64, int n, int lam, const double* D, const void* Z, int ldz,
+                             void* Y, int ldy);
+// separable: C_ii <- c_coef C_ii + c1 pc_i^2 + cmu sum_{r<mu} w_r y_{i, order[r]}^2
+hipError_t launch_sep_cov(hipStream_t st, bool fp64, int n, int mu, const void* Y, int ldy, const int32_t* order,
+                          const double* w, const double* pc, double c1, double cmu, double* C, int ldc,
+                          const DevScalars* sc);
+// separable: D = sqrt(diag C), B D = diag(D) in the sampling precision, the
+// decomposition's status (positive diagonal) into sc
+hipError_t launch_sep_eigen(hipStream_t st, bool fp64, int n, const double* C, int ldc, double* D, void* BD, int ldbd,
+                            DevScalars* sc);
 
 // misc
 // B <- (3 B - T) / 2 with T = B (B^T B) (Newton-Schulz step, rows < n)
