@@ -64,6 +64,7 @@ __all__ = [
     "Objective", "sphere", "rot_ellipsoid", "rot_rastrigin",
     "State", "new_descent", "sample", "rank_order", "covariance_update",
     "eigen_canonical", "generation", "StopOptions", "stop_bits", "ipop", "VARIANTS",
+    "krep_leaf_seed", "k_replicated",
     "STOP_TOLHISTFUN", "STOP_TOLFUN", "STOP_TOLX", "STOP_NOEFFECTAXIS",
     "STOP_NOEFFECTCOORD", "STOP_CONDITIONCOV", "STOP_FTARGET", "STOP_MAXGEN",
     "STOP_MAXEVALS", "STOP_NUMERIC",
@@ -532,3 +533,62 @@ def ipop(n, lam_start, sigma0, seed, objective, k_max=2 ** 9, box=(-4.0, 4.0),
         K *= 2
         restart += 1
     return best_f, best_x, log
+
+
+# ---------------------------------------------------------------------------
+# K-Replicated strategy (Alg. 3, Sec. 3.2.2) on one machine
+# ---------------------------------------------------------------------------
+
+_U64 = (1 << 64) - 1
+
+
+def krep_leaf_seed(seed: int, j: int) -> int:
+    """Seed of leaf j of the tree (reading: the run's seed mixed with the leaf
+    index by two odd 64-bit multipliers, so that leaves draw distinct
+    streams)."""
+    return (int(seed) * 0x9E3779B97F4A7C15 + j * 0xBF58476D1CE4E5B9 + 1) & _U64
+
+
+def k_replicated(n, lam_start, k_max, sigma0, seed, objective, so: StopOptions | None = None,
+                 box=(-4.0, 4.0), kappa=0, max_lockstep=100000):
+    """Alg. 3 with the processes replaced by lockstep generations: k_max leaf
+    descents with lam_start each start together; a generation steps every
+    running descent once; when both children of a tree node have stopped,
+    the node's descent starts with twice their population (it continues the
+    left child's stream at the next restart index, with the left child's
+    lambda doubled) and the children are done; the run ends when the root
+    stops or the best f of any descent falls below f_target.
+
+    Returns (best f, total evaluations, lockstep generations, per-node log)."""
+    so = so or StopOptions()
+    levels = int(round(math.log2(k_max)))
+    assert 1 << levels == k_max, "k_max must be a power of two"
+    # node (level l, index j) holds [state, finished, lam, seed, restart]
+    nodes = {}
+    for j in range(k_max):
+        s = krep_leaf_seed(seed, j)
+        nodes[(0, j)] = [new_descent(n, lam_start, sigma0, s, 0, box, kappa), False, lam_start, s, 0]
+    best, evals, gens, log = math.inf, 0, 0, []
+    while gens < max_lockstep:
+        running = [k for k, v in sorted(nodes.items()) if not v[1]]
+        for k in running:
+            st = nodes[k][0]
+            generation(st, objective, so=so)
+            evals += st.p.lam
+            best = min(best, st.f_best)
+            if st.stop:
+                nodes[k][1] = True
+                log.append({"node": k, "lam": st.p.lam, "gens": st.gen, "f_best": st.f_best, "stop": st.stop})
+        gens += 1
+        for l in range(1, levels + 1):
+            for j in range(k_max >> l):
+                a, b = (l - 1, 2 * j), (l - 1, 2 * j + 1)
+                if (l, j) in nodes or not (nodes.get(a, [None, False])[1] and nodes.get(b, [None, False])[1]):
+                    continue
+                _, _, lam_a, s_a, r_a = nodes[a]
+                nodes[(l, j)] = [new_descent(n, 2 * lam_a, sigma0, s_a, r_a + 1, box, kappa), False,
+                                 2 * lam_a, s_a, r_a + 1]
+        root = nodes.get((levels, 0))
+        if (root is not None and root[1]) or best < so.f_target:
+            break
+    return best, evals, gens, log
