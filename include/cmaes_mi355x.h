@@ -54,6 +54,21 @@ typedef enum {
   CMAES_MIXED_BF16X3 = 2 /* as MIXED, y = B D z as three bf16 split products   */
 } cmaes_precision_t;
 
+/* CMA-ES variants; the paper names the active and the large-scale ones as
+ * future work (Sec. 5):
+ *  STANDARD  - positive rank weights only (the default);
+ *  ACTIVE    - the covariance update also takes the worse half of the ranks
+ *              with negative weights (each scaled by n / ||C^{-1/2} y||^2);
+ *              mean and paths as STANDARD;
+ *  SEPARABLE - C kept diagonal (sep-CMA-ES, linear time and memory per
+ *              sample): y = D z elementwise, c1 and cmu times (n + 2) / 3,
+ *              no eigendecomposition (B = I, D = sqrt(diag C)). */
+typedef enum {
+  CMAES_VARIANT_STANDARD = 0,
+  CMAES_VARIANT_ACTIVE = 1,
+  CMAES_VARIANT_SEPARABLE = 2
+} cmaes_variant_t;
+
 typedef enum {
   CMAES_OBJ_NONE = 0,      /* no fused objective: host ask/tell only           */
   CMAES_OBJ_SPHERE = 1,    /* sum_i u_i^2                                      */
@@ -99,6 +114,10 @@ typedef struct {
   void* (*dev_malloc)(size_t bytes, void* alloc_ctx);
   void (*dev_free)(void* ptr, void* alloc_ctx);
   void* alloc_ctx;
+  /* cmaes_variant_t (default CMAES_VARIANT_STANDARD); changeable before the
+   * first generation only (CMAES_ESTATE otherwise). */
+  int32_t variant;
+  int32_t reserved_;      /* zero */
 } cmaes_options_t;
 
 /* Fill *opt with the defaults listed above.  Returns CMAES_EINVAL if opt is NULL. */

@@ -26,6 +26,7 @@ CMAES_ESTATE, CMAES_EKMAX, CMAES_ENUMERIC = -4, -5, -6
 CMAES_FP64, CMAES_MIXED, CMAES_MIXED_BF16X3 = 0, 1, 2
 OBJECTIVES = {"none": 0, "sphere": 1, "ellipsoid": 2, "rastrigin": 3}
 PRECISIONS = {"fp64": CMAES_FP64, "mixed": CMAES_MIXED, "mixed_bf16x3": CMAES_MIXED_BF16X3}
+VARIANTS = {"standard": 0, "active": 1, "separable": 2}
 STOP_BITS = ["tolhistfun", "tolfun", "tolx", "noeffectaxis", "noeffectcoord", "conditioncov",
              "ftarget", "maxgen", "maxevals", "numeric"]
 NUM_PHASES = 6
@@ -49,7 +50,7 @@ class CmaesOptions(C.Structure):
                 ("box_hi", C.c_double), ("f_target", C.c_double), ("tol_hist_fun", C.c_double),
                 ("tol_fun", C.c_double), ("tol_x_factor", C.c_double), ("max_condition", C.c_double),
                 ("stream", C.c_void_p), ("dev_malloc", DEV_MALLOC), ("dev_free", DEV_FREE),
-                ("alloc_ctx", C.c_void_p)]
+                ("alloc_ctx", C.c_void_p), ("variant", C.c_int32), ("reserved_", C.c_int32)]
 
 
 class TorchAllocator:
@@ -428,6 +429,8 @@ class CMAES:
         for k, v in options.items():
             if k == "stream":
                 v = C.c_void_p(v) if v else None
+            if k == "variant" and isinstance(v, str):
+                v = VARIANTS[v]
             setattr(opt, k, v)
         if allocator == "torch":
             import torch
@@ -594,6 +597,8 @@ class CMAESBatch:
         opt = cmaes_default_options()
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         for k, v in options.items():
+            if k == "variant" and isinstance(v, str):
+                v = VARIANTS[v]
             setattr(opt, k, v)
         cmaes_batch_set_options(self.b, opt)
 

@@ -40,14 +40,19 @@ std::atomic<uint64_t> g_epoch{1};
 struct HostParams {
   KParams kp;
   std::vector<double> w, sqrtw;
+  std::vector<double> w_all;  // all lam ranks: w, then 0 or the active negative weights
 };
 
-HostParams make_params(int n, int lam, int kappa_opt) {
+// variant (cmaes_variant_t): the active negative weights and the separable
+// rates follow the same readings as the oracle's variants
+HostParams make_params(int n, int lam, int kappa_opt, int variant = CMAES_VARIANT_STANDARD) {
   HostParams hp;
   KParams& k = hp.kp;
   k.n = n;
   k.lam = lam;
   k.mu = lam / 2;
+  k.variant = variant;
+  k.sumw = 1.0;
   hp.w.resize(k.mu);
   hp.sqrtw.resize(k.mu);
   double sw = 0.0;
@@ -68,8 +73,36 @@ HostParams make_params(int n, int lam, int kappa_opt) {
   k.c1 = 2.0 / ((n + 1.3) * (n + 1.3) + k.mueff);
   k.cmu = std::min(1.0 - k.c1, 2.0 * (k.mueff - 2.0 + 1.0 / k.mueff) / ((n + 2.0) * (n + 2.0) + k.mueff));
   k.chin = std::sqrt(static_cast<double>(n)) * (1.0 - 1.0 / (4.0 * n) + 1.0 / (21.0 * n * n));
+  hp.w_all.assign(lam, 0.0);
+  for (int i = 0; i < k.mu; ++i) hp.w_all[i] = hp.w[i];
+  if (variant == CMAES_VARIANT_SEPARABLE) {
+    k.c1 = std::min(1.0, k.c1 * (n + 2.0) / 3.0);
+    k.cmu = std::min(1.0 - k.c1, k.cmu * (n + 2.0) / 3.0);
+  }
+  if (variant == CMAES_VARIANT_ACTIVE && k.cmu > 0.0) {
+    // negative weights of the ranks beyond mu (an odd lam leaves rank mu+1 at 0)
+    double sneg = 0.0, sneg2 = 0.0;
+    std::vector<double> wn(lam - k.mu, 0.0);
+    for (int i = k.mu; i < lam; ++i) {
+      wn[i - k.mu] = std::min(0.0, std::log((lam + 1) / 2.0) - std::log(static_cast<double>(i + 1)));
+      sneg += wn[i - k.mu];
+      sneg2 += wn[i - k.mu] * wn[i - k.mu];
+    }
+    if (sneg < 0.0) {
+      const double mueff_neg = sneg * sneg / sneg2;
+      const double alpha = std::min({1.0 + k.c1 / k.cmu, 1.0 + 2.0 * mueff_neg / (k.mueff + 2.0),
+                                     (1.0 - k.c1 - k.cmu) / (n * k.cmu)});
+      double sum = 1.0;
+      for (int i = k.mu; i < lam; ++i) {
+        hp.w_all[i] = alpha * wn[i - k.mu] / -sneg;
+        sum += hp.w_all[i];
+      }
+      k.sumw = sum;
+    }
+  }
   k.kappa = kappa_opt > 0 ? kappa_opt
                           : std::max(1, static_cast<int>(std::ceil(1.0 / (10.0 * n * (k.c1 + k.cmu)))));
+  if (variant == CMAES_VARIANT_SEPARABLE) k.kappa = 1;
   return hp;
 }
 
@@ -133,10 +166,15 @@ struct cmaes {
   int32_t* rank_work = nullptr;  // partial rank counts
   // sampling-precision buffers
   void *BD = nullptr, *Rt = nullptr, *Z = nullptr, *Y = nullptr, *Ysel = nullptr, *coef = nullptr;
+  void* Ysig = nullptr;  // active: Ysel with the columns of negative weight negated
   void* partial = nullptr;
   void* syrk_work = nullptr;
   double* u = nullptr;
   EigWork ew{};
+  // small n: the eigensolve runs as a grouped solve of this one descent
+  // (convergence tested on the device, several short sweeps per host wait)
+  GroupEig ge1{};
+  uint64_t ge1_epoch = 0;
 };
 
 namespace {
@@ -181,6 +219,7 @@ void free_pop_buffers(cmaes* h) {
   dev_free(h, h->Z);
   dev_free(h, h->Y);
   dev_free(h, h->Ysel);
+  dev_free(h, h->Ysig);
   dev_free(h, h->partial);
   dev_free(h, h->part_yw);
   dev_free(h, h->part_zw);
@@ -245,6 +284,8 @@ void free_all(cmaes* h) {
   dev_free(h, h->ew.scale);
   dev_free(h, h->ew.status);
   dev_free(h, h->ew.gctl);
+  group_eig_release(h->ge1);
+  h->ge1_epoch = 0;
   if (h->ew.hflags) (void)hipHostFree(h->ew.hflags);
   h->ew.hflags = nullptr;
   h->ew.dflags = nullptr;
@@ -270,7 +311,10 @@ void refresh_stop_params(cmaes* h) {
 
 // population-size dependent buffers
 int alloc_pop(cmaes* h) {
-  const int n = h->n, ldn = h->ldn, lam = h->lam, mu = h->hp.kp.mu;
+  const int n = h->n, ldn = h->ldn, lam = h->lam;
+  // the rank-mu update runs over mu columns, or over all lam ranks (active)
+  const bool active = h->opt.variant == CMAES_VARIANT_ACTIVE;
+  const int mu = active ? lam : h->hp.kp.mu;
   if (lam <= h->cap_lam && mu <= h->cap_mu && hist_len_for(n, lam) <= h->hist_cap) return 0;
   drop_graphs(h);
   free_pop_buffers(h);
@@ -282,7 +326,7 @@ int alloc_pop(cmaes* h) {
       (rc = dev_alloc(h, &h->part_yw, 8ull * ceil_div(mu, 64) * n)) ||
       (rc = dev_alloc(h, &h->part_zw, 8ull * ceil_div(mu, 64) * n)) || (rc = dev_alloc(h, &h->f, 8ull * lam)) ||
       (rc = dev_alloc(h, &h->order, 4ull * lam)) || (rc = dev_alloc(h, &h->rank_work, 4ull * rank_work_elems(lam))) ||
-      (rc = dev_alloc(h, &h->w, 8ull * mu)) ||
+      (rc = dev_alloc(h, &h->w, 8ull * lam)) || (rc = dev_alloc(h, &h->Ysig, active ? e * ldn * lam : 16)) ||
       (rc = dev_alloc(h, &h->sqrtw, 8ull * mu)) || (rc = dev_alloc(h, &h->hist, 8ull * hist_len_for(n, lam))))
     return rc;
   {
@@ -344,7 +388,7 @@ int alloc_fixed(cmaes* h) {
 }
 
 int upload_params(cmaes* h) {
-  CMX_HIP(hipMemcpyAsync(h->w, h->hp.w.data(), 8 * h->hp.w.size(), hipMemcpyHostToDevice, h->st));
+  CMX_HIP(hipMemcpyAsync(h->w, h->hp.w_all.data(), 8 * h->hp.w_all.size(), hipMemcpyHostToDevice, h->st));
   CMX_HIP(hipMemcpyAsync(h->sqrtw, h->hp.sqrtw.data(), 8 * h->hp.sqrtw.size(), hipMemcpyHostToDevice, h->st));
   CMX_HIP(hipStreamSynchronize(h->st));
   return 0;
@@ -456,7 +500,9 @@ int phase_sample(cmaes* h, const double* Zhost) {
     kt_end(&h->kt);
   }
   kt_begin(&h->kt, KID_SAMPLE_GEMM);
-  if (h->opt.precision == CMAES_MIXED_BF16X3)
+  if (h->opt.variant == CMAES_VARIANT_SEPARABLE)
+    CMX_HIP(launch_sep_sample(h->st, h->fp64, n, lam, h->D, h->Z, ldn, h->Y, ldn));
+  else if (h->opt.precision == CMAES_MIXED_BF16X3)
     CMX_HIP(launch_sample_gemm_bf16x3(h->st, n, lam, static_cast<const float*>(h->BD), ldn,
                                       static_cast<const float*>(h->Z), ldn, static_cast<float*>(h->Y), ldn));
   else if (h->fp64)
@@ -510,17 +556,34 @@ int phase_update_pre(cmaes* h) {
   CMX_HIP(launch_matvec(h->st, n, h->B, ldn, h->zw, h->part_bz, &nchb));
   CMX_HIP(launch_vec_update(h->st, h->hp.kp, nchb, h->part_bz, h->yw, h->m, h->ps, h->pc, h->sc));
   rec(h, 4);
-  if (h->fp64) {
+  const int variant = h->opt.variant;
+  // the rank-mu operands: mu columns, or all lam ranks with signed copies (active)
+  int K = mu;
+  const void* Y2 = nullptr;
+  if (variant == CMAES_VARIANT_ACTIVE) {
+    CMX_HIP(launch_active_cols(h->st, h->fp64, n, lam, mu, h->Y, h->Z, ldn, h->order, h->w, h->Ysel, h->Ysig, ldn));
+    K = lam;
+    Y2 = h->Ysig;
+  }
+  if (variant == CMAES_VARIANT_SEPARABLE) {
+    CMX_HIP(launch_sep_cov(h->st, h->fp64, n, mu, h->Y, ldn, h->order, h->w, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->C,
+                           ldn, h->sc));
+  } else if (h->fp64) {
     kt_begin(&h->kt, KID_SYRK);
-    CMX_HIP(launch_syrk_update_f64(h->st, n, mu, static_cast<const double*>(h->Ysel), ldn, h->C, ldn, h->pc,
-                                   h->hp.kp.c1, h->hp.kp.cmu, h->sc, static_cast<double*>(h->syrk_work)));
+    CMX_HIP(launch_syrk_update_f64(h->st, n, K, static_cast<const double*>(h->Ysel), static_cast<const double*>(Y2),
+                                   ldn, h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc,
+                                   static_cast<double*>(h->syrk_work)));
     kt_end(&h->kt);
   } else {
-    CMX_HIP(g32_syrk(h->st, h->gcfg[G32_SYRK], n, mu, static_cast<const float*>(h->Ysel), ldn,
-                     static_cast<float*>(h->syrk_work), h->C, ldn, h->pc, h->hp.kp.c1, h->hp.kp.cmu, h->sc, false,
-                     &h->kt));
+    CMX_HIP(g32_syrk(h->st, h->gcfg[G32_SYRK], n, K, static_cast<const float*>(h->Ysel),
+                     static_cast<const float*>(Y2), ldn, static_cast<float*>(h->syrk_work), h->C, ldn, h->pc,
+                     h->hp.kp.c1, h->hp.kp.cmu, h->sc, false, &h->kt));
   }
   rec(h, 5);
+  if (variant == CMAES_VARIANT_SEPARABLE)  // D = sqrt(diag C) after every update, B = I
+    return launch_sep_eigen(h->st, h->fp64, n, h->C, ldn, h->D, h->BD, ldn, h->sc) == hipSuccess
+               ? 0
+               : fail(CMAES_EDEVICE, "separable decomposition launch failed");
   if (!h->eig_due) return 0;
   if (h->reorth_due) {
     // B drifts from orthogonality by the rounding of each eigensolve's
@@ -551,7 +614,7 @@ void set_due(cmaes* h) {
     h->reorth_sweeps += h->ew.sweeps;
     h->eig_uncounted = false;
   }
-  h->eig_due = due_next(h);
+  h->eig_due = due_next(h) && h->opt.variant != CMAES_VARIANT_SEPARABLE;
   h->reorth_due = h->eig_due && h->reorth_sweeps >= kReorthSweeps;
   if (h->reorth_due) h->reorth_sweeps = 0;
   if (h->eig_due) h->eig_uncounted = true;
@@ -618,13 +681,44 @@ int numeric_failure(const cmaes* h) {
   return fail(CMAES_ENUMERIC, "the eigendecomposition met non-finite values; the descent has stopped");
 }
 
+GEigDesc eig_desc(cmaes* h);
+
+// dimensions whose eigensolve runs as a grouped solve of one descent: a sweep
+// is one to three rounds there, so several are queued per host wait
+constexpr int kSmallEigenN = 64;
+
+// the eigensolve of the generation just queued, as a grouped solve of this
+// descent (no closing correction); *nonfinite when it met non-finite values
+int eigen_run_small(cmaes* h, bool* nonfinite) {
+  if (h->ge1_epoch != h->epoch || h->ge1.count != 1) {
+    if (int rc = group_eig_build(h->st, h->ge1, std::vector<GEigDesc>{eig_desc(h)})) return rc;
+    h->ge1_epoch = h->epoch;
+  }
+  GroupDueMask due{};
+  due.w[0] = 1u;
+  const int last = h->ew.last_sweeps;
+  int sweeps = 0, code = 1;
+  if (int rc = group_eig_solve(h->st, h->ge1, due, 40, last >= 2 ? last - 1 : 0, &sweeps, &code)) return rc;
+  h->ew.sweeps = sweeps;
+  h->ew.corrections = 0;
+  h->ew.last_sweeps = sweeps;
+  h->ew.last_closed = false;
+  h->ew.pending = false;
+  *nonfinite = code == 3;
+  return 0;
+}
+
 // the rest of a generation after its front: the eigensolve if due, then the
 // stop tests
 int finish_generation(cmaes* h) {
   bool nonfinite = false;
   if (h->eig_due) {
-    if (int rc = eigen_run(h)) return rc;
-    nonfinite = h->ew.hflags[1] != 0;
+    if (h->ew.N <= kSmallEigenN) {
+      if (int rc = eigen_run_small(h, &nonfinite)) return rc;
+    } else {
+      if (int rc = eigen_run(h)) return rc;
+      nonfinite = h->ew.hflags[1] != 0;
+    }
   }
   if (int rc = phase_update_post(h)) return rc;
   return nonfinite ? numeric_failure(h) : 0;
@@ -670,6 +764,7 @@ uint64_t front_key(const cmaes* h, bool due) {
   mix(reinterpret_cast<uintptr_t>(h->st));
   mix(static_cast<uint64_t>(h->obj_kind) | (h->have_R ? 16u : 0u) | (h->have_xstar ? 32u : 0u));
   mix(static_cast<uint64_t>(h->opt.precision));
+  mix(static_cast<uint64_t>(h->opt.variant) + 7);
   for (int i = 0; i < G32_NUM_SITES; ++i) mix(static_cast<uint64_t>(h->gcfg[i]));
   mix(due ? 1u : 0u);
   mix(h->reorth_due ? 1u : 0u);
@@ -828,15 +923,18 @@ int cmaes_set_options(cmaes_t* h, const cmaes_options_t* o) {
     return fail(CMAES_EINVAL, "unknown precision");
   if (o->k_max < 1 || !(o->box_hi > o->box_lo) || o->eigen_interval < 0 || o->max_gens < 0 || o->max_evals < 0)
     return fail(CMAES_EINVAL, "invalid option value");
+  if (o->variant < CMAES_VARIANT_STANDARD || o->variant > CMAES_VARIANT_SEPARABLE)
+    return fail(CMAES_EINVAL, "unknown variant");
   if ((o->dev_malloc == nullptr) != (o->dev_free == nullptr))
     return fail(CMAES_EINVAL, "dev_malloc and dev_free must both be set or both be NULL");
   if (h->allocated && (o->dev_malloc != h->alloc_fn || o->dev_free != h->free_fn || o->alloc_ctx != h->alloc_ctx))
     return fail(CMAES_ESTATE, "the allocator can only change before the handle's first allocation");
   const bool started = h->allocated && (h->gen > 0 || h->restart > 0);
   const bool prec_change = (o->precision == CMAES_FP64) != (h->opt.precision == CMAES_FP64);
-  if (started && (prec_change || o->stream != h->opt.stream))
-    return fail(CMAES_ESTATE, "precision and stream can only change before the first generation");
-  if (h->allocated && prec_change) free_all(h);  // re-created lazily in the new precision
+  const bool var_change = o->variant != h->opt.variant;
+  if (started && (prec_change || var_change || o->stream != h->opt.stream))
+    return fail(CMAES_ESTATE, "precision, variant and stream can only change before the first generation");
+  if (h->allocated && (prec_change || var_change)) free_all(h);  // re-created lazily
   const bool box_change = o->box_lo != h->opt.box_lo || o->box_hi != h->opt.box_hi;
   if (o->stream != h->opt.stream) {
     if (h->st) (void)hipStreamSynchronize(h->st);
@@ -851,7 +949,7 @@ int cmaes_set_options(cmaes_t* h, const cmaes_options_t* o) {
   }
   h->opt = *o;
   h->kt.st = h->st;
-  h->hp = make_params(h->n, h->lam, o->eigen_interval);
+  h->hp = make_params(h->n, h->lam, o->eigen_interval, o->variant);
   refresh_stop_params(h);
   if (h->allocated) {
     if (int rc = alloc_pop(h)) return rc;
@@ -1026,7 +1124,7 @@ int cmaes_restart_ipop(cmaes_t* h) {
   h->K *= 2;
   h->restart += 1;
   h->lam = h->K * h->lam0;
-  h->hp = make_params(h->n, h->lam, h->opt.eigen_interval);
+  h->hp = make_params(h->n, h->lam, h->opt.eigen_interval, h->opt.variant);
   if (int rc = alloc_pop(h)) return rc;
   if (int rc = upload_params(h)) return rc;
   return init_descent(h, false);
@@ -1264,7 +1362,8 @@ int cmaes_autotune(cmaes_t* h, int reps, double* us, int32_t* chosen) {
           if (site == G32_FITNESS)
             return g32_gemm(h->st, c, site, n, lam, n, static_cast<const float*>(h->Rt), ldn,
                             static_cast<const float*>(h->Y), ldn, h->partial, lam, &ga);
-          return g32_syrk(h->st, c, n, mu, static_cast<const float*>(h->Ysel), ldn, static_cast<float*>(h->syrk_work),
+          return g32_syrk(h->st, c, n, mu, static_cast<const float*>(h->Ysel), nullptr, ldn,
+                          static_cast<float*>(h->syrk_work),
                           cscratch, ldn, h->pc, 0.0, 0.0, h->sc, false, nullptr);
         };
         hipError_t e = launch();  // warm-up
@@ -1427,8 +1526,8 @@ int restart_same_lambda(cmaes* h) {
 // float32 sampling, a rotated fused objective, the same GEMM tiles, no timers
 bool front_groupable(const std::vector<cmaes*>& hs) {
   for (cmaes* h : hs) {
-    if (h->fp64 || h->opt.precision != CMAES_MIXED || !h->have_R || h->obj_kind == CMAES_OBJ_NONE || h->timing ||
-        h->kt.on)
+    if (h->fp64 || h->opt.precision != CMAES_MIXED || h->opt.variant != CMAES_VARIANT_STANDARD || !h->have_R ||
+        h->obj_kind == CMAES_OBJ_NONE || h->timing || h->kt.on)
       return false;
     for (int s = 0; s < G32_NUM_SITES; ++s)
       if (h->gcfg[s] != hs[0]->gcfg[s]) return false;
@@ -1494,8 +1593,6 @@ int build_front_tables(LockstepGroup& g, const std::vector<cmaes*>& hs) {
     e.f = h->f;
     e.rank_work = h->rank_work;
     e.order = h->order;
-    e.rank_span = rank_span_of(lam);
-    e.rank_splits = ceil_div(lam, e.rank_span);
     e.x_best = h->x_best;
     e.hist = h->hist;
     e.hist_len = h->sp.hist_len;
@@ -1541,8 +1638,9 @@ int build_front_tables(LockstepGroup& g, const std::vector<cmaes*>& hs) {
     wgs[GF_RVEC] = nb256;
     wgs[GF_FITNESS] = g32_tiles(ft.cfg[G32_FITNESS], n, lam);
     wgs[GF_FREDUCE] = ceil_div(lam, 256);
-    wgs[GF_RANK] = ceil_div(lam, 1024) * e.rank_splits;
-    wgs[GF_SCATTER] = ceil_div(lam, 256);
+    wgs[GF_RANK] = rank_chunks(lam);
+    wgs[GF_MERGE] = rank_merge_wgs(lam);
+    wgs[GF_SCATTER] = rank_chunks(lam);
     wgs[GF_BEST] = 1;
     wgs[GF_RECOMB] = nb256 * ceil_div(mu, 64);
     wgs[GF_REDYZ] = nb256;
@@ -1614,7 +1712,7 @@ int grouped_front(LockstepGroup& g, const std::vector<cmaes*>& hs, const GroupDu
     CMX_HIP(launch_group_update(st, k, tab, off(k), count, wgs(k), nullptr));
   CMX_HIP(launch_group_g32(st, ft.cfg[G32_FITNESS], G32_FITNESS, tab, off(GF_FITNESS), count, wgs(GF_FITNESS)));
   CMX_HIP(launch_group_fitness_reduce(st, tab, off(GF_FREDUCE), count, wgs(GF_FREDUCE)));
-  for (int k : {GF_RANK, GF_SCATTER, GF_BEST, GF_RECOMB, GF_REDYZ, GF_BMATVEC, GF_VECUPD})
+  for (int k : {GF_RANK, GF_MERGE, GF_SCATTER, GF_BEST, GF_RECOMB, GF_REDYZ, GF_BMATVEC, GF_VECUPD})
     CMX_HIP(launch_group_update(st, k, tab, off(k), count, wgs(k), nullptr));
   CMX_HIP(launch_group_syrk(st, ft.cfg[G32_SYRK], tab, off(GF_SYRK), wgs(GF_SYRK), off(GF_SYRKEPI), wgs(GF_SYRKEPI),
                             count));
@@ -1716,7 +1814,7 @@ int lockstep_generation(LockstepGroup& g, const std::vector<cmaes*>& hs) {
           CMX_HIP(hipStreamWaitEvent(g.st, g.ev[i], 0));
         }
     g.sweeps.assign(count, 0);
-    if (int rc = group_eig_solve(g.st, g.ge, due, 40, ahead, g.sweeps.data())) return rc;
+    if (int rc = group_eig_solve(g.st, g.ge, due, 40, ahead, g.sweeps.data(), nullptr)) return rc;
     if (!grouped) CMX_HIP(hipEventRecord(g.done, g.st));
     for (int i = 0; i < count; ++i)
       if (hs[i]->eig_due) {

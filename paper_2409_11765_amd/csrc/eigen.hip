@@ -241,9 +241,12 @@ __device__ __forceinline__ void inner_round(const double* S, double* Sn, double*
 // R1 on S (LDS, buffer S0; S1 is its double buffer): the rotations of one
 // outer round (optionally the 15 intra-block rounds, then the 16 cross
 // rounds), accumulated into Q (LDS) and written column-major to qout.  One
-// barrier per inner round.
+// barrier per inner round.  A block made of padding indices only (>= n) has
+// zero rows and columns in S, so every rotation that involves it is exactly
+// the identity (t = 0, c = 1, s = 0): with pad_j (block J is padding) the
+// cross rounds are skipped, with pad_i (both blocks) the intra rounds too.
 __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, double inv, bool with_intra,
-                            double* __restrict__ qout) {
+                            double* __restrict__ qout, bool pad_i = false, bool pad_j = false) {
   const int t = threadIdx.x;
   for (int idx = t; idx < kS * kS; idx += 256) Q[(idx % kS) * kLD + idx / kS] = (idx % kS == idx / kS) ? 1.0 : 0.0;
   // a row of 16 lanes shares y; x = (lane + y) mod 16, so lane 0 of the row
@@ -252,7 +255,7 @@ __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, doubl
   double* Sa = S0;
   double* Sb = S1;
   __syncthreads();
-  if (with_intra) {
+  if (with_intra && !pad_i) {
     for (int rr = 0; rr < kNB - 1; ++rr) {
       inner_round<true>(Sa, Sb, Q, thr, inv, rr, x, y);
       double* tmp = Sa;
@@ -268,7 +271,7 @@ __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, doubl
   double qa0 = Q[r0 * kLD + x], qa1 = Q[r1 * kLD + x];
   double qb0 = Q[r0 * kLD + kNB + x], qb1 = Q[r1 * kLD + kNB + x];
   double m00 = Sa[x * kLD + y], m10 = Sa[(kNB + x) * kLD + y];
-  for (int rr = 0; rr < kNB; ++rr) {
+  for (int rr = 0; rr < (pad_j ? 0 : kNB); ++rr) {
     inner_round_cross(Sa, Sb, thr, inv, rr, x, y, qa0, qa1, qb0, qb1, m00, m10);
     double* tmp = Sa;
     Sa = Sb;
@@ -281,7 +284,7 @@ __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, doubl
     __syncthreads();
   }
   {
-    const int b = kNB + ((x + kNB - 1) & (kNB - 1));
+    const int b = pad_j ? kNB + x : kNB + ((x + kNB - 1) & (kNB - 1));
     Q[r0 * kLD + x] = qa0;
     Q[r1 * kLD + x] = qa1;
     Q[r0 * kLD + b] = qb0;
@@ -294,7 +297,7 @@ __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, doubl
 
 // First pair solves of a descent's eigensolve: round 0 (with the intra-block
 // rotations) straight from A.
-__device__ __forceinline__ void jac_first_body(int P, const double* __restrict__ A, int N, int p,
+__device__ __forceinline__ void jac_first_body(int P, const double* __restrict__ A, int N, int n, int p,
                                                const double* __restrict__ scale, double* __restrict__ Qg,
                                                double* lds) {
   double* S0 = lds;
@@ -308,13 +311,14 @@ __device__ __forceinline__ void jac_first_body(int P, const double* __restrict__
   }
   __syncthreads();
   const double sc = *scale;
-  rotate_pair(S0, S1, Q, 2.2e-16 * sc, sc > 0.0 ? 1.0 / sc : 0.0, true, Qg + static_cast<int64_t>(P) * kS * kS);
+  rotate_pair(S0, S1, Q, 2.2e-16 * sc, sc > 0.0 ? 1.0 / sc : 0.0, true, Qg + static_cast<int64_t>(P) * kS * kS,
+              I * kNB >= n, J * kNB >= n);
 }
 
-__global__ void __launch_bounds__(256) k_jac_first(const double* __restrict__ A, int N, int p,
+__global__ void __launch_bounds__(256) k_jac_first(const double* __restrict__ A, int N, int n, int p,
                                                    const double* __restrict__ scale, double* __restrict__ Qg) {
   __shared__ double lds[3 * kS * kLD];
-  jac_first_body(blockIdx.x, A, N, p, scale, Qg, lds);
+  jac_first_body(blockIdx.x, A, N, n, p, scale, Qg, lds);
 }
 
 // One outer round r: workgroups [0, q) run the pair solves of the next round
@@ -339,7 +343,7 @@ constexpr int kRoundLds = 3 * kS * kLD + 3 * kS * kLU;  // doubles of LDS per wo
 
 __device__ __forceinline__ void jac_round_body(int b, const double* __restrict__ Acur, double* __restrict__ Anext,
                                                double* __restrict__ V, const double* __restrict__ Qcur,
-                                               double* __restrict__ Qnext, int N, int r,
+                                               double* __restrict__ Qnext, int N, int n, int r,
                                                const double* __restrict__ scale, double* __restrict__ tilepart,
                                                double* lds) {
   const int p = N / kNB, q = p / 2;
@@ -429,7 +433,7 @@ __device__ __forceinline__ void jac_round_body(int b, const double* __restrict__
     __builtin_amdgcn_s_setprio(2);  // the pair solves are the round's critical path
     const double sc = *scale;
     rotate_pair(S, Qa, Qb, 2.2e-16 * sc, sc > 0.0 ? 1.0 / sc : 0.0, wrap,
-                Qnext + static_cast<int64_t>(b) * kS * kS);
+                Qnext + static_cast<int64_t>(b) * kS * kS, In * kNB >= n, Jn * kNB >= n);
     return;
   }
   b -= q;
@@ -546,10 +550,10 @@ __device__ __forceinline__ void jac_round_body(int b, const double* __restrict__
 
 __global__ void __launch_bounds__(256) k_jac_round(const double* __restrict__ Acur, double* __restrict__ Anext,
                                                    double* __restrict__ V, const double* __restrict__ Qcur,
-                                                   double* __restrict__ Qnext, int N, int r,
+                                                   double* __restrict__ Qnext, int N, int n, int r,
                                                    const double* __restrict__ scale, double* __restrict__ tilepart) {
   __shared__ double lds[kRoundLds];
-  jac_round_body(blockIdx.x, Acur, Anext, V, Qcur, Qnext, N, r, scale, tilepart, lds);
+  jac_round_body(blockIdx.x, Acur, Anext, V, Qcur, Qnext, N, n, r, scale, tilepart, lds);
 }
 
 // off-diagonal / total squared norms and max |diagonal| of A, per column
@@ -986,7 +990,7 @@ __global__ void __launch_bounds__(256) kg_first(const GEigDesc* __restrict__ g, 
   const int i = group_find(off, count, blockIdx.x);
   const GEigDesc& e = g[i];
   if (!e.ctl[GC_DUE] || e.ctl[GC_STOPR] == 0) return;
-  jac_first_body(blockIdx.x - off[i], e.A, e.N, e.N / kNB, e.scale, e.Q, lds);
+  jac_first_body(blockIdx.x - off[i], e.A, e.N, e.n, e.N / kNB, e.scale, e.Q, lds);
 }
 
 // global round rg of the group: descent i runs its round rg mod (p_i - 1)
@@ -1008,7 +1012,7 @@ __global__ void __launch_bounds__(256) kg_round(const GEigDesc* __restrict__ g, 
   const int rl = rg % (p - 1), sw = rg / (p - 1);
   const bool odd = rg & 1;
   const int b = blockIdx.x - off[i];
-  jac_round_body(b, odd ? e.A2 : e.A, odd ? e.A : e.A2, e.V, odd ? e.Q2 : e.Q, odd ? e.Q : e.Q2, N, rl,
+  jac_round_body(b, odd ? e.A2 : e.A, odd ? e.A : e.A2, e.V, odd ? e.Q2 : e.Q, odd ? e.Q : e.Q2, N, e.n, rl,
                  e.scale + (sw & 1), e.part, lds);
   if (rl != p - 2 || b < q || b >= q + ntiles) return;
   // the end of sweep sw: the last tile workgroup to finish decides
@@ -1154,16 +1158,16 @@ int eigen_step(hipStream_t st, int n, double* B, int ldb, double* D, void* BD, b
     auto queue_sweep = [&](double* a0, double* a1, double* q0, double* q1, bool first) -> hipError_t {
       if (first) {
         kt_begin(kt, KID_JACOBI);
-        k_jac_first<<<q, 256, 0, st>>>(a0, N, p, w.scale, q0);
+        k_jac_first<<<q, 256, 0, st>>>(a0, N, n, p, w.scale, q0);
         kt_end(kt);
       }
       for (int r = 0; r < p - 1; ++r) {
         hipEvent_t t0, t1;
         if (kt_ext(kt, KID_JACOBI, &t0, &t1))
           hipExtLaunchKernelGGL(k_jac_round, dim3(round_blocks), dim3(256), 0, st, t0, t1, 0, a0, a1, w.V, q0, q1,
-                                N, r, w.scale, w.part);
+                                N, n, r, w.scale, w.part);
         else
-          k_jac_round<<<round_blocks, 256, 0, st>>>(a0, a1, w.V, q0, q1, N, r, w.scale, w.part);
+          k_jac_round<<<round_blocks, 256, 0, st>>>(a0, a1, w.V, q0, q1, N, n, r, w.scale, w.part);
         std::swap(a0, a1);
         std::swap(q0, q1);
       }

@@ -467,8 +467,8 @@ __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
 // tiles of an n x n result still fill the GPU: block (t, s) writes the partial
 // product of lower tile t over k-range s into its own slot of `work`.
 template <typename T>
-__global__ void __launch_bounds__(256) k_syrk_part(int n, int K, int kspan, const T* __restrict__ Y, int ldy,
-                                                   T* __restrict__ work, int ntl) {
+__global__ void __launch_bounds__(256) k_syrk_part(int n, int K, int kspan, const T* __restrict__ Y,
+                                                   const T* __restrict__ Y2, int ldy, T* __restrict__ work, int ntl) {
   using C = Cfg<T>;
   __shared__ T As[C::BK * (C::BM + C::PAD)];
   __shared__ T Bs[C::BK * (C::BN + C::PAD)];
@@ -478,8 +478,10 @@ __global__ void __launch_bounds__(256) k_syrk_part(int n, int K, int kspan, cons
   const int k0 = s * kspan, k1 = min(K, k0 + kspan);
   typename C::acc_t acc[2][2];
   const T* Yk = Y + static_cast<int64_t>(k0) * ldy;
-  // A = Yhat (n x K, rows contiguous), B = Yhat^T stored N x K -> TB
-  gemm_mainloop<T, false, true>(n, n, max(0, k1 - k0), Yk, ldy, Yk, ldy, tm * C::BM, tn * C::BN, As, Bs, acc);
+  const T* Yk2 = Y2 + static_cast<int64_t>(k0) * ldy;
+  // A = Yhat (n x K, rows contiguous), B = Yhat2^T stored N x K -> TB (Yhat2
+  // = Yhat, or its columns signed by the weights' signs)
+  gemm_mainloop<T, false, true>(n, n, max(0, k1 - k0), Yk, ldy, Yk2, ldy, tm * C::BM, tn * C::BN, As, Bs, acc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   T* out = work + (static_cast<int64_t>(s) * ntl + t) * (C::BM * C::BN);
@@ -774,12 +776,13 @@ hipError_t launch_sample_gemm_bf16x3(hipStream_t st, int n, int lam, const float
   return hipGetLastError();
 }
 
-hipError_t launch_syrk_update_f64(hipStream_t st, int n, int mu, const double* Ysel, int ldsel, double* C, int ldc,
-                                  const double* pc, double c1, double cmu, const DevScalars* sc, double* work) {
+hipError_t launch_syrk_update_f64(hipStream_t st, int n, int mu, const double* Ysel, const double* Ysel2, int ldsel,
+                                  double* C, int ldc, const double* pc, double c1, double cmu, const DevScalars* sc,
+                                  double* work) {
   int ntl, splits, kspan;
   size_t we;
   syrk_plan_f64(n, mu, &ntl, &splits, &kspan, &we);
-  k_syrk_part<double><<<ntl * splits, 256, 0, st>>>(n, mu, kspan, Ysel, ldsel, work, ntl);
+  k_syrk_part<double><<<ntl * splits, 256, 0, st>>>(n, mu, kspan, Ysel, Ysel2 ? Ysel2 : Ysel, ldsel, work, ntl);
   k_syrk_epi<double><<<ntl * 16, 256, 0, st>>>(n, ntl, splits, work, C, ldc, pc, c1, cmu, sc);
   return hipGetLastError();
 }

@@ -301,7 +301,8 @@ __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
 // workgroup covers twice the k-range per partial tile written.
 template <int BM, int BK, int NT>
 __device__ __forceinline__ void syrk32_body(int bid, int nwg, int n, int K, int kspan, const float* __restrict__ Y,
-                                            int ldy, float* __restrict__ work, int ntl, float* smem) {
+                                            const float* __restrict__ Y2, int ldy, float* __restrict__ work, int ntl,
+                                            float* smem) {
   using G = G32<BM, BM, BK, true, NT>;
   float* As = smem;
   float* Bs = smem + 2 * BK * G::LDA;
@@ -312,8 +313,9 @@ __device__ __forceinline__ void syrk32_body(int bid, int nwg, int n, int K, int 
   const int k0 = s * kspan, k1 = min(K, k0 + kspan);
   floatx16 acc[G::TMB][G::TMB];
   const float* Yk = Y + static_cast<int64_t>(k0) * ldy;
+  const float* Yk2 = Y2 + static_cast<int64_t>(k0) * ldy;
   G g;
-  g.mainloop(n, n, max(0, k1 - k0), Yk, ldy, Yk, ldy, tm * BM, tn * BM, As, Bs, acc);
+  g.mainloop(n, n, max(0, k1 - k0), Yk, ldy, Yk2, ldy, tm * BM, tn * BM, As, Bs, acc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if constexpr (G::KG == 2) {
     // k-group 1 hands its sums to k-group 0 (lane-contiguous, conflict free)
@@ -351,11 +353,12 @@ __device__ __forceinline__ void syrk32_body(int bid, int nwg, int n, int K, int 
 }
 
 template <int BM, int BK, int NT>
-__global__ void __launch_bounds__(NT) k_syrk32(int n, int K, int kspan, const float* __restrict__ Y, int ldy,
-                                               float* __restrict__ work, int ntl) {
+__global__ void __launch_bounds__(NT) k_syrk32(int n, int K, int kspan, const float* __restrict__ Y,
+                                               const float* __restrict__ Y2, int ldy, float* __restrict__ work,
+                                               int ntl) {
   using G = G32<BM, BM, BK, true, NT>;
   __shared__ float smem[2 * BK * G::LDA + 2 * BK * G::LDB];
-  syrk32_body<BM, BK, NT>(blockIdx.x, static_cast<int>(gridDim.x), n, K, kspan, Y, ldy, work, ntl, smem);
+  syrk32_body<BM, BK, NT>(blockIdx.x, static_cast<int>(gridDim.x), n, K, kspan, Y, Y2, ldy, work, ntl, smem);
 }
 
 template <int BM, int BK, int NT>
@@ -364,8 +367,8 @@ __global__ void __launch_bounds__(NT) kg_syrk32(const GFront* __restrict__ g, co
   __shared__ float smem[2 * BK * G::LDA + 2 * BK * G::LDB];
   const int i = group_find(off, count, blockIdx.x);
   const GFront& e = g[i];
-  syrk32_body<BM, BK, NT>(blockIdx.x - off[i], e.syrk_ntl * e.syrk_splits, e.n, e.mu, e.syrk_kspan, e.Ysel, e.ldn,
-                          e.syrk_work, e.syrk_ntl, smem);
+  syrk32_body<BM, BK, NT>(blockIdx.x - off[i], e.syrk_ntl * e.syrk_splits, e.n, e.mu, e.syrk_kspan, e.Ysel, e.Ysel,
+                          e.ldn, e.syrk_work, e.syrk_ntl, smem);
 }
 
 // C <- a C + c1 pc pc^T + cmu * sum_s partial_s, one workgroup per 32 x 32
@@ -495,14 +498,14 @@ hipError_t launch_cfg(hipStream_t st, int site, int M, int N, int K, const float
 }
 
 template <int BM, int BK, int NT>
-hipError_t launch_syrk_cfg(hipStream_t st, int cfg, int n, int K, const float* Y, int ldy, float* work, double* C,
-                           int ldc, const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only,
-                           KTimer* kt) {
+hipError_t launch_syrk_cfg(hipStream_t st, int cfg, int n, int K, const float* Y, const float* Y2, int ldy,
+                           float* work, double* C, int ldc, const double* pc, double c1, double cmu,
+                           const DevScalars* sc, bool partial_only, KTimer* kt) {
   int ntl, splits, kspan;
   size_t we;
   syrk32_plan(cfg, n, K, &ntl, &splits, &kspan, &we);
   kt_begin(kt, KID_SYRK);
-  k_syrk32<BM, BK, NT><<<ntl * splits, NT, 0, st>>>(n, K, kspan, Y, ldy, work, ntl);
+  k_syrk32<BM, BK, NT><<<ntl * splits, NT, 0, st>>>(n, K, kspan, Y, Y2 ? Y2 : Y, ldy, work, ntl);
   kt_end(kt);
   if (!partial_only) {
     const int nb = (n + 31) / 32;
@@ -608,13 +611,18 @@ hipError_t launch_group_syrk(hipStream_t st, int cfg, const GFront* g, const int
   }
 }
 
-hipError_t g32_syrk(hipStream_t st, int cfg, int n, int K, const float* Y, int ldy, float* work, double* C, int ldc,
-                    const double* pc, double c1, double cmu, const DevScalars* sc, bool partial_only, KTimer* kt) {
+hipError_t g32_syrk(hipStream_t st, int cfg, int n, int K, const float* Y, const float* Y2, int ldy, float* work,
+                    double* C, int ldc, const double* pc, double c1, double cmu, const DevScalars* sc,
+                    bool partial_only, KTimer* kt) {
   switch (cfg) {
-    case 0: return launch_syrk_cfg<128, 16, 256>(st, 0, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
-    case 4: return launch_syrk_cfg<128, 32, 512>(st, 4, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
-    case 5: return launch_syrk_cfg<64, 32, 256>(st, 5, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
-    case 6: return launch_syrk_cfg<64, 16, 256>(st, 6, n, K, Y, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
+    case 0:
+      return launch_syrk_cfg<128, 16, 256>(st, 0, n, K, Y, Y2, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
+    case 4:
+      return launch_syrk_cfg<128, 32, 512>(st, 4, n, K, Y, Y2, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
+    case 5:
+      return launch_syrk_cfg<64, 32, 256>(st, 5, n, K, Y, Y2, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
+    case 6:
+      return launch_syrk_cfg<64, 16, 256>(st, 6, n, K, Y, Y2, ldy, work, C, ldc, pc, c1, cmu, sc, partial_only, kt);
     default: return hipErrorInvalidValue;
   }
 }

@@ -127,7 +127,8 @@ hipError_t launch_fitness_reduce(hipStream_t st, bool fp64, int kind, int n, int
                                  const void* partial, int ld_partial, int row_tiles, double* f);
 
 // ranking
-// order[r] = index of rank r; work holds rank_work_elems(lam) int32 partial counts
+// order[r] = index of rank r (ascending f, ties by index, NaN last); work
+// holds rank_work_elems(lam) int32: the sorted chunks and partial counts
 hipError_t launch_rank(hipStream_t st, const double* f, int lam, int32_t* order, int32_t* work);
 size_t rank_work_elems(int lam);
 
@@ -311,7 +312,8 @@ __device__ __forceinline__ int group_find(const int* __restrict__ off, int count
 // mixed precision with a rotated fused objective, one launch per step for all
 // of them (workgroups split over the descents by prefix sums, kind by kind)
 enum GroupFrontKind {
-  GF_NORMALS = 0, GF_SAMPLE, GF_SUB, GF_RMATVEC, GF_RVEC, GF_FITNESS, GF_FREDUCE, GF_RANK, GF_SCATTER, GF_BEST,
+  GF_NORMALS = 0, GF_SAMPLE, GF_SUB, GF_RMATVEC, GF_RVEC, GF_FITNESS, GF_FREDUCE, GF_RANK, GF_MERGE, GF_SCATTER,
+  GF_BEST,
   GF_RECOMB, GF_REDYZ, GF_BMATVEC, GF_VECUPD, GF_SYRK, GF_SYRKEPI, GF_INIT, GF_OFFCOLS, GF_OFFFIN, GF_POLAR,
   GF_STOP, GF_KINDS
 };
@@ -339,7 +341,6 @@ struct GFront {  // one descent (device table entry)
   // ranking, best point
   int32_t* rank_work;
   int32_t* order;
-  int rank_span, rank_splits;
   double* x_best;
   double* hist;
   int hist_len;
@@ -396,7 +397,9 @@ hipError_t launch_group_eigen_begin(hipStream_t st, int kind, const GFront* g, c
 // syrk workgroups per descent (products, epilogue) for tile configuration cfg
 void syrk32_group_wgs(int cfg, int n, int K, int* wgs_products, int* wgs_epi);
 int g32_tiles(int cfg, int M, int N);
-int rank_span_of(int lam);
+// workgroups of the rank's chunk sort and scatter, and of its merge counts
+int rank_chunks(int lam);
+int rank_merge_wgs(int lam);
 
 // stop tests; the bits go to sc->stop and, when hstop is not null, to that
 // word of pinned, mapped host memory (device address)

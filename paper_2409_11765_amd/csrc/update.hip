@@ -15,69 +15,104 @@ namespace {
 
 __device__ __forceinline__ double rank_key(double v) { return v != v ? __builtin_inf() : v; }
 
-// Rank by counting: rank(i) = #{ j : f_j < f_i or (f_j == f_i and j < i) },
-// NaN counted as +inf.  Keys (f, index) are distinct, so the ranks form a
-// permutation and the result is the stable ascending order.  The j range is
-// split over blockIdx.y (span values each, staged through LDS kRankChunk at a
-// time); each thread counts for kRankPer candidates per value read and writes
-// its partial count to part[y][i] (summed by k_scatter_order; integers, so
-// the sum is order independent).
-constexpr int kRankChunk = 128, kRankPer = 4, kRankMaxSplits = 64;
-__device__ __forceinline__ void rank_count_body(int bx, int by, const double* __restrict__ f, int lam, int span,
-                                                int32_t* __restrict__ part) {
-  __shared__ double sf[kRankChunk];
-  int idx[kRankPer], cnt[kRankPer];
-  double fi[kRankPer];
-#pragma unroll
-  for (int r = 0; r < kRankPer; ++r) {
-    idx[r] = (bx * kRankPer + r) * 256 + threadIdx.x;
-    fi[r] = idx[r] < lam ? rank_key(f[idx[r]]) : 0.0;
-    cnt[r] = 0;
-  }
-  const int j1 = min(lam, (by + 1) * span);
-  for (int j0 = by * span; j0 < j1; j0 += kRankChunk) {
-    const int lim = min(kRankChunk, j1 - j0);
-    __syncthreads();
-    if (threadIdx.x < lim) sf[threadIdx.x] = rank_key(f[j0 + threadIdx.x]);
-    __syncthreads();
-    if (lim == kRankChunk) {
-#pragma unroll 8
-      for (int q = 0; q < kRankChunk; ++q) {
-        const double fj = sf[q];
-#pragma unroll
-        for (int r = 0; r < kRankPer; ++r) cnt[r] += (fj < fi[r]) || (fj == fi[r] && j0 + q < idx[r]);
-      }
-    } else {
-      for (int q = 0; q < lim; ++q) {
-        const double fj = sf[q];
-#pragma unroll
-        for (int r = 0; r < kRankPer; ++r) cnt[r] += (fj < fi[r]) || (fj == fi[r] && j0 + q < idx[r]);
+// ---- ranking by chunk sort and merge: the keys (f, index), NaN counted as
+// +inf, are cut into chunks of kSortChunk; each chunk is sorted by a bitonic
+// network in LDS (k_chunk_sort); the rank of a key is its position in its own
+// chunk plus, for every other chunk, the number of that chunk's keys below
+// it, found by binary search (k_merge_count, chunks taken kMergeGroup at a
+// time from LDS, one partial count per group); k_merge_scatter sums the
+// counts and writes order[rank] = index.  The keys are distinct, so the ranks
+// form the stable ascending permutation exactly; the counts are integers.
+constexpr int kSortChunk = 256, kMergeGroup = 8;
+
+__device__ __forceinline__ bool key_less(double ka, int ia, double kb, int ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+// the sorted chunks: keys in skey (double), indices in sidx; padding entries
+// (+inf, INT_MAX) sort after every real key
+__device__ __forceinline__ void chunk_sort_body(int c, const double* __restrict__ f, int lam,
+                                                double* __restrict__ skey, int* __restrict__ sidx) {
+  __shared__ double k[kSortChunk];
+  __shared__ int ix[kSortChunk];
+  const int t = threadIdx.x, i = c * kSortChunk + t;
+  k[t] = i < lam ? rank_key(f[i]) : __builtin_inf();
+  ix[t] = i < lam ? i : 0x7fffffff;
+  for (int size = 2; size <= kSortChunk; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      const int u = t ^ stride;
+      if (u > t) {
+        const bool up = (t & size) == 0;
+        const double ka = k[t], kb = k[u];
+        const int ia = ix[t], ib = ix[u];
+        if (key_less(kb, ib, ka, ia) == up) {
+          k[t] = kb;
+          ix[t] = ib;
+          k[u] = ka;
+          ix[u] = ia;
+        }
       }
     }
+  __syncthreads();
+  skey[i] = k[t];
+  sidx[i] = ix[t];
+}
+
+__global__ void __launch_bounds__(256) k_chunk_sort(const double* __restrict__ f, int lam, double* __restrict__ skey,
+                                                    int* __restrict__ sidx) {
+  chunk_sort_body(blockIdx.x, f, lam, skey, sidx);
+}
+
+// workgroup (c, g): the keys of chunk c counted against chunks
+// [g kMergeGroup, (g + 1) kMergeGroup) other than c
+__device__ __forceinline__ void merge_count_body(int c, int g, int nchunks, const double* __restrict__ skey,
+                                                 const int* __restrict__ sidx, int lam, int32_t* __restrict__ part) {
+  __shared__ double ok[kSortChunk];
+  __shared__ int oi[kSortChunk];
+  const int t = threadIdx.x;
+  const double kt = skey[c * kSortChunk + t];
+  const int it = sidx[c * kSortChunk + t];
+  int cnt = 0;
+  const int c1 = min(nchunks, (g + 1) * kMergeGroup);
+  for (int o = g * kMergeGroup; o < c1; ++o) {
+    if (o == c) continue;  // uniform over the workgroup
+    __syncthreads();
+    ok[t] = skey[o * kSortChunk + t];
+    oi[t] = sidx[o * kSortChunk + t];
+    __syncthreads();
+    int lo = 0, hi = kSortChunk;  // the first entry not below (kt, it)
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (key_less(ok[mid], oi[mid], kt, it))
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    cnt += lo;
   }
-#pragma unroll
-  for (int r = 0; r < kRankPer; ++r)
-    if (idx[r] < lam) part[static_cast<int64_t>(by) * lam + idx[r]] = cnt[r];
+  if (it < lam) part[static_cast<int64_t>(g) * lam + it] = cnt;
 }
 
-__global__ void __launch_bounds__(256) k_rank_count(const double* __restrict__ f, int lam, int span,
-                                                    int32_t* __restrict__ part) {
-  rank_count_body(blockIdx.x, blockIdx.y, f, lam, span, part);
+__global__ void __launch_bounds__(256) k_merge_count(int nchunks, const double* __restrict__ skey,
+                                                     const int* __restrict__ sidx, int lam,
+                                                     int32_t* __restrict__ part) {
+  merge_count_body(blockIdx.x, blockIdx.y, nchunks, skey, sidx, lam, part);
 }
 
-__device__ __forceinline__ void scatter_order_body(int bx, const int32_t* __restrict__ part, int splits, int lam,
-                                                   int32_t* __restrict__ order) {
-  const int i = bx * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void merge_scatter_body(int c, int ngroups, const int* __restrict__ sidx, int lam,
+                                                   const int32_t* __restrict__ part, int32_t* __restrict__ order) {
+  const int t = threadIdx.x;
+  const int i = sidx[c * kSortChunk + t];
   if (i >= lam) return;
-  int rank = 0;
-#pragma unroll 16
-  for (int y = 0; y < splits; ++y) rank += part[static_cast<int64_t>(y) * lam + i];
+  int rank = t;
+  for (int g = 0; g < ngroups; ++g) rank += part[static_cast<int64_t>(g) * lam + i];
   order[rank] = i;
 }
 
-__global__ void k_scatter_order(const int32_t* __restrict__ part, int splits, int lam,
-                                int32_t* __restrict__ order) {
-  scatter_order_body(blockIdx.x, part, splits, lam, order);
+__global__ void __launch_bounds__(256) k_merge_scatter(int ngroups, const int* __restrict__ sidx, int lam,
+                                                       const int32_t* __restrict__ part, int32_t* __restrict__ order) {
+  merge_scatter_body(blockIdx.x, ngroups, sidx, lam, part, order);
 }
 
 // y_w = sum_{r<mu} w_r y_{order[r]}, z_w likewise (float64 accumulation), and
@@ -199,7 +234,7 @@ __device__ __forceinline__ void vec_update_body(const KParams& kp, int nchunks, 
   if (threadIdx.x == 0) {
     sc->ps_norm = nps;
     sc->hsig = hsig;
-    sc->c_coef = 1.0 - kp.c1 - kp.cmu + (1.0 - hsig) * kp.c1 * kp.cc * (2.0 - kp.cc);
+    sc->c_coef = 1.0 - kp.c1 - kp.cmu * kp.sumw + (1.0 - hsig) * kp.c1 * kp.cc * (2.0 - kp.cc);
     sc->sigma = sigma * exp((kp.cs / kp.ds) * (nps / kp.chin - 1.0));
     sc->gen = g + 1;
     sc->evals += kp.lam;
@@ -381,18 +416,37 @@ __global__ void k_convert(const double* __restrict__ s, int lds, T* __restrict__
 
 }  // namespace
 
-// j values per split: chunks of kRankChunk, at most kRankMaxSplits splits
-int rank_span(int lam) { return round_up(ceil_div(lam, kRankMaxSplits), kRankChunk); }
+
+// the rank work area (int32 elements): sorted keys (double, 2 words each),
+// their indices, then the per-group counts
+struct RankWork {
+  double* skey;
+  int* sidx;
+  int32_t* part;
+  int nchunks, ngroups;
+};
+__host__ __device__ inline RankWork rank_work_of(int32_t* work, int lam) {
+  RankWork w;
+  w.nchunks = (lam + kSortChunk - 1) / kSortChunk;
+  w.ngroups = (w.nchunks + kMergeGroup - 1) / kMergeGroup;
+  w.skey = reinterpret_cast<double*>(work);
+  w.sidx = work + 2 * w.nchunks * kSortChunk;
+  w.part = w.sidx + w.nchunks * kSortChunk;
+  return w;
+}
 
 hipError_t launch_rank(hipStream_t st, const double* f, int lam, int32_t* order, int32_t* work) {
-  const int span = rank_span(lam), splits = ceil_div(lam, span);
-  dim3 grid(ceil_div(lam, 256 * kRankPer), splits);
-  k_rank_count<<<grid, 256, 0, st>>>(f, lam, span, work);
-  k_scatter_order<<<ceil_div(lam, 256), 256, 0, st>>>(work, splits, lam, order);
+  const RankWork w = rank_work_of(work, lam);
+  k_chunk_sort<<<w.nchunks, 256, 0, st>>>(f, lam, w.skey, w.sidx);
+  if (w.nchunks > 1) k_merge_count<<<dim3(w.nchunks, w.ngroups), 256, 0, st>>>(w.nchunks, w.skey, w.sidx, lam, w.part);
+  k_merge_scatter<<<w.nchunks, 256, 0, st>>>(w.nchunks > 1 ? w.ngroups : 0, w.sidx, lam, w.part, order);
   return hipGetLastError();
 }
 
-size_t rank_work_elems(int lam) { return static_cast<size_t>(ceil_div(lam, rank_span(lam))) * lam; }
+size_t rank_work_elems(int lam) {
+  const size_t nchunks = ceil_div(lam, kSortChunk), ngroups = ceil_div(static_cast<int>(nchunks), kMergeGroup);
+  return 3 * nchunks * kSortChunk + ngroups * static_cast<size_t>(lam) + 2;
+}
 
 hipError_t launch_recombine(hipStream_t st, bool fp64, int n, int lam, int mu, const void* Y, const void* Z,
                             int ld, const int32_t* order, const double* w, const double* sqrtw, void* Ysel,
@@ -478,6 +532,96 @@ __global__ void k_polar_step(int n, double* __restrict__ B, int ldb, const doubl
   polar_body(blockIdx.x, n, B, ldb, T, ldt);
 }
 
+// ---- variants
+
+// active covariance update: one workgroup per rank r; ranks beyond mu get the
+// negative weight scaled by n / ||C^{-1/2} y||^2 = n / ||z||^2 (y = B D z with
+// orthonormal B), the norm summed in float64 in a fixed order
+template <typename T>
+__global__ void __launch_bounds__(256) k_active_cols(int n, int mu, const T* __restrict__ Y, const T* __restrict__ Z,
+                                                     int ld, const int32_t* __restrict__ order,
+                                                     const double* __restrict__ w_all, T* __restrict__ Ysel,
+                                                     T* __restrict__ Ysig, int ldsel) {
+  __shared__ double red[256];
+  const int r = blockIdx.x;
+  T* ys = Ysel + static_cast<int64_t>(r) * ldsel;
+  T* yg = Ysig + static_cast<int64_t>(r) * ldsel;
+  if (r < mu) {  // the positive columns, as the recombination wrote them
+    for (int i = threadIdx.x; i < n; i += 256) yg[i] = ys[i];
+    return;
+  }
+  const int64_t c = static_cast<int64_t>(order[r]) * ld;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double z = static_cast<double>(Z[c + i]);
+    acc += z * z;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double wr = w_all[r], z2 = red[0];
+  const double sc = (wr < 0.0 && z2 > 0.0) ? sqrt(-wr * n / z2) : 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double v = sc * static_cast<double>(Y[c + i]);
+    ys[i] = static_cast<T>(v);
+    yg[i] = static_cast<T>(-v);
+  }
+}
+
+// separable sampling: y = D z
+template <typename T>
+__global__ void __launch_bounds__(256) k_sep_sample(int n, int lam, const double* __restrict__ D,
+                                                    const T* __restrict__ Z, int ldz, T* __restrict__ Y, int ldy) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * lam) return;
+  const int k = static_cast<int>(idx / n), i = static_cast<int>(idx % n);
+  Y[static_cast<int64_t>(k) * ldy + i] = static_cast<T>(D[i] * static_cast<double>(Z[static_cast<int64_t>(k) * ldz + i]));
+}
+
+// separable covariance update: the diagonal of the rank-one plus rank-mu update
+template <typename T>
+__global__ void __launch_bounds__(256) k_sep_cov(int n, int mu, const T* __restrict__ Y, int ldy,
+                                                 const int32_t* __restrict__ order, const double* __restrict__ w,
+                                                 const double* __restrict__ pc, double c1, double cmu,
+                                                 double* __restrict__ C, int ldc, const DevScalars* __restrict__ sc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int r = 0; r < mu; ++r) {
+    const double y = static_cast<double>(Y[static_cast<int64_t>(order[r]) * ldy + i]);
+    acc += w[r] * y * y;
+  }
+  double& cii = C[static_cast<int64_t>(i) * ldc + i];
+  cii = sc->c_coef * cii + c1 * pc[i] * pc[i] + cmu * acc;
+}
+
+// separable "decomposition": D = sqrt(diag C), B D = diag(D); eig_ok when the
+// diagonal is positive (a one-workgroup kernel)
+template <typename T>
+__global__ void __launch_bounds__(256) k_sep_eigen(int n, const double* __restrict__ C, int ldc,
+                                                   double* __restrict__ D, T* __restrict__ BD, int ldbd,
+                                                   DevScalars* __restrict__ sc) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double cii = C[static_cast<int64_t>(i) * ldc + i];
+    if (!(cii > 0.0)) atomicOr(&bad, 1);
+    const double d = sqrt(fmax(cii, 0.0));
+    D[i] = d;
+    BD[static_cast<int64_t>(i) * ldbd + i] = static_cast<T>(d);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sc->eig_ok = bad ? 0 : 1;
+    sc->jac_sweeps = 0;
+    sc->jac_corr = 0;
+  }
+}
+
 // ---- the update steps of a grouped front (one launch per step for all
 // descents; workgroup w of descent i is local block w - off[i], split into
 // (bx, by) by the descent's own grid width)
@@ -492,11 +636,20 @@ __global__ void __launch_bounds__(256) kg_update256(int kind, const GFront* __re
     case GF_RMATVEC: matvec_body(w % gx, w / gx, e.n, e.Rd, e.ldn, e.u, e.part_bz); break;
     case GF_RVEC: reduce_vec_body(w, e.n, (e.n + 63) / 64, e.part_bz, e.d); break;
     case GF_RANK: {
-      const int rx = (e.lam + 256 * kRankPer - 1) / (256 * kRankPer);
-      rank_count_body(w % rx, w / rx, e.f, e.lam, e.rank_span, e.rank_work);
+      const RankWork rw = rank_work_of(e.rank_work, e.lam);
+      chunk_sort_body(w, e.f, e.lam, rw.skey, rw.sidx);
       break;
     }
-    case GF_SCATTER: scatter_order_body(w, e.rank_work, e.rank_splits, e.lam, e.order); break;
+    case GF_MERGE: {
+      const RankWork rw = rank_work_of(e.rank_work, e.lam);
+      merge_count_body(w % rw.nchunks, w / rw.nchunks, rw.nchunks, rw.skey, rw.sidx, e.lam, rw.part);
+      break;
+    }
+    case GF_SCATTER: {
+      const RankWork rw = rank_work_of(e.rank_work, e.lam);
+      merge_scatter_body(w, rw.nchunks > 1 ? rw.ngroups : 0, rw.sidx, e.lam, rw.part, e.order);
+      break;
+    }
     case GF_BEST: best_body<float>(e.n, e.lam, e.f, e.order, e.Y, e.ldn, e.m, e.x_best, e.hist, e.hist_len, e.sc); break;
     case GF_RECOMB:
       recombine_body<float>(w % gx, w / gx, e.n, e.mu, e.Y, e.Z, e.ldn, e.order, e.w, e.sqrtw, e.Ysel, e.ldn,
@@ -532,7 +685,58 @@ hipError_t launch_group_update(hipStream_t st, int kind, const GFront* g, const 
   return hipGetLastError();
 }
 
-int rank_span_of(int lam) { return rank_span(lam); }
+int rank_chunks(int lam) { return ceil_div(lam, kSortChunk); }
+int rank_merge_wgs(int lam) {
+  const int nch = ceil_div(lam, kSortChunk);
+  return nch > 1 ? nch * ceil_div(nch, kMergeGroup) : 0;
+}
+
+hipError_t launch_active_cols(hipStream_t st, bool fp64, int n, int lam, int mu, const void* Y, const void* Z, int ld,
+                              const int32_t* order, const double* w_all, void* Ysel, void* Ysig, int ldsel) {
+  if (fp64)
+    k_active_cols<double><<<lam, 256, 0, st>>>(n, mu, static_cast<const double*>(Y), static_cast<const double*>(Z), ld,
+                                               order, w_all, static_cast<double*>(Ysel), static_cast<double*>(Ysig),
+                                               ldsel);
+  else
+    k_active_cols<float><<<lam, 256, 0, st>>>(n, mu, static_cast<const float*>(Y), static_cast<const float*>(Z), ld,
+                                              order, w_all, static_cast<float*>(Ysel), static_cast<float*>(Ysig),
+                                              ldsel);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_sample(hipStream_t st, bool fp64, int n, int lam, const double* D, const void* Z, int ldz,
+                             void* Y, int ldy) {
+  const int64_t total = static_cast<int64_t>(n) * lam;
+  const int blocks = static_cast<int>((total + 255) / 256);
+  if (fp64)
+    k_sep_sample<double><<<blocks, 256, 0, st>>>(n, lam, D, static_cast<const double*>(Z), ldz,
+                                                 static_cast<double*>(Y), ldy);
+  else
+    k_sep_sample<float><<<blocks, 256, 0, st>>>(n, lam, D, static_cast<const float*>(Z), ldz, static_cast<float*>(Y),
+                                                ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_cov(hipStream_t st, bool fp64, int n, int mu, const void* Y, int ldy, const int32_t* order,
+                          const double* w, const double* pc, double c1, double cmu, double* C, int ldc,
+                          const DevScalars* sc) {
+  if (fp64)
+    k_sep_cov<double><<<ceil_div(n, 256), 256, 0, st>>>(n, mu, static_cast<const double*>(Y), ldy, order, w, pc, c1,
+                                                        cmu, C, ldc, sc);
+  else
+    k_sep_cov<float><<<ceil_div(n, 256), 256, 0, st>>>(n, mu, static_cast<const float*>(Y), ldy, order, w, pc, c1,
+                                                       cmu, C, ldc, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_eigen(hipStream_t st, bool fp64, int n, const double* C, int ldc, double* D, void* BD, int ldbd,
+                            DevScalars* sc) {
+  if (fp64)
+    k_sep_eigen<double><<<1, 256, 0, st>>>(n, C, ldc, D, static_cast<double*>(BD), ldbd, sc);
+  else
+    k_sep_eigen<float><<<1, 256, 0, st>>>(n, C, ldc, D, static_cast<float*>(BD), ldbd, sc);
+  return hipGetLastError();
+}
 
 hipError_t launch_polar_step(hipStream_t st, int n, double* B, int ldb, const double* T, int ldt) {
   const int64_t total = static_cast<int64_t>(n) * n;

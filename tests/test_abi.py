@@ -39,9 +39,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     import paper_2409_11765_amd.binding as B
-    # int32 x4, int64, double x7, stream pointer, two function pointers and
-    # the allocator context -> 112 bytes on x86-64
-    assert ctypes.sizeof(B.CmaesOptions) == 4 * 4 + 8 + 8 * 7 + 8 + 3 * 8
+    # int32 x4, int64, double x7, stream pointer, two function pointers, the
+    # allocator context and two int32 (variant) -> 120 bytes on x86-64
+    assert ctypes.sizeof(B.CmaesOptions) == 4 * 4 + 8 + 8 * 7 + 8 + 3 * 8 + 8
     assert B.CmaesOptions.dev_malloc.offset == 88 and B.CmaesOptions.alloc_ctx.offset == 104
     assert B.CmaesState.m.offset == 4 * 4 + 8 * 3 + 8 * 2 + 4 + 4 + 4 + 4
 
@@ -115,8 +115,9 @@ def test_ctypes_layouts_equal_the_c_compilers(tmp_path):
 #include <stdio.h>
 #include "cmaes_mi355x.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cmaes_options_t), offsetof(cmaes_options_t, stream),
-         offsetof(cmaes_options_t, dev_malloc), offsetof(cmaes_options_t, alloc_ctx), sizeof(cmaes_state_t),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cmaes_options_t), offsetof(cmaes_options_t, stream),
+         offsetof(cmaes_options_t, dev_malloc), offsetof(cmaes_options_t, alloc_ctx),
+         offsetof(cmaes_options_t, variant), sizeof(cmaes_state_t),
          offsetof(cmaes_state_t, m), offsetof(cmaes_state_t, order), sizeof(cmaes_krep_status_t));
   return 0;
 }
@@ -125,6 +126,7 @@ int main(void) {
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(B.CmaesOptions), B.CmaesOptions.stream.offset, B.CmaesOptions.dev_malloc.offset,
-            B.CmaesOptions.alloc_ctx.offset, ctypes.sizeof(B.CmaesState), B.CmaesState.m.offset,
+            B.CmaesOptions.alloc_ctx.offset, B.CmaesOptions.variant.offset, ctypes.sizeof(B.CmaesState),
+            B.CmaesState.m.offset,
             B.CmaesState.order.offset, ctypes.sizeof(B.KrepStatus)]
     assert got == want

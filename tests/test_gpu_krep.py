@@ -67,3 +67,26 @@ def test_reaches_target_on_sphere(P, precision):
         r.run(3000)
         st = r.status()
     assert st["done"] == 1 and st["f_best"] < 1e-8, st
+
+
+def test_matches_the_oracles_k_replicated(P):
+    """The device tree against the oracle's Alg. 3 on the same seeds: both
+    reach the target on every seed and the median evaluation counts agree
+    within 15% (single runs separate once an eigendecomposition meets a
+    repeated eigenvalue; 10 seeds)."""
+    import oracle as O
+    n, lam0, kmax = 10, 6, 4
+    gpu, ora = [], []
+    for seed in range(1, 11):
+        xs = synth.optimum(n, seed)
+        with P.KReplicated(n, lam0, kmax, 2.0, seed=seed, precision="fp64", objective="sphere", xstar=xs) as r:
+            r.run(5000)
+            st = r.status()
+        assert st["done"] == 1 and st["f_best"] < 1e-8, (seed, st)
+        gpu.append(st["total_evals"])
+        best, evals, _, _ = O.k_replicated(n, lam0, kmax, 2.0, seed, O.Objective("sphere", None, xs))
+        assert best < 1e-8
+        ora.append(evals)
+    mg, mo = float(np.median(gpu)), float(np.median(ora))
+    print(f"k-replicated median evals gpu {mg} oracle {mo}", flush=True)
+    assert abs(mg - mo) <= 0.15 * mo

@@ -1,9 +1,9 @@
 """Ranking (Alg. 1: the candidates sorted by fitness, rk(i) in Sec. 2.1)
 through the C ABI's ask/tell path: the device permutation must equal, index
 for index, the stable ascending order of the told values with NaN ranked as
-+inf and -0 tied with +0.  The sizes cover one split of the counting rank,
-ragged splits and candidate blocks, and the growth of the split span beyond
-64 splits (lambda > 8192)."""
++inf and -0 tied with +0.  The sizes cover a single sorted chunk of 256
+keys (no merge), ragged last chunks, one and several merge groups of 8
+chunks, and lambda = 20011 (79 chunks, 10 groups)."""
 
 import numpy as np
 import pytest
