@@ -49,31 +49,36 @@ struct G32 {
   static_assert(BK % (2 * KG) == 0, "k-tile must split evenly over the k-groups");
   float4 ra[A_V4], rb[B_V4];
 
-  __device__ static float4 ld4(const float* __restrict__ P, int64_t off, bool full, int lim) {
-    if (full) return *reinterpret_cast<const float4*>(P + off);
-    float v[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) v[c] = c < lim ? P[off + c] : 0.0f;
-    return make_float4(v[0], v[1], v[2], v[3]);
+  // Operand loads are branch free.  Every operand is stored with a leading
+  // dimension that is a multiple of 4 and at least its row count rounded up
+  // to 4, so a float4 that starts inside a column stays inside it.  Rows past
+  // the tile's edge (m >= M, n >= N) are clamped into the last float4 of the
+  // column: they load values that only reach output rows / columns past the
+  // edge, which no epilogue stores.  Entries past the reduction length K are
+  // read from a clamped address and replaced by zero when they are staged in
+  // LDS, so the loads of the next k-tile stay in flight over the current
+  // tile's MFMAs.
+  __device__ static float4 zero_unless(float4 v, bool ok) {
+    return make_float4(ok ? v.x : 0.0f, ok ? v.y : 0.0f, ok ? v.z : 0.0f, ok ? v.w : 0.0f);
   }
 
   // A: M x K column-major (m contiguous)
-  __device__ void load_a(const float* __restrict__ A, int lda, int M, int K, int m0, int k0) {
+  __device__ void load_a(const float* __restrict__ A, int lda, int K, int m0, int k0) {
     constexpr int PER_COL = BM / 4;
 #pragma unroll
     for (int p = 0; p < A_V4; ++p) {
       const int q = p * NT + threadIdx.x;
-      const int m = m0 + (q % PER_COL) * 4, k = k0 + q / PER_COL;
-      const bool ok = k < K;
-      ra[p] = ld4(A, static_cast<int64_t>(k) * lda + m, ok && m + 4 <= M, ok ? M - m : 0);
+      const int m = min(m0 + (q % PER_COL) * 4, lda - 4), k = k0 + q / PER_COL;
+      ra[p] = *reinterpret_cast<const float4*>(A + static_cast<int64_t>(min(k, K - 1)) * lda + m);
     }
   }
-  __device__ void store_a(float* S) const {
+  __device__ void store_a(float* S, int K, int k0) const {
     constexpr int PER_COL = BM / 4;
 #pragma unroll
     for (int p = 0; p < A_V4; ++p) {
       const int q = p * NT + threadIdx.x;
-      *reinterpret_cast<float4*>(&S[(q / PER_COL) * LDA + (q % PER_COL) * 4]) = ra[p];
+      *reinterpret_cast<float4*>(&S[(q / PER_COL) * LDA + (q % PER_COL) * 4]) =
+          zero_unless(ra[p], k0 + q / PER_COL < K);
     }
   }
   // B: K x N column-major (k contiguous) when !TB, else element (k, n) at B[n + k ldb]
@@ -83,39 +88,44 @@ struct G32 {
       const int q = p * NT + threadIdx.x;
       if constexpr (!TB) {
         constexpr int PER_ROW = BK / 4;
-        const int k = k0 + (q % PER_ROW) * 4, n = n0 + q / PER_ROW;
-        const bool ok = n < N;
-        rb[p] = ld4(B, static_cast<int64_t>(n) * ldb + k, ok && k + 4 <= K, ok ? K - k : 0);
+        const int k = k0 + (q % PER_ROW) * 4, n = min(n0 + q / PER_ROW, N - 1);
+        rb[p] = *reinterpret_cast<const float4*>(B + static_cast<int64_t>(n) * ldb + min(k, ldb - 4));
       } else {
         constexpr int PER_COL = BN / 4;
-        const int n = n0 + (q % PER_COL) * 4, k = k0 + q / PER_COL;
-        const bool ok = k < K;
-        rb[p] = ld4(B, static_cast<int64_t>(k) * ldb + n, ok && n + 4 <= N, ok ? N - n : 0);
+        const int n = min(n0 + (q % PER_COL) * 4, ldb - 4), k = k0 + q / PER_COL;
+        rb[p] = *reinterpret_cast<const float4*>(B + static_cast<int64_t>(min(k, K - 1)) * ldb + n);
       }
     }
   }
-  __device__ void store_b(float* S) const {
+  __device__ void store_b(float* S, int K, int k0) const {
 #pragma unroll
     for (int p = 0; p < B_V4; ++p) {
       const int q = p * NT + threadIdx.x;
       if constexpr (!TB) {
         constexpr int PER_ROW = BK / 4;
-        const int k = (q % PER_ROW) * 4, n = q / PER_ROW;
-        S[(k + 0) * LDB + n] = rb[p].x;
-        S[(k + 1) * LDB + n] = rb[p].y;
-        S[(k + 2) * LDB + n] = rb[p].z;
-        S[(k + 3) * LDB + n] = rb[p].w;
+        const int k = (q % PER_ROW) * 4, n = q / PER_ROW, kk = k0 + k;
+        S[(k + 0) * LDB + n] = kk < K ? rb[p].x : 0.0f;
+        S[(k + 1) * LDB + n] = kk + 1 < K ? rb[p].y : 0.0f;
+        S[(k + 2) * LDB + n] = kk + 2 < K ? rb[p].z : 0.0f;
+        S[(k + 3) * LDB + n] = kk + 3 < K ? rb[p].w : 0.0f;
       } else {
         constexpr int PER_COL = BN / 4;
-        *reinterpret_cast<float4*>(&S[(q / PER_COL) * LDB + (q % PER_COL) * 4]) = rb[p];
+        *reinterpret_cast<float4*>(&S[(q / PER_COL) * LDB + (q % PER_COL) * 4]) =
+            zero_unless(rb[p], k0 + q / PER_COL < K);
       }
     }
   }
 
+  // 32x32 block (i, j) of this wave lies strictly above the tile's diagonal
+  __device__ static bool upper_block(int wm, int wn, int i, int j) {
+    return wm * (BM / 2) + i * 32 < wn * (BN / 2) + j * 32;
+  }
+
   // acc += A[m0.., k-range] * B[k-range, n0..] for k in [0, K)
-  __device__ void mainloop(int M, int N, int K, const float* __restrict__ A, int lda, const float* __restrict__ B,
-                           int ldb, int m0, int n0, float* As, float* Bs, floatx16 (&acc)[TMB][TNB]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __device__ void mainloop(int N, int K, const float* __restrict__ A, int lda, const float* __restrict__ B, int ldb,
+                           int m0, int n0, float* As, float* Bs, floatx16 (&acc)[TMB][TNB]) {
+    // the wave index is uniform; readfirstlane lets the compiler keep it scalar
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = wave & 1, wn = (wave >> 1) & 1, kg = wave >> 2;
 #pragma unroll
     for (int i = 0; i < TMB; ++i)
@@ -125,10 +135,10 @@ struct G32 {
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
     const int nk = (K + BK - 1) / BK;
     if (nk == 0) return;
-    load_a(A, lda, M, K, m0, 0);
+    load_a(A, lda, K, m0, 0);
     load_b(B, ldb, N, K, n0, 0);
-    store_a(As);
-    store_b(Bs);
+    store_a(As, K, 0);
+    store_b(Bs, K, 0);
     __syncthreads();
     const int kidx = lane >> 5, midx = lane & 31;
     for (int kt = 0; kt < nk; ++kt) {
@@ -136,7 +146,7 @@ struct G32 {
       const float* Ac = As + cur * BK * LDA;
       const float* Bc = Bs + cur * BK * LDB;
       if (kt + 1 < nk) {
-        load_a(A, lda, M, K, m0, (kt + 1) * BK);
+        load_a(A, lda, K, m0, (kt + 1) * BK);
         load_b(B, ldb, N, K, n0, (kt + 1) * BK);
       }
 #pragma unroll
@@ -153,8 +163,8 @@ struct G32 {
           for (int j = 0; j < TNB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
       }
       if (kt + 1 < nk) {
-        store_a(As + (cur ^ 1) * BK * LDA);
-        store_b(Bs + (cur ^ 1) * BK * LDB);
+        store_a(As + (cur ^ 1) * BK * LDA, K, (kt + 1) * BK);
+        store_b(Bs + (cur ^ 1) * BK * LDB, K, (kt + 1) * BK);
       }
       __syncthreads();
     }
@@ -256,7 +266,7 @@ __device__ __forceinline__ void g32_body(int bid, int M, int N, int K, const flo
   const int m0 = (tile % tiles_m) * BM, n0 = (tile / tiles_m) * BN;
   floatx16 acc[G::TMB][G::TNB];
   G g;
-  g.mainloop(M, N, K, A, lda, B, ldb, m0, n0, As, Bs, acc);
+  g.mainloop(N, K, A, lda, B, ldb, m0, n0, As, Bs, acc);
   epi(acc, M, N, m0, n0, As);
 }
 
@@ -315,7 +325,8 @@ __device__ __forceinline__ void syrk32_body(int bid, int nwg, int n, int K, int 
   const float* Yk = Y + static_cast<int64_t>(k0) * ldy;
   const float* Yk2 = Y2 + static_cast<int64_t>(k0) * ldy;
   G g;
-  g.mainloop(n, n, max(0, k1 - k0), Yk, ldy, Yk2, ldy, tm * BM, tn * BM, As, Bs, acc);
+  const bool diag = tm == tn;
+  g.mainloop(n, max(0, k1 - k0), Yk, ldy, Yk2, ldy, tm * BM, tn * BM, As, Bs, acc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if constexpr (G::KG == 2) {
     // k-group 1 hands its sums to k-group 0 (lane-contiguous, conflict free)
@@ -339,12 +350,14 @@ __device__ __forceinline__ void syrk32_body(int bid, int nwg, int n, int K, int 
         for (int r = 0; r < 16; ++r) acc[i][j][r] += smem[(((r * 4 + wq) * G::TMB + i) * G::TMB + j) * 64 + lane];
   }
   // fragment-native layout: each lane stores its 16 accumulator values
-  // contiguously, so a wave writes one contiguous 4 KiB run per 32x32 block
+  // contiguously, so a wave writes one contiguous 4 KiB run per 32x32 block.
+  // Blocks above a diagonal tile's diagonal are never read back.
   float* out = work + (static_cast<int64_t>(s) * ntl + t) * (BM * BM);
 #pragma unroll
   for (int i = 0; i < G::TMB; ++i)
 #pragma unroll
     for (int j = 0; j < G::TMB; ++j) {
+      if (diag && G::upper_block(wave & 1, wave >> 1, i, j)) continue;
       float4* dst = reinterpret_cast<float4*>(out + ((((wave * G::TMB + i) * G::TMB + j) * 64 + lane) << 4));
 #pragma unroll
       for (int q = 0; q < 4; ++q)

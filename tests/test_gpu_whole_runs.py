@@ -61,3 +61,33 @@ def test_config2_ipop_rotated_ellipsoid(P, golden):
     mg, mo = float(np.median(gpu)), float(np.median(ref))
     print(f"config2 median evals gpu {mg:.0f} oracle {mo:.0f} ratio {mg / mo:.3f}", flush=True)
     assert abs(mg - mo) <= 0.1 * mo
+
+
+def test_config5_scaled_bf16x3_rotated_ellipsoid(P, golden):
+    """The large workload's path at a size the oracle runs whole: one descent,
+    mixed precision with y = B D z as bf16x3 split products, float32 rank-mu
+    SYRK, float64 eigensolve at the automatic interval; rotated ellipsoid
+    (condition 1e6), n = 100, lambda = 2n = 200, mu = 100 (the ratios of
+    n = 2000, lambda = 4096, mu = 2048), seeds 1..15."""
+    n, lam = 100, 200
+    recs = golden["config5"]
+    gpu = []
+    for rec in recs:
+        seed = rec["seed"]
+        print(f"case config5 seed={seed}", flush=True)
+        R, xs = synth.problem(n, seed)
+        with P.CMAES(n, lam, 2.0, seed=seed, precision="mixed_bf16x3", objective="ellipsoid", R=R, xstar=xs,
+                     max_gens=20000) as es:
+            assert es.state(False)["kappa"] == rec["kappa"]
+            while True:
+                es.generation()
+                s = es.state(False)
+                if s["stop"]:
+                    break
+        assert s["f_best"] < 1e-8, (seed, s["f_best"], s["stop_names"])
+        gpu.append(s["evals"])
+    ref = [rec["evals"] for rec in recs]
+    assert all(rec["f_best"] < 1e-8 for rec in recs)
+    mg, mo = float(np.median(gpu)), float(np.median(ref))
+    print(f"config5 (scaled) median evals gpu {mg:.0f} oracle {mo:.0f} ratio {mg / mo:.3f}", flush=True)
+    assert abs(mg - mo) <= 0.1 * mo
