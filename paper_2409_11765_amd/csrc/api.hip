@@ -599,6 +599,10 @@ int phase_update_pre(cmaes* h) {
     kt_end(&h->kt);
     CMX_HIP(launch_polar_step(h->st, n, h->B, ldn, h->ew.T, ldn));
   }
+  if (h->ew.N == kWholeSolveN) {  // the single-workgroup solve forms its own warm start
+    eigen_begin_host(h->ew);
+    return 0;
+  }
   return eigen_begin(h->st, n, h->C, ldn, h->B, ldn, h->ew, &h->kt);
 }
 
@@ -1489,6 +1493,8 @@ GEigDesc eig_desc(cmaes* h) {
   e.Q2 = w.Q2;
   e.part = w.part;
   e.scale = w.scale;
+  e.C = h->C;
+  e.ldc = h->ldn;
   e.status = w.status;
   e.ctl = w.gctl;
   e.B = h->B;
@@ -1723,14 +1729,25 @@ int grouped_front(LockstepGroup& g, const std::vector<cmaes*>& hs, const GroupDu
                                reorth));
     CMX_HIP(launch_group_update(st, GF_POLAR, tab, off(GF_POLAR), count, wgs(GF_POLAR), &reorth));
   }
-  if (any_due) {
-    CMX_HIP(launch_group_eigen_begin(st, GF_INIT, tab, off(GF_INIT), count, wgs(GF_INIT), due));
+  // warm starts of the due descents, except those whose single-workgroup
+  // solve forms its own
+  GroupDueMask begin = due;
+  bool any_begin = false;
+  for (int i = 0; i < count; ++i)
+    if (due_mask_bit(due, i)) {
+      if (hs[i]->ew.N == kWholeSolveN)
+        begin.w[i >> 5] &= ~(1u << (i & 31));
+      else
+        any_begin = true;
+    }
+  if (any_due && any_begin) {
+    CMX_HIP(launch_group_eigen_begin(st, GF_INIT, tab, off(GF_INIT), count, wgs(GF_INIT), begin));
     CMX_HIP(launch_group_dgemm(st, false, mm + 2 * kGroupMax, moff(2, 0), mwgs(2, 0), moff(2, 1), mwgs(2, 1), count,
-                               due));
+                               begin));
     CMX_HIP(launch_group_dgemm(st, true, mm + 3 * kGroupMax, moff(3, 0), mwgs(3, 0), moff(3, 1), mwgs(3, 1), count,
-                               due));
-    CMX_HIP(launch_group_eigen_begin(st, GF_OFFCOLS, tab, off(GF_OFFCOLS), count, wgs(GF_OFFCOLS), due));
-    CMX_HIP(launch_group_eigen_begin(st, GF_OFFFIN, tab, off(GF_OFFFIN), count, wgs(GF_OFFFIN), due));
+                               begin));
+    CMX_HIP(launch_group_eigen_begin(st, GF_OFFCOLS, tab, off(GF_OFFCOLS), count, wgs(GF_OFFCOLS), begin));
+    CMX_HIP(launch_group_eigen_begin(st, GF_OFFFIN, tab, off(GF_OFFFIN), count, wgs(GF_OFFFIN), begin));
   }
   return 0;
 }

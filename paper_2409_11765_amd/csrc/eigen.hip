@@ -291,7 +291,8 @@ __device__ void rotate_pair(double* S0, double* S1, double* Q, double thr, doubl
     Q[r1 * kLD + b] = qb1;
   }
   __syncthreads();
-  for (int idx = t; idx < kS * kS; idx += 256) qout[idx] = Q[(idx % kS) * kLD + idx / kS];
+  if (qout)
+    for (int idx = t; idx < kS * kS; idx += 256) qout[idx] = Q[(idx % kS) * kLD + idx / kS];
   __syncthreads();
 }
 
@@ -956,7 +957,7 @@ __global__ void __launch_bounds__(64) kg_start(const GEigDesc* __restrict__ g, i
                                                 int max_sweeps, int* __restrict__ hactive,
                                                 int* __restrict__ hsweeps) {
   const int i = blockIdx.x;
-  if (i >= count || threadIdx.x != 0) return;
+  if (i >= count || threadIdx.x != 0 || g[i].N == kS) return;  // N = 32: kg_small_solve
   int* c = g[i].ctl;
   const int d = due_bit(due, i) ? 1 : 0;
   c[GC_DUE] = d;
@@ -1041,6 +1042,211 @@ __global__ void __launch_bounds__(256) kg_round(const GEigDesc* __restrict__ g, 
   __hip_atomic_store(&hsweeps[i], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   __hip_atomic_store(&hsweeps[kGroupMax + i], st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   __hip_atomic_fetch_add(hactive, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// ---- whole solve of a descent with N = 32 (n <= 32) in one workgroup, from
+// the warm start to the canonical B, D and B D.  The warm start A = B_old^T C
+// B_old and V = B_old are formed in LDS, and whether to sweep at all is decided
+// from A's off-diagonal norm and the previous solve's sweep count as kg_start
+// decides it.  With two blocks there is a single block pair, so a sweep is one
+// pair solve on the whole matrix: the rotations of rotate_pair (intra-block
+// rounds, then cross rounds) give Q, then A <- Q^T A Q and V <- V Q are formed
+// on the float64 matrix cores, and the off-diagonal norm decides on the next
+// sweep, all inside the kernel.  The stopping rule, the rotation threshold
+// (from the previous max |a_ii|) and the sweep accounting are those of
+// kg_round; the finishing steps (ranks, column signs, canonical B, D and B D)
+// follow in the same workgroup.  Later launches of a mixed group skip the
+// descent (kg_start leaves it alone, its due word is cleared).
+
+// P = X Y for 32 x 32 matrices in LDS (row stride kLD), X given as X(r, k) =
+// xs[r * kLD + k] or, with XT, as xs[k * kLD + r]; each of the four waves
+// forms one 16 x 16 block of P (mfma_k32 layout)
+template <bool XT>
+__device__ __forceinline__ doublex4 small_product(const double* xs, const double* ys, int bi, int bj) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  double a[8], b[8];
+#pragma unroll
+  for (int s2 = 0; s2 < 8; ++s2) {
+    const int k = 4 * s2 + lk;
+    a[s2] = XT ? xs[k * kLD + bi * kNB + li] : xs[(bi * kNB + li) * kLD + k];
+    b[s2] = ys[k * kLD + bj * kNB + li];
+  }
+  return mfma_k32(a, b);
+}
+
+// off-diagonal / total squared norms over the n x n part of Aw and max
+// |a_ii|: one column per thread, then the columns in order by thread 0, which
+// gets the flags (as offnorm_flags) and the new scale in red[2][0]
+__device__ __forceinline__ void small_offnorm(const double* Aw, int n, double (*red)[kS], int& more, int& nonfin) {
+  const int t = threadIdx.x;
+  if (t < kS) {
+    double off = 0.0, tot = 0.0;
+    for (int r = 0; r < n; ++r) {
+      const double v = Aw[r * kLD + t];
+      tot += v * v;
+      if (r != t) off += v * v;
+    }
+    red[0][t] = t < n ? off : 0.0;
+    red[1][t] = t < n ? tot : 0.0;
+    red[2][t] = t < n ? fabs(Aw[t * kLD + t]) : 0.0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double off = 0.0, tot = 0.0, dmax = 0.0;
+    for (int k = 0; k < kS; ++k) {
+      off += red[0][k];
+      tot += red[1][k];
+      dmax = fmax(dmax, red[2][k]);
+    }
+    red[2][0] = dmax;
+    int small;
+    offnorm_flags(off, tot, more, nonfin, small);
+  }
+}
+
+__global__ void __launch_bounds__(256) kg_small_solve(const GEigDesc* __restrict__ g, int count, GroupDueMask due,
+                                                      int max_sweeps, int* __restrict__ hsweeps) {
+  __shared__ double Aw[kS * kLD], S0[kS * kLD], S1[kS * kLD], Q[kS * kLD], Vw[kS * kLD], T[kS * kLD];
+  __shared__ double red[3][kS];
+  __shared__ double ev[kS], sgn[kS];
+  __shared__ int perm[kS];
+  __shared__ int go;
+  const int i = blockIdx.x;
+  if (i >= count) return;
+  const GEigDesc& e = g[i];
+  if (e.N != kS) return;
+  int* c = e.ctl;
+  const int n = e.n, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int li = lane & 15, lk = lane >> 4, bi = w & 1, bj = w >> 1;
+  if (!due_mask_bit(due, i)) {
+    if (t == 0) c[GC_DUE] = 0;
+    return;
+  }
+  // warm start: C and V = B_old padded with zeros / the identity; T = C V,
+  // then A = V^T T (mirrored from its lower half)
+  for (int idx = t; idx < kS * kS; idx += 256) {
+    const int r = idx % kS, cc = idx / kS;
+    const bool in = r < n && cc < n;
+    S0[r * kLD + cc] = in ? e.C[static_cast<int64_t>(cc) * e.ldc + r] : 0.0;
+    Vw[r * kLD + cc] = in ? e.B[static_cast<int64_t>(cc) * e.ldb + r] : (r == cc ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  {
+    const doublex4 cv = small_product<false>(S0, Vw, bi, bj);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) T[(bi * kNB + lk + 4 * rr) * kLD + bj * kNB + li] = cv[rr];
+    __syncthreads();
+    const doublex4 vt = small_product<true>(Vw, T, bi, bj);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) Aw[(bi * kNB + lk + 4 * rr) * kLD + bj * kNB + li] = vt[rr];
+    __syncthreads();
+    for (int idx = t; idx < kS * kS; idx += 256) {
+      const int r = idx / kS, cc = idx % kS;
+      if (r < cc) Aw[r * kLD + cc] = Aw[cc * kLD + r];
+    }
+    __syncthreads();
+  }
+  int done = 0, more = 0, nonfin = 0;
+  small_offnorm(Aw, n, red, more, nonfin);
+  // whether to sweep (kg_start): at least last - 1 sweeps after a solve of
+  // `last` sweeps, else only while the warm start is not diagonal enough
+  const int last = c[GC_LAST];
+  const int mins = last >= 2 ? min(last - 1, max_sweeps) : 0;
+  if (t == 0) go = (mins > 0 || (more && !nonfin)) ? 1 : 0;
+  __syncthreads();
+  const bool active = go != 0;
+  double scale = red[2][0];
+  __syncthreads();
+  while (active) {
+    for (int idx = t; idx < kS * kS; idx += 256) S0[(idx / kS) * kLD + idx % kS] = Aw[(idx / kS) * kLD + idx % kS];
+    __syncthreads();
+    rotate_pair(S0, S1, Q, 2.2e-16 * scale, scale > 0.0 ? 1.0 / scale : 0.0, true, nullptr, false, kNB >= n);
+    // T = A Q and V Q (into S1), then A = Q^T T, mirrored from its lower half
+    const doublex4 aq = small_product<false>(Aw, Q, bi, bj);
+    const doublex4 vq = small_product<false>(Vw, Q, bi, bj);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      T[(bi * kNB + lk + 4 * rr) * kLD + bj * kNB + li] = aq[rr];
+      S1[(bi * kNB + lk + 4 * rr) * kLD + bj * kNB + li] = vq[rr];
+    }
+    __syncthreads();
+    const doublex4 qt = small_product<true>(Q, T, bi, bj);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) Aw[(bi * kNB + lk + 4 * rr) * kLD + bj * kNB + li] = qt[rr];
+    __syncthreads();
+    for (int idx = t; idx < kS * kS; idx += 256) {
+      const int r = idx / kS, cc = idx % kS;
+      if (r < cc) Aw[r * kLD + cc] = Aw[cc * kLD + r];
+      Vw[r * kLD + cc] = S1[r * kLD + cc];
+    }
+    __syncthreads();
+    small_offnorm(Aw, n, red, more, nonfin);
+    if (t == 0) {
+      ++done;
+      go = (done < max_sweeps && (done < mins || (more && !nonfin))) ? 1 : 0;
+    }
+    __syncthreads();
+    scale = red[2][0];
+    if (!go) break;
+    __syncthreads();
+  }
+  if (t == 0) {
+    int* st = e.status;
+    st[0] = nonfin ? 3 : (more ? 2 : 1);
+    st[1] = done;
+    st[2] = 0;
+    c[GC_LAST] = done;
+    c[GC_STOPR] = 0;
+    c[GC_DUE] = 0;
+    __hip_atomic_store(&hsweeps[i], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&hsweeps[kGroupMax + i], st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  // finishing steps, as kg_rank / kg_colsign / kg_permute: ascending
+  // eigenvalues (ties by index), each column's largest-magnitude entry (first
+  // on ties) positive, then B, D and B D in that order
+  if (t < kS) {
+    ev[t] = Aw[t * kLD + t];
+    perm[t] = t;  // (non-finite eigenvalues can leave ranks unassigned)
+  }
+  __syncthreads();
+  if (t < n) {
+    const double vi = ev[t];
+    int cnt = 0;
+    for (int j = 0; j < n; ++j) cnt += (ev[j] < vi) || (ev[j] == vi && j < t);
+    perm[cnt] = t;
+    e.perm[cnt] = t;
+    e.evals[t] = vi;
+    double best = -1.0;
+    int arg = 0;
+    for (int r = 0; r < n; ++r) {
+      const double v = fabs(Vw[r * kLD + t]);
+      if (v > best) {
+        best = v;
+        arg = r;
+      }
+    }
+    sgn[t] = Vw[arg * kLD + t] < 0.0 ? -1.0 : 1.0;
+    e.sign[t] = sgn[t];
+    if (cnt == 0) {
+      const int* st = e.status;
+      e.sc->eig_ok = (vi > 0.0 && st[0] == 1) ? 1 : 0;
+      e.sc->jac_sweeps = st[1];
+      e.sc->jac_corr = st[2];
+    }
+  }
+  __syncthreads();
+  for (int idx = t; idx < n * n; idx += 256) {
+    const int r = idx / n, row = idx % n;  // output column r, row
+    const int cc = min(max(perm[r], 0), n - 1);
+    const double d = sqrt(fmax(ev[cc], 0.0));
+    const double v = sgn[cc] * Vw[row * kLD + cc];
+    if (row == 0) e.D[r] = d;
+    e.B[static_cast<int64_t>(r) * e.ldb + row] = v;
+    if (e.bd64)
+      static_cast<double*>(e.BD)[static_cast<int64_t>(r) * e.ldbd + row] = v * d;
+    else
+      static_cast<float*>(e.BD)[static_cast<int64_t>(r) * e.ldbd + row] = static_cast<float>(v * d);
+  }
 }
 
 // the finishing steps of every descent that solved: eigenvalue ranks, column
@@ -1316,8 +1522,11 @@ int group_eig_build(hipStream_t st, GroupEig& ge, const std::vector<GEigDesc>& d
                                   ceil_div(e.n, 256) * e.n};
     for (int k = 0; k < kGroupKinds; ++k) off[k * (count + 1) + i + 1] = off[k * (count + 1) + i] + wgs[k];
   }
-  int pmax = 2;
-  for (const auto& e : descs) pmax = std::max(pmax, e.N / kNB);
+  int pmax = 2, nsmall = 0;
+  for (const auto& e : descs) {
+    pmax = std::max(pmax, e.N / kNB);
+    nsmall += e.N == kS ? 1 : 0;
+  }
   const size_t tab_bytes = sizeof(GEigDesc) * count, off_bytes = sizeof(int) * off.size();
   if (ge.cap < count) {
     group_eig_release(ge);
@@ -1337,6 +1546,7 @@ int group_eig_build(hipStream_t st, GroupEig& ge, const std::vector<GEigDesc>& d
   }
   ge.count = count;
   ge.pmax = pmax;
+  ge.nsmall = nsmall;
   ge.off = off;
   // the table and the offsets, on the group's stream; consumed before return
   CMX_HIP(hipMemcpyAsync(ge.dtab, descs.data(), tab_bytes, hipMemcpyHostToDevice, st));
@@ -1356,6 +1566,22 @@ int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int m
   int* hactive = ge.dflags;            // [0]: descents still sweeping
   int* hsweeps = ge.dflags + 1;        // [1 + i]: sweeps of descent i
   ge.hflags[0] = 0;
+  auto read_out = [&]() {
+    for (int i = 0; i < count; ++i)
+      if (due_mask_bit(due, i)) {
+        sweeps_out[i] = __atomic_load_n(&ge.hflags[1 + i], __ATOMIC_ACQUIRE);
+        if (code_out) code_out[i] = __atomic_load_n(&ge.hflags[1 + kGroupMax + i], __ATOMIC_ACQUIRE);
+      }
+  };
+  // descents with N = 32 solve whole in one workgroup each, warm start
+  // included, to completion
+  if (ge.nsmall > 0) kg_small_solve<<<count, 256, 0, st>>>(tab, count, due, max_sweeps, hsweeps);
+  if (ge.nsmall == count) {
+    CMX_HIP(hipGetLastError());
+    CMX_HIP(hipStreamSynchronize(st));
+    read_out();
+    return 0;
+  }
   kg_start<<<count, 64, 0, st>>>(tab, count, due, max_sweeps, hactive, hsweeps);
   kg_first<<<wgs_of(0), 256, 0, st>>>(tab, off_of(0), count);
   CMX_HIP(hipGetLastError());
@@ -1392,11 +1618,7 @@ int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int m
   kg_colsign<<<wgs_of(3), 256, 0, st>>>(tab, off_of(3), count);
   kg_permute<<<wgs_of(4), 256, 0, st>>>(tab, off_of(4), count);
   CMX_HIP(hipGetLastError());
-  for (int i = 0; i < count; ++i)
-    if (due_mask_bit(due, i)) {
-      sweeps_out[i] = __atomic_load_n(&ge.hflags[1 + i], __ATOMIC_ACQUIRE);
-      if (code_out) code_out[i] = __atomic_load_n(&ge.hflags[1 + kGroupMax + i], __ATOMIC_ACQUIRE);
-    }
+  read_out();
   return 0;
 }
 

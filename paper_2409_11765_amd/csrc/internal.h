@@ -251,6 +251,9 @@ void eigen_drop_graphs(EigWork& w);
 // ---- grouped eigensolve: the sweeps of many descents in one launch per
 // round, convergence decided per descent on the device (see eigen.hip)
 constexpr int kGroupMax = 1024;  // descents per group
+// padded size whose eigensolve, warm start included, runs whole in one
+// workgroup (n <= 32): no separate warm-start launches are queued for it
+constexpr int kWholeSolveN = 32;
 constexpr int kGroupKinds = 5;   // launch kinds with per-descent workgroups
 // words of a descent's control block (EigWork::gctl); k_offnorm_final of the
 // warm start writes GC_MORE and GC_NONFIN
@@ -258,6 +261,8 @@ enum GroupCtl { GC_STOPR = 0, GC_MIN = 1, GC_LAST = 2, GC_CNT = 3, GC_MORE = 4, 
                 GC_WORDS = 8 };
 struct GEigDesc {  // one descent of a grouped solve (device table entry)
   double *A, *A2, *V, *Q, *Q2, *part, *scale;
+  const double* C;  // the covariance (read by the single-workgroup solve's warm start)
+  int ldc;
   int* status;
   int* ctl;
   double* B;
@@ -282,6 +287,7 @@ struct GroupEig {
                           // [1 + kGroupMax + i] its status (1 converged, 2 sweep limit, 3 non-finite)
   int* dflags = nullptr;  // device address of hflags
   int cap = 0, count = 0, pmax = 2;
+  int nsmall = 0;         // descents with N = kWholeSolveN (solved whole by one workgroup each)
   std::vector<int> off;   // host copy of the offsets (kGroupKinds x (count + 1))
 };
 // (re)load the table of descents (their buffers must stay allocated while in use)
