@@ -499,7 +499,9 @@ int phase_sample(cmaes* h, const double* Zhost) {
     CMX_HIP(launch_normals(h->st, h->Z, h->fp64, ldn, n, lam, h->seed, static_cast<uint32_t>(h->restart), h->sc));
     kt_end(&h->kt);
   }
-  kt_begin(&h->kt, KID_SAMPLE_GEMM);
+  // the float32 tile launch times itself (its dispatch's own timestamps)
+  const bool g32 = h->opt.variant != CMAES_VARIANT_SEPARABLE && h->opt.precision != CMAES_MIXED_BF16X3 && !h->fp64;
+  if (!g32) kt_begin(&h->kt, KID_SAMPLE_GEMM);
   if (h->opt.variant == CMAES_VARIANT_SEPARABLE)
     CMX_HIP(launch_sep_sample(h->st, h->fp64, n, lam, h->D, h->Z, ldn, h->Y, ldn));
   else if (h->opt.precision == CMAES_MIXED_BF16X3)
@@ -510,8 +512,8 @@ int phase_sample(cmaes* h, const double* Zhost) {
                                    static_cast<const double*>(h->Z), ldn, static_cast<double*>(h->Y), ldn));
   else
     CMX_HIP(g32_gemm(h->st, h->gcfg[G32_SAMPLE], G32_SAMPLE, n, lam, n, static_cast<const float*>(h->BD), ldn,
-                     static_cast<const float*>(h->Z), ldn, h->Y, ldn, nullptr));
-  kt_end(&h->kt);
+                     static_cast<const float*>(h->Z), ldn, h->Y, ldn, nullptr, &h->kt, KID_SAMPLE_GEMM));
+  if (!g32) kt_end(&h->kt);
   rec(h, 1);
   return 0;
 }
@@ -522,18 +524,19 @@ int phase_fitness(cmaes* h) {
                        h->part_bz, h->d));
   FitnessArgs fa{h->obj_kind, h->d, h->coef, h->sc, h->partial, lam};
   int tiles = 0;
-  kt_begin(&h->kt, KID_FITNESS);
-  if (h->have_R && !h->fp64) {
+  const bool g32 = h->have_R && !h->fp64;  // the float32 tile launch times itself
+  if (!g32) kt_begin(&h->kt, KID_FITNESS);
+  if (g32) {
     const G32FitArgs ga{h->obj_kind, h->d, static_cast<const float*>(h->coef), h->sc};
     tiles = g32_row_tiles(h->gcfg[G32_FITNESS], n);
     CMX_HIP(g32_gemm(h->st, h->gcfg[G32_FITNESS], G32_FITNESS, n, lam, n, static_cast<const float*>(h->Rt), ldn,
-                     static_cast<const float*>(h->Y), ldn, h->partial, lam, &ga));
+                     static_cast<const float*>(h->Y), ldn, h->partial, lam, &ga, &h->kt, KID_FITNESS));
   } else if (h->have_R)
     CMX_HIP(launch_fitness_gemm_f64(h->st, n, lam, static_cast<const double*>(h->Rt), ldn,
                                     static_cast<const double*>(h->Y), ldn, fa, &tiles));
   else
     CMX_HIP(launch_fitness_direct(h->st, h->fp64, n, lam, h->Y, ldn, fa, &tiles));
-  kt_end(&h->kt);
+  if (!g32) kt_end(&h->kt);
   CMX_HIP(launch_fitness_reduce(h->st, h->fp64, h->obj_kind, n, lam, h->partial, lam, tiles, h->f));
   return 0;
 }

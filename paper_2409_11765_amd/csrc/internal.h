@@ -172,8 +172,10 @@ bool g32_config_valid(int cfg, int site);
 int g32_row_tiles(int cfg, int M);
 // site G32_SAMPLE: out = A*B (float, ld ldo); G32_FITNESS: out = per-row-tile
 // partial objective sums of d + sigma A*B ([row_tiles][N] floats, ld ldo)
+// kt / kid: while kt is timing, the launch records its own start and end
+// timestamps under kid
 hipError_t g32_gemm(hipStream_t st, int cfg, int site, int M, int N, int K, const float* A, int lda, const float* B,
-                    int ldb, void* out, int ldo, const G32FitArgs* fa);
+                    int ldb, void* out, int ldo, const G32FitArgs* fa, KTimer* kt = nullptr, int kid = 0);
 void syrk32_plan(int cfg, int n, int K, int* ntl, int* splits, int* kspan, size_t* work_elems);
 int syrk32_threads(int cfg);
 size_t syrk32_max_work(int n, int K);

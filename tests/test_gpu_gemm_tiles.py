@@ -133,3 +133,33 @@ def test_autotune_keeps_state_and_caches(P, precision, tmp_path):
             assert es2.gemm_config(site) == cfg
     finally:
         es2.close()
+
+
+@pytest.mark.parametrize("precision,cfg", [("fp64", 0)] + [("mixed", c) for c in range(NUM_CONFIGS)])
+def test_integer_inputs_give_exact_fitness(P, precision, cfg):
+    """Integer-valued operands make the sampling product and the fused
+    fitness exact in both precisions and with every tile: B a signed
+    permutation, D and z small integers, m integer, sigma = 1/2, the
+    unrotated sphere (every x_i is a multiple of 1/2, every f a multiple of
+    1/4 far below 2^24), so each f must equal the plain float64 sum of
+    squares bit for bit and the ranks must equal a stable argsort."""
+    n, lam = 37, 53
+    g = synth.rng(91)
+    perm = g.permutation(n)
+    B = np.zeros((n, n))
+    B[perm, np.arange(n)] = g.choice([-1.0, 1.0], n)
+    D = g.integers(1, 4, n).astype(np.float64)
+    st = {"n": n, "lambda": lam, "m": g.integers(-3, 4, n).astype(np.float64), "sigma": 0.5,
+          "C": (B * D ** 2) @ B.T, "B": B, "D": D, "p_sigma": np.zeros(n), "p_c": np.zeros(n), "gen": 3}
+    Z = g.integers(-4, 5, (n, lam)).astype(np.float64)
+    with P.CMAES(n, lam, 1.0, seed=1, precision=precision, objective="sphere", xstar=np.zeros(n)) as es:
+        if precision == "mixed":
+            es.set_gemm_config("sample", cfg)
+            es.set_gemm_config("fitness", cfg)
+        es.set_state(st)
+        es.generation_with_z(Z)
+        s = es.state()
+    X = st["m"][:, None] + 0.5 * (B @ (D[:, None] * Z))
+    f = np.sum(X * X, axis=0)
+    assert np.array_equal(s["f"], f)
+    assert np.array_equal(s["order"], np.argsort(f, kind="stable"))
