@@ -156,15 +156,17 @@ def test_set_eigen_correction_checks_its_bound(P):
         es.set_eigen_correction(True, 2e-3)
 
 
-@pytest.mark.parametrize("n,lam", [(64, 128), (24, 48)])
+@pytest.mark.parametrize("n,lam", [(100, 128), (64, 128), (24, 48)])
 def test_non_finite_covariance_after_warm_solves(P, n, lam):
     """A non-finite C in the middle of a descent whose solves take several
-    sweeps: the first batch of sweeps is then queued before the warm start's
-    flags are read, runs on NaN, and the solve must still end with the
-    descent stopped (no hang; the generation reports CMAES_ENUMERIC); a
-    restart then decomposes correctly, the solve's set-up having cleared what
-    the NaN left in the A buffers.  n = 24 takes the single-workgroup solve
-    (N = 32), whose sweeps run inside one kernel."""
+    sweeps: on the block path (n = 100) the first batch of sweeps is then
+    queued before the warm start's flags are read, runs on NaN, and the solve
+    must still end with the descent stopped (no hang; the generation reports
+    CMAES_ENUMERIC); a restart then decomposes correctly, the solve's set-up
+    having cleared what the NaN left in the A buffers.  n = 64 takes the
+    grouped solve of one descent (several sweeps queued per host wait), and
+    n = 24 the single-workgroup solve (padded size 32), whose sweeps run
+    inside one kernel."""
     print(f"case non-finite C n={n} lam={lam}", flush=True)
     R, xs = synth.problem(n, seed=1)
     with P.CMAES(n, lam, 2.0, seed=1, precision="fp64", objective="ellipsoid", R=R, xstar=xs,

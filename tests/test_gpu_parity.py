@@ -100,11 +100,12 @@ def test_normals_and_initial_mean_match_oracle(P, precision):
     assert np.max(np.abs(X - Xref)) < 1e-13
 
 
-@pytest.mark.parametrize("n", [2, 10, 16, 17, 31, 32, 33, 37, 100, 200, 333])
+@pytest.mark.parametrize("n", [2, 10, 16, 17, 31, 32, 33, 37, 48, 63, 64, 65, 100, 200, 333])
 def test_eigendecomposition_invariants(P, n):
     """After a generation with an eigen step (kappa = 1): C = B D^2 B^T to
     1e-12, B orthonormal, eigenvalues equal to a library eigensolver's, and
-    the canonical order/sign convention."""
+    the canonical order/sign convention (n <= 32 through the single-workgroup
+    solve, 33 and up through the block path)."""
     lam = max(8, 4 * n)
     st = synth.random_state(n, lam, seed=n, cond=1e4)
     R, xs = synth.problem(n, seed=1)
@@ -140,7 +141,8 @@ def test_eigen_cold_start_from_identity(P):
 
 
 @pytest.mark.parametrize("n,lam,precision", [(1000, 2048, "mixed"), (1000, 24, "mixed"), (400, 800, "fp64"),
-                                              (24, 48, "mixed"), (32, 12, "fp64")])
+                                              (24, 48, "mixed"), (32, 12, "fp64"), (40, 60, "mixed"),
+                                              (64, 16, "fp64")])
 def test_eigenvectors_stay_orthonormal_over_a_long_run(P, n, lam, precision):
     """B is carried from one warm-started eigensolve to the next (B = B_old V),
     so rounding in the rotations accumulates unless B is re-orthogonalised;
