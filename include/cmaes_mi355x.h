@@ -272,8 +272,9 @@ int cmaes_batch_best(const cmaes_batch_t* b, double* f_best, int* k_best);
 int cmaes_enable_timing(cmaes_t* h, int on);
 int cmaes_phase_times(const cmaes_t* h, double* out);
 
-/* Per-kernel device time, measured with HIP events recorded around the
- * launches of the kernels below while enabled (enabling resets the totals).
+/* Per-kernel device time while enabled (enabling resets the totals): the
+ * float32 tile launches and the Jacobi rounds record their own dispatch start
+ * and end timestamps; the other kernels below are bracketed by HIP events.
  * cmaes_kernel_times() writes CMAES_NUM_KERNELS totals in microseconds and
  * launch counts, indexed by the CMAES_KERNEL_* values. */
 #define CMAES_KERNEL_NORMALS 0     /* Philox + Box-Muller sampler               */

@@ -8,7 +8,9 @@
 //    (BM/2) x (BN/2) sub-tile of 32 x 32 MFMA blocks;
 //  * operands staged k-major in LDS (m / n contiguous, conflict-free MFMA
 //    reads), double buffered, one barrier per k-tile; the next k-tile's global
-//    loads are in flight while the current one is multiplied;
+//    loads (unconditional float4 reads from clamped addresses, the k-tail
+//    zeroed only when staged) are in flight while the current one is
+//    multiplied;
 //  * XCD-aware tile order: consecutive workgroups are dispatched round-robin
 //    over the 8 XCDs, so workgroup w is given tile (w mod 8) * T/8 + w / 8 and
 //    each XCD walks a contiguous run of tiles that share their B columns in
