@@ -185,8 +185,10 @@ def run_gpu(P, torch, n, lam, precision, steps, warmup, seed, R, xs, tune=True, 
         wall = time.perf_counter() - wall0
         ms = t0.elapsed_time(t1) / steps
         st = es.state(arrays=False)
-        # per-kernel device time from HIP events around each launch, on the
-        # handle's stream (a separate pass: the events add a little overhead)
+        # per-kernel device time, on the handle's stream, in a separate pass:
+        # the float32 tiles and the Jacobi rounds record their own dispatch
+        # timestamps, the other kernels are bracketed by HIP events (which
+        # add a little overhead to the generation)
         ksteps = max(2, min(steps, 5))
         es.enable_kernel_timing(True)
         for _ in range(ksteps):
@@ -593,6 +595,16 @@ def main():
                        "gens_per_s": 1e3 / fp64["ms_per_step"], "phases_us": fp64["phases_us"]}
         out["mixed_over_fp64"] = fp64["ms_per_step"] / mixed["ms_per_step"]
     kt = mixed["kernels"]
+    # the same fractions from the kernels' own dispatch-timed durations (the
+    # phase figures above also hold the small kernels around each product)
+    kus = {k: kt[k]["total_us"] / kt[k]["calls"] for k in ("sample_gemm", "fitness", "syrk")
+           if k in kt and kt[k]["calls"]}
+    if len(kus) == 3:
+        out["gemm_kernel_frac"] = {
+            "sample": frac(flop_sample, kus["sample_gemm"]), "fitness": frac(flop_fit, kus["fitness"]),
+            "syrk": frac(flop_syrk, kus["syrk"]),
+            "sampling_and_rank_mu": frac(flop_sample + flop_syrk, kus["sample_gemm"] + kus["syrk"]),
+            "all_gemm": frac(flop_sample + flop_fit + flop_syrk, sum(kus.values()))}
     syrk_cfg = mixed["tiles"]["syrk"]["config"] if mixed["tiles"] else None
     work = kernel_work(n, lam, a.precision, mixed["state"]["eig_sweeps"], syrk_cfg)
     per_kernel = {k: roofline_entry(k, kt, work) for k in kt if kt[k]["calls"] and k in work}
