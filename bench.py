@@ -136,6 +136,8 @@ def parse():
                     help="instead of the headline line: the large workload (n=2000, lambda=4096, rotated "
                          "ellipsoid, bf16x3 sampling)")
     ap.add_argument("--large-steps", type=int, default=50)
+    ap.add_argument("--no-large", action="store_true",
+                    help="leave the large workload (n=2000, lambda=4096) out of the headline line")
     ap.add_argument("--ert", action="store_true",
                     help="instead of the headline line: ERT / ECDF of IPOP, K-Distributed and K-Replicated on "
                          "synthetic functions")
@@ -625,6 +627,8 @@ def main():
     out["gemm_tiles"] = mixed["tiles"]
     if a.batch_steps > 0:
         out["batch"] = run_batch(P, torch, a.batch_steps, 3, a.seed)
+    if not a.no_large:
+        out["large"] = run_large(P, torch, a.large_steps, a.seed)
     if not a.no_cpu_baseline:
         cb = cpu_baseline(P, n, lam, a.seed, R, xs, a.cpu_seconds)
         # each result's error against the FP64 oracle, one generation from the

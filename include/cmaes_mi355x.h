@@ -273,8 +273,9 @@ int cmaes_enable_timing(cmaes_t* h, int on);
 int cmaes_phase_times(const cmaes_t* h, double* out);
 
 /* Per-kernel device time while enabled (enabling resets the totals): the
- * float32 tile launches and the Jacobi rounds record their own dispatch start
- * and end timestamps; the other kernels below are bracketed by HIP events.
+ * float32 tile launches, the bf16 x 3 product (without its operand split) and
+ * the Jacobi rounds record their own dispatch start and end timestamps; the
+ * other kernels below are bracketed by HIP events.
  * cmaes_kernel_times() writes CMAES_NUM_KERNELS totals in microseconds and
  * launch counts, indexed by the CMAES_KERNEL_* values. */
 #define CMAES_KERNEL_NORMALS 0     /* Philox + Box-Muller sampler               */

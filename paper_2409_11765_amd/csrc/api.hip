@@ -169,6 +169,8 @@ struct cmaes {
   void* Ysig = nullptr;  // active: Ysel with the columns of negative weight negated
   void* partial = nullptr;
   void* syrk_work = nullptr;
+  void* split = nullptr;  // bf16 hi / lo operands of the bf16 x 3 sampling product
+  size_t split_cap = 0;
   double* u = nullptr;
   EigWork ew{};
   // small n: the eigensolve runs as a grouped solve of this one descent
@@ -231,7 +233,9 @@ void free_pop_buffers(cmaes* h) {
   dev_free(h, h->sqrtw);
   dev_free(h, h->hist);
   dev_free(h, h->syrk_work);
+  dev_free(h, h->split);
   h->cap_lam = h->cap_mu = h->hist_cap = 0;
+  h->split_cap = 0;
 }
 
 void drop_graphs(cmaes* h) {
@@ -309,13 +313,27 @@ void refresh_stop_params(cmaes* h) {
   s.hist_len = hist_len_for(h->n, h->lam);
 }
 
+// split operands of the bf16 x 3 sampling product (that precision only; the
+// precision may switch between the two float32 modes after allocation)
+int alloc_split(cmaes* h) {
+  const size_t need = h->opt.precision == CMAES_MIXED_BF16X3 ? bf16x3_work_bytes(h->n, h->lam) : 0;
+  if (need <= h->split_cap) return 0;
+  drop_graphs(h);
+  if (h->st) (void)hipStreamSynchronize(h->st);  // nothing in flight uses the old buffer
+  dev_free(h, h->split);
+  h->split_cap = 0;
+  if (int rc = dev_alloc(h, &h->split, need)) return rc;
+  h->split_cap = need;
+  return 0;
+}
+
 // population-size dependent buffers
 int alloc_pop(cmaes* h) {
   const int n = h->n, ldn = h->ldn, lam = h->lam;
   // the rank-mu update runs over mu columns, or over all lam ranks (active)
   const bool active = h->opt.variant == CMAES_VARIANT_ACTIVE;
   const int mu = active ? lam : h->hp.kp.mu;
-  if (lam <= h->cap_lam && mu <= h->cap_mu && hist_len_for(n, lam) <= h->hist_cap) return 0;
+  if (lam <= h->cap_lam && mu <= h->cap_mu && hist_len_for(n, lam) <= h->hist_cap) return alloc_split(h);
   drop_graphs(h);
   free_pop_buffers(h);
   const size_t e = esz(h);
@@ -341,7 +359,7 @@ int alloc_pop(cmaes* h) {
   h->cap_lam = lam;
   h->cap_mu = mu;
   h->hist_cap = hist_len_for(n, lam);
-  return 0;
+  return alloc_split(h);
 }
 
 int alloc_fixed(cmaes* h) {
@@ -499,21 +517,23 @@ int phase_sample(cmaes* h, const double* Zhost) {
     CMX_HIP(launch_normals(h->st, h->Z, h->fp64, ldn, n, lam, h->seed, static_cast<uint32_t>(h->restart), h->sc));
     kt_end(&h->kt);
   }
-  // the float32 tile launch times itself (its dispatch's own timestamps)
-  const bool g32 = h->opt.variant != CMAES_VARIANT_SEPARABLE && h->opt.precision != CMAES_MIXED_BF16X3 && !h->fp64;
-  if (!g32) kt_begin(&h->kt, KID_SAMPLE_GEMM);
+  // the float32 and bf16 x 3 products time themselves (their dispatches' own
+  // timestamps; for bf16 x 3 the product alone, not the operand split)
+  const bool self_timed = h->opt.variant != CMAES_VARIANT_SEPARABLE && !h->fp64;
+  if (!self_timed) kt_begin(&h->kt, KID_SAMPLE_GEMM);
   if (h->opt.variant == CMAES_VARIANT_SEPARABLE)
     CMX_HIP(launch_sep_sample(h->st, h->fp64, n, lam, h->D, h->Z, ldn, h->Y, ldn));
   else if (h->opt.precision == CMAES_MIXED_BF16X3)
     CMX_HIP(launch_sample_gemm_bf16x3(h->st, n, lam, static_cast<const float*>(h->BD), ldn,
-                                      static_cast<const float*>(h->Z), ldn, static_cast<float*>(h->Y), ldn));
+                                      static_cast<const float*>(h->Z), ldn, static_cast<float*>(h->Y), ldn,
+                                      h->split, &h->kt, KID_SAMPLE_GEMM));
   else if (h->fp64)
     CMX_HIP(launch_sample_gemm_f64(h->st, n, lam, static_cast<const double*>(h->BD), ldn,
                                    static_cast<const double*>(h->Z), ldn, static_cast<double*>(h->Y), ldn));
   else
     CMX_HIP(g32_gemm(h->st, h->gcfg[G32_SAMPLE], G32_SAMPLE, n, lam, n, static_cast<const float*>(h->BD), ldn,
                      static_cast<const float*>(h->Z), ldn, h->Y, ldn, nullptr, &h->kt, KID_SAMPLE_GEMM));
-  if (!g32) kt_end(&h->kt);
+  if (!self_timed) kt_end(&h->kt);
   rec(h, 1);
   return 0;
 }

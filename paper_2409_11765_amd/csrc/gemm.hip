@@ -584,128 +584,6 @@ __global__ void __launch_bounds__(256) kg_fitness_reduce(const GFront* __restric
   fitness_reduce_body<float>(blockIdx.x - off[i], e.lam, e.partial, e.lam, e.fit_tiles, 0.0, e.f);
 }
 
-// ---------------------------------------------------------- bf16 x 3 sampling
-// Y = (B D) Z with both operands split into bfloat16 pairs x = hi + lo
-// (hi = bf16(x), lo = bf16(x - hi)) and the three significant products
-// hi*hi + hi*lo + lo*hi accumulated in float32 on v_mfma_f32_32x32x16_bf16:
-// about 16 significant bits per operand instead of 8, at the bfloat16 matrix
-// rate.  Tiles are staged k-contiguous (m or n rows of 16 k values) so every
-// MFMA operand is one 16-byte LDS read.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ unsigned short f2bf(float x) {
-  const unsigned u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<unsigned short>(u >> 16);  // inf / nan
-  return static_cast<unsigned short>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);         // nearest even
-}
-__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(static_cast<unsigned>(h) << 16); }
-
-constexpr int kB3M = 128, kB3N = 128, kB3K = 16, kB3LD = kB3K + 8;
-
-__global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, const float* __restrict__ A, int lda,
-                                                     const float* __restrict__ B, int ldb, float* __restrict__ Y,
-                                                     int ldy) {
-  __shared__ unsigned short Ah[kB3M * kB3LD], Al[kB3M * kB3LD], Bh[kB3N * kB3LD], Bl[kB3N * kB3LD];
-  const int tiles_m = (M + kB3M - 1) / kB3M;
-  const int m0 = (blockIdx.x % tiles_m) * kB3M;
-  const int n0 = (blockIdx.x / tiles_m) * kB3N;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  floatx16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-  const int nk = (K + kB3K - 1) / kB3K;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int k0 = kt * kB3K;
-    // A tile: 128 (m) x 16 (k), m contiguous in memory -> two float4 per thread
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const int q = p * 256 + t;
-      const int mm = (q % 32) * 4, kk = q / 32;
-      const int gm = m0 + mm, gk = k0 + kk;
-      float v[4];
-      if (gk < K && gm + 4 <= M) {
-        const float4 x = *reinterpret_cast<const float4*>(A + static_cast<int64_t>(gk) * lda + gm);
-        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-      } else {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = (gk < K && gm + c < M) ? A[static_cast<int64_t>(gk) * lda + gm + c] : 0.0f;
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const unsigned short h = f2bf(v[c]);
-        Ah[(mm + c) * kB3LD + kk] = h;
-        Al[(mm + c) * kB3LD + kk] = f2bf(v[c] - bf2f(h));
-      }
-    }
-    // B tile: 16 (k) x 128 (n), k contiguous in memory -> two float4 per thread
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const int q = p * 256 + t;
-      const int kk = (q % 4) * 4, nn = q / 4;
-      const int gk = k0 + kk, gn = n0 + nn;
-      float v[4];
-      if (gn < N && gk + 4 <= K) {
-        const float4 x = *reinterpret_cast<const float4*>(B + static_cast<int64_t>(gn) * ldb + gk);
-        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-      } else {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = (gn < N && gk + c < K) ? B[static_cast<int64_t>(gn) * ldb + gk + c] : 0.0f;
-      }
-      ushort4 hh, ll;
-      unsigned short* ph = reinterpret_cast<unsigned short*>(&hh);
-      unsigned short* pl = reinterpret_cast<unsigned short*>(&ll);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        ph[c] = f2bf(v[c]);
-        pl[c] = f2bf(v[c] - bf2f(ph[c]));
-      }
-      *reinterpret_cast<ushort4*>(&Bh[nn * kB3LD + kk]) = hh;
-      *reinterpret_cast<ushort4*>(&Bl[nn * kB3LD + kk]) = ll;
-    }
-    __syncthreads();
-    const int row = lane & 31, kofs = (lane >> 5) * 8;
-    bf16x8 ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int m = wm * 64 + i * 32 + row;
-      ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[m * kB3LD + kofs]);
-      al[i] = *reinterpret_cast<const bf16x8*>(&Al[m * kB3LD + kofs]);
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int nn = wn * 64 + j * 32 + row;
-      bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[nn * kB3LD + kofs]);
-      bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[nn * kB3LD + kofs]);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-      }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + wn * 64 + j * 32 + (lane & 31);
-      if (col >= N) continue;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int rr = m0 + wm * 64 + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        if (rr < M) Y[static_cast<int64_t>(col) * ldy + rr] = acc[i][j][r];
-      }
-    }
-}
-
 }  // namespace
 
 hipError_t launch_sample_gemm_f64(hipStream_t st, int n, int lam, const double* BD, int ldbd, const double* Z,
@@ -765,15 +643,6 @@ void syrk_plan_f64(int n, int K, int* ntl, int* splits, int* kspan, size_t* work
   *kspan = round_up(ceil_div(std::max(K, 1), s), bk);
   *splits = ceil_div(std::max(K, 1), *kspan);
   *work_elems = static_cast<size_t>(*splits) * (*ntl) * bm * bm;
-}
-
-hipError_t launch_sample_gemm_bf16x3(hipStream_t st, int n, int lam, const float* BD, int ldbd, const float* Z,
-                                     int ldz, float* Y, int ldy) {
-  if ((ldbd & 3) || (ldz & 3)) return hipErrorInvalidValue;
-  const int tiles = ceil_div(n, kB3M) * ceil_div(lam, kB3N);
-  if (tiles == 0) return hipSuccess;
-  k_gemm_bf16x3<<<tiles, 256, 0, st>>>(n, lam, n, BD, ldbd, Z, ldz, Y, ldy);
-  return hipGetLastError();
 }
 
 hipError_t launch_syrk_update_f64(hipStream_t st, int n, int mu, const double* Ysel, const double* Ysel2, int ldsel,

@@ -15,7 +15,6 @@
 //    over the 8 XCDs, so workgroup w is given tile (w mod 8) * T/8 + w / 8 and
 //    each XCD walks a contiguous run of tiles that share their B columns in
 //    its own L2.
-#include <hip/hip_ext.h>
 
 #include <algorithm>
 
@@ -510,19 +509,6 @@ hipError_t launch_group_syrk_cfg(hipStream_t st, const GFront* g, const int* off
   if (wgs_syrk > 0) kg_syrk32<BM, BK, NT><<<wgs_syrk, NT, 0, st>>>(g, off_syrk, count);
   if (wgs_epi > 0) kg_syrk32_epi<BM><<<wgs_epi, 256, 0, st>>>(g, off_epi, count);
   return hipGetLastError();
-}
-
-// a launch that, while the kernel timer is on, records the dispatch's own
-// start and end timestamps (hipExtLaunchKernelGGL), so its measured duration
-// is the kernel's alone, without the marker packets of separate events
-template <typename... Formals, typename... Actuals>
-void timed_launch(KTimer* kt, int kid, void (*kern)(Formals...), int grid, int block, hipStream_t st,
-                  Actuals... args) {
-  hipEvent_t t0, t1;
-  if (kt_ext(kt, kid, &t0, &t1))
-    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, t0, t1, 0, static_cast<Formals>(args)...);
-  else
-    kern<<<grid, block, 0, st>>>(static_cast<Formals>(args)...);
 }
 
 template <int BM, int BN, int BK>

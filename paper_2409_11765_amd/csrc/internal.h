@@ -1,6 +1,7 @@
 // Internal declarations shared by the HIP translation units of the library.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -83,6 +84,19 @@ inline bool kt_ext(KTimer* t, int kid, hipEvent_t* start, hipEvent_t* stop) {
   return true;
 }
 
+// A launch that, while the kernel timer is on, records the dispatch's own
+// start and end timestamps (hipExtLaunchKernelGGL), so its measured duration
+// is the kernel's alone, without the marker packets of separate events.
+template <typename... Formals, typename... Actuals>
+void timed_launch(KTimer* kt, int kid, void (*kern)(Formals...), int grid, int block, hipStream_t st,
+                  Actuals... args) {
+  hipEvent_t t0, t1;
+  if (kt_ext(kt, kid, &t0, &t1))
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, t0, t1, 0, static_cast<Formals>(args)...);
+  else
+    kern<<<grid, block, 0, st>>>(static_cast<Formals>(args)...);
+}
+
 // ---- error plumbing -------------------------------------------------------
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
@@ -116,9 +130,11 @@ struct FitnessArgs {
 };
 hipError_t launch_sample_gemm_f64(hipStream_t st, int n, int lam, const double* BD, int ldbd, const double* Z,
                                   int ldz, double* Y, int ldy);
-// y = (B D) z as bf16 x 3 split products with float32 accumulation
+// y = (B D) z as bf16 x 3 split products with float32 accumulation; `work`
+// holds the split operands (bf16x3_work_bytes(n, lam) bytes)
+size_t bf16x3_work_bytes(int n, int lam);
 hipError_t launch_sample_gemm_bf16x3(hipStream_t st, int n, int lam, const float* BD, int ldbd, const float* Z,
-                                     int ldz, float* Y, int ldy);
+                                     int ldz, float* Y, int ldy, void* work, KTimer* kt, int kid);
 hipError_t launch_fitness_gemm_f64(hipStream_t st, int n, int lam, const double* R, int ldr, const double* Y, int ldy,
                                    const FitnessArgs& fa, int* row_tiles);
 hipError_t launch_fitness_direct(hipStream_t st, bool fp64, int n, int lam, const void* Y, int ldy,
