@@ -163,3 +163,28 @@ def test_integer_inputs_give_exact_fitness(P, precision, cfg):
     f = np.sum(X * X, axis=0)
     assert np.array_equal(s["f"], f)
     assert np.array_equal(s["order"], np.argsort(f, kind="stable"))
+
+
+@pytest.mark.parametrize("n,lam", [(2, 5), (37, 53), (64, 128), (257, 512), (300, 1100)])
+def test_integer_inputs_give_exact_fitness_bf16x3(P, n, lam):
+    """The same exactness check for the bf16 x 3 sampling product: operands
+    of at most two significant bits are bf16 numbers (lo = 0), so the three
+    products sum exactly in float32.  The shapes cover a single partial tile,
+    exact tile edges, a ragged edge in both dimensions, a launch of 8 tiles
+    (one run per XCD) and one of 18 (plain order)."""
+    g = synth.rng(92 + n)
+    perm = g.permutation(n)
+    B = np.zeros((n, n))
+    B[perm, np.arange(n)] = g.choice([-1.0, 1.0], n)
+    D = g.integers(1, 4, n).astype(np.float64)
+    st = {"n": n, "lambda": lam, "m": g.integers(-3, 4, n).astype(np.float64), "sigma": 0.5,
+          "C": (B * D ** 2) @ B.T, "B": B, "D": D, "p_sigma": np.zeros(n), "p_c": np.zeros(n), "gen": 3}
+    Z = g.integers(-4, 5, (n, lam)).astype(np.float64)
+    with P.CMAES(n, lam, 1.0, seed=1, precision="mixed_bf16x3", objective="sphere", xstar=np.zeros(n)) as es:
+        es.set_state(st)
+        es.generation_with_z(Z)
+        s = es.state()
+    X = st["m"][:, None] + 0.5 * (B @ (D[:, None] * Z))
+    f = np.sum(X * X, axis=0)
+    assert np.array_equal(s["f"], f)
+    assert np.array_equal(s["order"], np.argsort(f, kind="stable"))
