@@ -216,6 +216,10 @@ void dev_free(cmaes* h, P*& p) {
 
 size_t esz(const cmaes* h) { return h->fp64 ? sizeof(double) : sizeof(float); }
 
+// f_best as of the handle's last stop tests: the mapped host copy the stop
+// kernel writes next to the stop bits
+double* host_fbest(const cmaes* h) { return reinterpret_cast<double*>(h->hstop + 2); }
+
 void free_pop_buffers(cmaes* h) {
   if (h->st) (void)hipStreamSynchronize(h->st);  // nothing in flight uses the buffers
   dev_free(h, h->Z);
@@ -464,6 +468,7 @@ int init_descent(cmaes* h, bool fresh) {
   CMX_HIP(hipMemsetAsync(h->ew.gctl, 0, 4ull * GC_WORDS, h->st));  // no previous solve
   CMX_HIP(hipStreamSynchronize(h->st));  // s and ones are consumed
   *h->hstop = 0;
+  *host_fbest(h) = f_best;
   h->stop_pending = false;
   h->gen = 0;
   h->evals = 0;
@@ -842,6 +847,25 @@ int front(cmaes* h) {
 int read_scalars(const cmaes* h, DevScalars* s) {
   CMX_HIP(hipMemcpyAsync(s, h->sc, sizeof(*s), hipMemcpyDeviceToHost, h->st));
   CMX_HIP(hipStreamSynchronize(h->st));
+  return 0;
+}
+
+// The stop bits and f_best after everything queued on the handle's stream,
+// read from the mapped host copy: one stream synchronisation (none with
+// sync = false, for a caller that has already waited for that work) and no
+// copy.
+int read_stop_best(const cmaes* h, uint32_t* stop, double* f_best, bool sync = true) {
+  if (!h->allocated) {  // no generation and no state yet
+    if (stop) *stop = 0;
+    if (f_best) *f_best = HUGE_VAL;
+    return 0;
+  }
+  if (sync) CMX_HIP(hipStreamSynchronize(h->st));
+  if (stop) *stop = __atomic_load_n(h->hstop, __ATOMIC_ACQUIRE);
+  if (f_best) {
+    const uint64_t bits = __atomic_load_n(reinterpret_cast<const uint64_t*>(h->hstop + 2), __ATOMIC_ACQUIRE);
+    std::memcpy(f_best, &bits, sizeof(bits));
+  }
   return 0;
 }
 
@@ -1269,6 +1293,7 @@ int cmaes_set_state(cmaes_t* h, const cmaes_state_t* in) {
   }
   CMX_HIP(hipStreamSynchronize(h->st));
   *h->hstop = 0;  // the stop bits were cleared
+  *host_fbest(h) = s.f_best;
   h->stop_pending = false;
   h->ask_pending = false;
   return CMAES_OK;
@@ -1486,6 +1511,9 @@ struct LockstepGroup {
   std::vector<int> sweeps;
   FrontTables ft;
   std::vector<cmaes*> fmembers;  // the descents the front tables were built for
+  // the last lockstep generation ended with the host waiting for the group,
+  // so every member's stream was idle and its stop copy current on return
+  bool synced = false;
 };
 
 int group_init(LockstepGroup& g) {
@@ -1605,6 +1633,7 @@ int build_front_tables(LockstepGroup& g, const std::vector<cmaes*>& hs) {
     e.k1 = static_cast<uint32_t>(h->seed >> 32);
     e.restart = static_cast<uint32_t>(h->restart);
     e.sc = h->sc;
+    e.hstop = h->dstop;
     e.BD = static_cast<const float*>(h->BD);
     e.Z = static_cast<float*>(h->Z);
     e.Y = static_cast<float*>(h->Y);
@@ -1799,6 +1828,12 @@ int lockstep_generation(LockstepGroup& g, const std::vector<cmaes*>& hs) {
       g.ev.push_back(e);
     }
     for (int i = 0; i < count; ++i) {
+      // a descent's stream is usually idle here (the calls between
+      // generations wait for their own work); only one with work still
+      // queued needs the event
+      const hipError_t q = hipStreamQuery(hs[i]->st);
+      (void)hipGetLastError();  // a not-ready query is not an error of the next launch
+      if (q == hipSuccess) continue;
       CMX_HIP(hipEventRecord(g.ev[i], hs[i]->st));
       CMX_HIP(hipStreamWaitEvent(g.st, g.ev[i], 0));
     }
@@ -1876,13 +1911,15 @@ int lockstep_generation(LockstepGroup& g, const std::vector<cmaes*>& hs) {
                                                    sizeof(GDgemm) * kFrontMM * kGroupMax);
     CMX_HIP(launch_group_update(g.st, GF_STOP, reinterpret_cast<const GFront*>(base), offd + GF_STOP * (count + 1),
                                 count, ft.off[GF_STOP * (count + 1) + count], nullptr));
-    CMX_HIP(hipEventRecord(g.done, g.st));
-    for (cmaes* h : hs) {
-      CMX_HIP(hipStreamWaitEvent(h->st, g.done, 0));
-      h->stop_pending = false;
-    }
+    // the host waits for the group (the callers read every descent's stop
+    // bits next anyway), so later work on a descent's own stream is ordered
+    // after the group without an event wait per stream
+    CMX_HIP(hipStreamSynchronize(g.st));
+    for (cmaes* h : hs) h->stop_pending = false;
+    g.synced = true;
     return 0;
   }
+  g.synced = false;
   for (cmaes* h : hs)
     if (int rc = phase_update_post(h)) return rc;
   return 0;
@@ -1970,9 +2007,9 @@ int cmaes_batch_generation(cmaes_batch_t* b) {
   // restart-on-finish with the same population size
   for (size_t k = 0; k < b->inst.size(); ++k) {
     cmaes* h = b->inst[k];
-    DevScalars s;
-    if (int rc = read_scalars(h, &s)) return rc;
-    if (s.stop) {
+    uint32_t stop = 0;
+    if (int rc = read_stop_best(h, &stop, nullptr, !b->grp.synced)) return rc;
+    if (stop) {
       if (int rc = restart_same_lambda(h)) return rc;
       b->restarts[k] += 1;
     }
@@ -1990,10 +2027,10 @@ int cmaes_batch_best(const cmaes_batch_t* b, double* f_best, int* k_best) {
   double best = HUGE_VAL;
   int arg = -1;
   for (size_t k = 0; k < b->inst.size(); ++k) {
-    DevScalars s;
-    if (int rc = read_scalars(b->inst[k], &s)) return rc;
-    if (s.f_best < best) {
-      best = s.f_best;
+    double fb = HUGE_VAL;
+    if (int rc = read_stop_best(b->inst[k], nullptr, &fb)) return rc;
+    if (fb < best) {
+      best = fb;
       arg = static_cast<int>(k);
     }
   }
@@ -2154,17 +2191,20 @@ int cmaes_krep_generation(cmaes_krep_t* r) {
   if (int rc = lockstep_generation(r->grp, run)) return rc;
   r->lockstep_gens += 1;
   double best = r->released_best;
+  // the members' streams are idle after a synchronised lockstep generation,
+  // and the other descents' streams were left idle by their last call
+  const bool sync = !r->grp.synced;
   for (size_t i = 0; i < run.size(); ++i) {
-    DevScalars sc;
-    if (int rc = read_scalars(run[i], &sc)) return rc;
+    uint32_t stop = 0;
+    if (int rc = read_stop_best(run[i], &stop, nullptr, sync)) return rc;
     r->gens[slot[i]] += 1;
-    if (sc.stop) r->finished[slot[i]] = 1;
+    if (stop) r->finished[slot[i]] = 1;
   }
   for (cmaes* h : r->handle)
     if (h) {
-      DevScalars sc;
-      if (int rc = read_scalars(h, &sc)) return rc;
-      best = std::min(best, sc.f_best);
+      double fb = HUGE_VAL;
+      if (int rc = read_stop_best(h, nullptr, &fb, sync)) return rc;
+      best = std::min(best, fb);
     }
   // merge finished sibling pairs into their parent (Alg. 3: the control flows
   // back to the parent communicator once both halves are done)
@@ -2174,9 +2214,9 @@ int cmaes_krep_generation(cmaes_krep_t* r) {
       if (r->handle[p] || r->finished[p] || !r->finished[a] || !r->finished[b]) continue;
       cmaes* hb = r->handle[b];
       if (hb) {
-        DevScalars sb;
-        if (int rc = read_scalars(hb, &sb)) return rc;
-        r->released_best = std::min(r->released_best, sb.f_best);
+        double fb = HUGE_VAL;
+        if (int rc = read_stop_best(hb, nullptr, &fb, sync)) return rc;
+        r->released_best = std::min(r->released_best, fb);
         r->released_evals += hb->total_evals;
         r->handle[b] = nullptr;
         cmaes_destroy(hb);
@@ -2208,9 +2248,10 @@ int cmaes_krep_status(const cmaes_krep_t* r, cmaes_krep_status_t* out) {
         out->running += 1;
         lmax = std::max(lmax, h->lam);
       }
-      DevScalars sc;
-      if (int rc = read_scalars(const_cast<cmaes*>(h), &sc)) return rc;
-      best = std::min(best, sc.f_best);
+      double fb = HUGE_VAL;
+      // after a synchronised lockstep generation every descent's stream is idle
+      if (int rc = read_stop_best(h, nullptr, &fb, !r->grp.synced)) return rc;
+      best = std::min(best, fb);
       evals += h->total_evals;
     }
   out->lambda_max_running = lmax;

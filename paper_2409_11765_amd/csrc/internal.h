@@ -345,6 +345,7 @@ struct GFront {  // one descent (device table entry)
   int n, lam, mu, ldn, N;
   uint32_t k0, k1, restart;
   DevScalars* sc;
+  uint32_t* hstop;  // device address of the host's mapped copy of the stop bits and f_best
   const float* BD;
   float* Z;
   float* Y;

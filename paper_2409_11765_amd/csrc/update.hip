@@ -359,9 +359,15 @@ __device__ __forceinline__ void stop_body(const KParams& kp, const StopParams& s
   if (sp.max_evals > 0 && sc->evals >= sp.max_evals) bits |= 1u << 8;
   if (nonfinite || !isfinite(sigma)) bits |= 1u << 9;
   sc->stop = bits;
-  // the host's copy of the bits (pinned, mapped host memory): a system-scope
-  // store, read by the host after the end of this kernel
-  if (hstop) __hip_atomic_store(hstop, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  // the host's copy of the bits and of f_best (pinned, mapped host memory:
+  // the bits at hstop[0], f_best at hstop[2..3]): system-scope stores, read
+  // by the host after the end of this kernel
+  if (hstop) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(hstop + 2),
+                       static_cast<unsigned long long>(__double_as_longlong(sc->f_best)), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(hstop, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 __global__ void __launch_bounds__(256) k_stop(KParams kp, StopParams sp, const double* __restrict__ m,
@@ -660,7 +666,7 @@ __global__ void __launch_bounds__(256) kg_update256(int kind, const GFront* __re
     case GF_POLAR:
       if (due_mask_bit(mask, i)) polar_body(w, e.n, e.B, e.ldn, e.T, e.ldn);
       break;
-    case GF_STOP: stop_body(e.kp, e.sp, e.m, e.C, e.ldn, e.B, e.ldn, e.D, e.pc, e.hist, e.sc, nullptr); break;
+    case GF_STOP: stop_body(e.kp, e.sp, e.m, e.C, e.ldn, e.B, e.ldn, e.D, e.pc, e.hist, e.sc, e.hstop); break;
     default: break;
   }
 }

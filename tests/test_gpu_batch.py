@@ -65,6 +65,30 @@ def test_batch_restart_on_finish_keeps_lambda(P):
     assert kb in (0, 1) and f == min(s[0]["f_best"], s[1]["f_best"])
 
 
+def test_grouped_batch_restart_on_finish_and_best(P):
+    """The same on the grouped front (mixed precision, rotated objectives):
+    the stop bits and f_best the host reads after a batch generation come
+    from the stop kernel's mapped copy, and must agree with each descent's
+    state."""
+    ns, lams = [12, 30], [8, 16]
+    with P.CMAESBatch(ns, lams, [2.0, 2.0], [1, 2], precision="mixed", max_gens=3) as b:
+        for k, n in enumerate(ns):
+            R, xs = synth.problem(n, 40 + k)
+            b.set_objective(k, "rastrigin", R, xs)
+        f0, k0 = b.best()
+        assert k0 == -1 and f0 == np.inf    # no generation yet
+        for g in range(4):
+            b.generation()
+            s = [b.state(k, arrays=False) for k in range(2)]
+            f, kb = b.best()
+            assert f == min(s[0]["f_best"], s[1]["f_best"]) and s[kb]["f_best"] == f
+    for k, lam in enumerate(lams):
+        assert s[k]["lambda"] == lam
+        assert s[k]["restart"] == 1
+        assert s[k]["gen"] == 1
+        assert s[k]["total_evals"] == 4 * lam
+
+
 def test_concurrent_restart_workload_runs(P):
     """10 instances, n = 200, lambda_k = 19 * 2^k (k = 0..9), rotated Rastrigin
     with per-instance seeds, mixed precision."""
