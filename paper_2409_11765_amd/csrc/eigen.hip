@@ -950,48 +950,61 @@ __global__ void __launch_bounds__(256) k_permute(const double* __restrict__ Bn, 
 
 __device__ __forceinline__ bool due_bit(const GroupDueMask& m, int i) { return (m.w[i >> 5] >> (i & 31)) & 1u; }
 
-// one workgroup per descent: whether its solve sweeps at all (from the warm
-// start's flags and the previous solve's sweep count, as the single-descent
-// solve decides), and the control words of the solve
-__global__ void __launch_bounds__(64) kg_start(const GEigDesc* __restrict__ g, int count, GroupDueMask due,
-                                                int max_sweeps, int* __restrict__ hactive,
-                                                int* __restrict__ hsweeps) {
-  const int i = blockIdx.x;
-  if (i >= count || threadIdx.x != 0 || g[i].N == kS) return;  // N = 32: kg_small_solve
-  int* c = g[i].ctl;
-  const int d = due_bit(due, i) ? 1 : 0;
-  c[GC_DUE] = d;
-  if (!d) return;
-  const int last = c[GC_LAST];
-  const int mins = last >= 2 ? min(last - 1, max_sweeps) : 0;
-  const int more = c[GC_MORE], nonfin = c[GC_NONFIN];
-  const bool active = mins > 0 || (more && !nonfin);
-  c[GC_MIN] = mins;
-  c[GC_CNT] = 0;
-  if (active) {
-    c[GC_STOPR] = 0x7fffffff;
-    __hip_atomic_fetch_add(hactive, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  } else {
-    c[GC_STOPR] = 0;
-    c[GC_LAST] = 0;
-    int* st = g[i].status;
-    st[0] = nonfin ? 3 : (more ? 2 : 1);
-    st[1] = 0;
-    st[2] = 0;
-    __hip_atomic_store(&hsweeps[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&hsweeps[kGroupMax + i], st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+// whether each descent's solve sweeps at all (from the warm start's flags and
+// the previous solve's sweep count, as the single-descent solve decides), and
+// the control words of the solve; one workgroup, a thread per descent.  The
+// number of sweeping descents goes to the device counter dactive and, in one
+// system-scope store, to the host's copy (per-descent atomics on host memory
+// would each make a round trip over the bus, one after another).
+__global__ void __launch_bounds__(256) kg_start(const GEigDesc* __restrict__ g, int count, GroupDueMask due,
+                                                int max_sweeps, int* __restrict__ dactive,
+                                                int* __restrict__ hactive, int* __restrict__ hsweeps) {
+  __shared__ int cnt[256];
+  int act = 0;
+  for (int i = threadIdx.x; i < count; i += 256) {
+    if (g[i].N == kS) continue;  // N = 32: kg_small_solve
+    int* c = g[i].ctl;
+    const int d = due_bit(due, i) ? 1 : 0;
+    c[GC_DUE] = d;
+    if (!d) continue;
+    const int last = c[GC_LAST];
+    const int mins = last >= 2 ? min(last - 1, max_sweeps) : 0;
+    const int more = c[GC_MORE], nonfin = c[GC_NONFIN];
+    const bool active = mins > 0 || (more && !nonfin);
+    c[GC_MIN] = mins;
+    c[GC_CNT] = 0;
+    if (active) {
+      c[GC_STOPR] = 0x7fffffff;
+      ++act;
+    } else {
+      c[GC_STOPR] = 0;
+      c[GC_LAST] = 0;
+      int* st = g[i].status;
+      st[0] = nonfin ? 3 : (more ? 2 : 1);
+      st[1] = 0;
+      st[2] = 0;
+      __hip_atomic_store(&hsweeps[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&hsweeps[kGroupMax + i], st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+  cnt[threadIdx.x] = act;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) cnt[threadIdx.x] += cnt[threadIdx.x + s2];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(dactive, cnt[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(hactive, cnt[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
-// the first pair solves (round 0 with the intra-block rotations) of every
-// sweeping descent, from its warm-started A
-__global__ void __launch_bounds__(256) kg_first(const GEigDesc* __restrict__ g, const int* __restrict__ off,
-                                                int count) {
-  __shared__ double lds[3 * kS * kLD];
-  const int i = group_find(off, count, blockIdx.x);
-  const GEigDesc& e = g[i];
-  if (!e.ctl[GC_DUE] || e.ctl[GC_STOPR] == 0) return;
-  jac_first_body(blockIdx.x - off[i], e.A, e.N, e.n, e.N / kNB, e.scale, e.Q, lds);
+// the device count of sweeping descents into the host's copy (after a batch
+// of rounds; the host reads it once the stream has drained)
+__global__ void kg_publish(const int* __restrict__ dactive, int* __restrict__ hactive) {
+  if (threadIdx.x == 0)
+    __hip_atomic_store(hactive, __hip_atomic_load(dactive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // global round rg of the group: descent i runs its round rg mod (p_i - 1)
@@ -1000,7 +1013,7 @@ __global__ void __launch_bounds__(256) kg_first(const GEigDesc* __restrict__ g, 
 // scale that sets the rotation threshold is double buffered by sweep parity:
 // sweep s reads scale[s & 1], its closing workgroup writes scale[(s + 1) & 1].
 __global__ void __launch_bounds__(256) kg_round(const GEigDesc* __restrict__ g, const int* __restrict__ off,
-                                                int count, int rg, int max_sweeps, int* __restrict__ hactive,
+                                                int count, int rg, int max_sweeps, int* __restrict__ dactive,
                                                 int* __restrict__ hsweeps) {
   __shared__ double lds[kRoundLds];
   __shared__ double red[3][256];
@@ -1041,7 +1054,7 @@ __global__ void __launch_bounds__(256) kg_round(const GEigDesc* __restrict__ g, 
   st[2] = 0;
   __hip_atomic_store(&hsweeps[i], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   __hip_atomic_store(&hsweeps[kGroupMax + i], st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_fetch_add(hactive, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_fetch_add(dactive, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---- whole solve of a descent with N = 32 (n <= 32) in one workgroup, from
@@ -1531,9 +1544,11 @@ int group_eig_build(hipStream_t st, GroupEig& ge, const std::vector<GEigDesc>& d
   if (ge.cap < count) {
     group_eig_release(ge);
     void* d = nullptr;
-    if (hipMalloc(&d, sizeof(GEigDesc) * kGroupMax + sizeof(int) * kGroupKinds * (kGroupMax + 1)) != hipSuccess)
-      return fail(-2, "grouped eigensolve: hipMalloc failed");
+    const size_t tab_off = sizeof(GEigDesc) * kGroupMax + sizeof(int) * kGroupKinds * (kGroupMax + 1);
+    const size_t cnt_off = (tab_off + 255) / 256 * 256;  // the device count of sweeping descents
+    if (hipMalloc(&d, cnt_off + 256) != hipSuccess) return fail(-2, "grouped eigensolve: hipMalloc failed");
     ge.dtab = d;
+    ge.dactive = reinterpret_cast<int*>(static_cast<char*>(d) + cnt_off);
     void* hf = nullptr;
     if (hipHostMalloc(&hf, sizeof(int) * (2 * kGroupMax + 1), hipHostMallocMapped | hipHostMallocCoherent) !=
         hipSuccess)
@@ -1582,7 +1597,7 @@ int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int m
     read_out();
     return 0;
   }
-  kg_start<<<count, 64, 0, st>>>(tab, count, due, max_sweeps, hactive, hsweeps);
+  kg_start<<<1, 256, 0, st>>>(tab, count, due, max_sweeps, ge.dactive, hactive, hsweeps);
   kg_first<<<wgs_of(0), 256, 0, st>>>(tab, off_of(0), count);
   CMX_HIP(hipGetLastError());
   // sweeps: every batch is one sweep of the largest descent (p_max - 1
@@ -1599,7 +1614,8 @@ int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int m
   int rg = 0;
   auto queue_batch = [&]() -> int {
     for (int r = 0; r < rounds; ++r, ++rg)
-      kg_round<<<wgs_of(1), 256, 0, st>>>(tab, off_of(1), count, rg, max_sweeps, hactive, hsweeps);
+      kg_round<<<wgs_of(1), 256, 0, st>>>(tab, off_of(1), count, rg, max_sweeps, ge.dactive, hsweeps);
+    kg_publish<<<1, 64, 0, st>>>(ge.dactive, hactive);
     CMX_HIP(hipGetLastError());
     return 0;
   };

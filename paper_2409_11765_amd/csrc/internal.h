@@ -304,6 +304,7 @@ struct GroupEig {
   int* hflags = nullptr;  // pinned, mapped: [0] descents still sweeping, [1 + i] sweeps of descent i,
                           // [1 + kGroupMax + i] its status (1 converged, 2 sweep limit, 3 non-finite)
   int* dflags = nullptr;  // device address of hflags
+  int* dactive = nullptr; // device memory: descents still sweeping (copied into hflags[0] after each batch)
   int cap = 0, count = 0, pmax = 2;
   int nsmall = 0;         // descents with N = kWholeSolveN (solved whole by one workgroup each)
   std::vector<int> off;   // host copy of the offsets (kGroupKinds x (count + 1))
