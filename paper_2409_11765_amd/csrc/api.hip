@@ -1903,8 +1903,8 @@ int lockstep_generation(LockstepGroup& g, const std::vector<cmaes*>& hs) {
       }
   }
   if (grouped) {
-    // the stop tests of every descent, then each descent's stream waits for
-    // the group (its state is read there)
+    // the stop tests of every descent (they also write its mapped copy of
+    // the stop bits and f_best)
     const FrontTables& ft = g.ft;
     const char* base = static_cast<const char*>(ft.dmem);
     const int* offd = reinterpret_cast<const int*>(base + sizeof(GFront) * kGroupMax +

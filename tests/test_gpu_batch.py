@@ -23,7 +23,7 @@ def P():
     return P
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_bf16x3"])
 def test_batch_instance_equals_solo_run(P, precision):
     ns, lams, seeds = [10, 37, 64], [10, 20, 40], [5, 6, 7]
     sig = [2.0, 1.5, 1.0]
