@@ -1007,6 +1007,17 @@ __global__ void kg_publish(const int* __restrict__ dactive, int* __restrict__ ha
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// the first pair solves (round 0 with the intra-block rotations) of every
+// sweeping descent, from its warm-started A
+__global__ void __launch_bounds__(256) kg_first(const GEigDesc* __restrict__ g, const int* __restrict__ off,
+                                                int count) {
+  __shared__ double lds[3 * kS * kLD];
+  const int i = group_find(off, count, blockIdx.x);
+  const GEigDesc& e = g[i];
+  if (!e.ctl[GC_DUE] || e.ctl[GC_STOPR] == 0) return;
+  jac_first_body(blockIdx.x - off[i], e.A, e.N, e.n, e.N / kNB, e.scale, e.Q, lds);
+}
+
 // global round rg of the group: descent i runs its round rg mod (p_i - 1)
 // (every descent starts its first sweep at rg = 0) until the round after the
 // one in which it stopped; A and Q ping-pong with the parity of rg.  The
