@@ -518,7 +518,7 @@ __device__ __forceinline__ void jac_round_body(int b, const double* __restrict__
       red[3 * w + 2] = dmax;
     }
     __syncthreads();
-    if (t == 0) {
+    if (t == 0 && tilepart) {  // null: a round whose norms nobody reads
       tilepart[3 * b + 0] = ((red[0] + red[3]) + red[6]) + red[9];
       tilepart[3 * b + 1] = ((red[1] + red[4]) + red[7]) + red[10];
       tilepart[3 * b + 2] = fmax(fmax(red[2], red[5]), fmax(red[8], red[11]));
@@ -942,9 +942,9 @@ __global__ void __launch_bounds__(256) k_permute(const double* __restrict__ Bn, 
 // descriptor table, uneven n allowed) advance together, one launch per round
 // for all of them.  Each launch's workgroups are split over the descents by a
 // prefix-sum table (workgroup w belongs to descent i with off[i] <= w <
-// off[i + 1]); a descent's convergence is decided on the device, at the end
-// of each of its sweeps, by the last of its tile workgroups to finish (a
-// counter in its control block), so the host only waits for the whole group.
+// off[i + 1]); a descent's convergence is decided on the device, after each
+// of its sweeps, at the start of the next round (see kg_round), so the host
+// only waits for the whole group.
 // The arithmetic of every step is that of the single-descent solve (the same
 // bodies, the same reduction order), without the closing correction.
 
@@ -972,7 +972,6 @@ __global__ void __launch_bounds__(256) kg_start(const GEigDesc* __restrict__ g, 
     const int more = c[GC_MORE], nonfin = c[GC_NONFIN];
     const bool active = mins > 0 || (more && !nonfin);
     c[GC_MIN] = mins;
-    c[GC_CNT] = 0;
     if (active) {
       c[GC_STOPR] = 0x7fffffff;
       ++act;
@@ -999,14 +998,6 @@ __global__ void __launch_bounds__(256) kg_start(const GEigDesc* __restrict__ g, 
   }
 }
 
-// the device count of sweeping descents into the host's copy (after a batch
-// of rounds; the host reads it once the stream has drained)
-__global__ void kg_publish(const int* __restrict__ dactive, int* __restrict__ hactive) {
-  if (threadIdx.x == 0)
-    __hip_atomic_store(hactive, __hip_atomic_load(dactive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
 // the first pair solves (round 0 with the intra-block rotations) of every
 // sweeping descent, from its warm-started A
 __global__ void __launch_bounds__(256) kg_first(const GEigDesc* __restrict__ g, const int* __restrict__ off,
@@ -1022,50 +1013,83 @@ __global__ void __launch_bounds__(256) kg_first(const GEigDesc* __restrict__ g, 
 // (every descent starts its first sweep at rg = 0) until the round after the
 // one in which it stopped; A and Q ping-pong with the parity of rg.  The
 // scale that sets the rotation threshold is double buffered by sweep parity:
-// sweep s reads scale[s & 1], its closing workgroup writes scale[(s + 1) & 1].
-__global__ void __launch_bounds__(256) kg_round(const GEigDesc* __restrict__ g, const int* __restrict__ off,
-                                                int count, int rg, int max_sweeps, int* __restrict__ dactive,
+// sweep s reads scale[s & 1], written when sweep s - 1 is decided.
+// The launch puts every descent's pair solves first (offq: prefix sums of
+// the q_i), then the tile and V workgroups (off: prefix sums of whole rounds,
+// so off[i] - offq[i] is descent i's first tile-or-V workgroup): the pair
+// solves, the round's critical path, are then dispatched ahead of the rest
+// and spread over distinct CUs instead of sharing some CUs two by two.
+__device__ __forceinline__ void round_slot(const int* __restrict__ offq, const int* __restrict__ off, int count,
+                                           int w, int& i, int& b) {
+  const int tq = offq[count];
+  if (w < tq) {
+    i = group_find(offq, count, w);
+    b = w - offq[i];
+    return;
+  }
+  w -= tq;
+  int lo = 0, hi = count;  // the last i with off[i] - offq[i] <= w
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] - offq[mid] <= w) lo = mid;
+    else hi = mid;
+  }
+  i = lo;
+  b = (offq[i + 1] - offq[i]) + (w - (off[i] - offq[i]));
+}
+
+// The decision on sweep s (more sweeps, the next rotation threshold) is
+// taken at the start of the next launch, the first round of sweep s + 1, by
+// every workgroup of the descent alike: each sums the partial norms of sweep
+// s's last round in the same fixed order, so all reach the same decision
+// without waiting for one another; workgroup 0 records it.  Only that last
+// round writes the partial sums.  (Deciding inside the last round instead
+// needs a device-wide fence in every tile workgroup, an L2 write-back and
+// invalidate each, which slowed the pair solves running beside them; a
+// launch of its own between the rounds costs a dependent launch per sweep.)
+__global__ void __launch_bounds__(256) kg_round(const GEigDesc* __restrict__ g, const int* __restrict__ offq,
+                                                const int* __restrict__ off, int count, int rg, int max_sweeps,
+                                                int* __restrict__ dactive, int* __restrict__ hactive,
                                                 int* __restrict__ hsweeps) {
   __shared__ double lds[kRoundLds];
   __shared__ double red[3][256];
-  __shared__ int last;
-  const int i = group_find(off, count, blockIdx.x);
+  int i, b;
+  round_slot(offq, off, count, blockIdx.x, i, b);
   const GEigDesc& e = g[i];
   int* c = e.ctl;
   if (!c[GC_DUE] || rg >= c[GC_STOPR]) return;
   const int N = e.N, p = N / kNB, q = p / 2, ntiles = q * (q + 1) / 2;
   const int rl = rg % (p - 1), sw = rg / (p - 1);
   const bool odd = rg & 1;
-  const int b = blockIdx.x - off[i];
-  jac_round_body(b, odd ? e.A2 : e.A, odd ? e.A : e.A2, e.V, odd ? e.Q2 : e.Q, odd ? e.Q : e.Q2, N, e.n, rl,
-                 e.scale + (sw & 1), e.part, lds);
-  if (rl != p - 2 || b < q || b >= q + ntiles) return;
-  // the end of sweep sw: the last tile workgroup to finish decides
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0)
-    last = (atomicAdd(reinterpret_cast<unsigned int*>(&c[GC_CNT]), 1u) == static_cast<unsigned int>(ntiles - 1));
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  offnorm_reduce(e.part, ntiles, red);
-  if (threadIdx.x != 0) return;
-  c[GC_CNT] = 0;
-  e.scale[(sw + 1) & 1] = red[2][0];
-  int more, nonfin, small;
-  offnorm_flags(red[0][0], red[1][0], more, nonfin, small);
-  const int done = sw + 1;
-  const bool cont = done < max_sweeps && (done < c[GC_MIN] || (more && !nonfin));
-  if (cont) return;
-  c[GC_STOPR] = rg + 1;
-  c[GC_LAST] = done;
-  int* st = e.status;
-  st[0] = nonfin ? 3 : (more ? 2 : 1);
-  st[1] = done;
-  st[2] = 0;
-  __hip_atomic_store(&hsweeps[i], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(&hsweeps[kGroupMax + i], st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_fetch_add(dactive, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double* scale = e.scale + (sw & 1);
+  if (rl == 0 && sw > 0) {
+    offnorm_reduce(e.part, ntiles, red);
+    int more, nonfin, small;
+    offnorm_flags(red[0][0], red[1][0], more, nonfin, small);
+    const int done = sw;
+    const bool cont = done < max_sweeps && (done < c[GC_MIN] || (more && !nonfin));
+    if (b == 0 && threadIdx.x == 0) {
+      if (cont) {
+        e.scale[sw & 1] = red[2][0];
+      } else {
+        c[GC_STOPR] = rg;
+        c[GC_LAST] = done;
+        int* st = e.status;
+        st[0] = nonfin ? 3 : (more ? 2 : 1);
+        st[1] = done;
+        st[2] = 0;
+        __hip_atomic_store(&hsweeps[i], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&hsweeps[kGroupMax + i], st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        // the descent that stops last tells the host (one store over the bus)
+        if (__hip_atomic_fetch_add(dactive, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1)
+          __hip_atomic_store(hactive, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+    if (!cont) return;
+    scale = &red[2][0];  // this launch's pair solves use the new threshold at once
+  }
+  jac_round_body(b, odd ? e.A2 : e.A, odd ? e.A : e.A2, e.V, odd ? e.Q2 : e.Q, odd ? e.Q : e.Q2, N, e.n, rl, scale,
+                 rl == p - 2 ? e.part : nullptr, lds);
 }
 
 // ---- whole solve of a descent with N = 32 (n <= 32) in one workgroup, from
@@ -1625,8 +1649,8 @@ int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int m
   int rg = 0;
   auto queue_batch = [&]() -> int {
     for (int r = 0; r < rounds; ++r, ++rg)
-      kg_round<<<wgs_of(1), 256, 0, st>>>(tab, off_of(1), count, rg, max_sweeps, ge.dactive, hsweeps);
-    kg_publish<<<1, 64, 0, st>>>(ge.dactive, hactive);
+      kg_round<<<wgs_of(1), 256, 0, st>>>(tab, off_of(0), off_of(1), count, rg, max_sweeps, ge.dactive, hactive,
+                                          hsweeps);
     CMX_HIP(hipGetLastError());
     return 0;
   };

@@ -275,8 +275,7 @@ constexpr int kWholeSolveN = 32;
 constexpr int kGroupKinds = 5;   // launch kinds with per-descent workgroups
 // words of a descent's control block (EigWork::gctl); k_offnorm_final of the
 // warm start writes GC_MORE and GC_NONFIN
-enum GroupCtl { GC_STOPR = 0, GC_MIN = 1, GC_LAST = 2, GC_CNT = 3, GC_MORE = 4, GC_NONFIN = 5, GC_DUE = 6,
-                GC_WORDS = 8 };
+enum GroupCtl { GC_STOPR = 0, GC_MIN = 1, GC_LAST = 2, GC_MORE = 4, GC_NONFIN = 5, GC_DUE = 6, GC_WORDS = 8 };
 struct GEigDesc {  // one descent of a grouped solve (device table entry)
   double *A, *A2, *V, *Q, *Q2, *part, *scale;
   const double* C;  // the covariance (read by the single-workgroup solve's warm start)
@@ -304,7 +303,7 @@ struct GroupEig {
   int* hflags = nullptr;  // pinned, mapped: [0] descents still sweeping, [1 + i] sweeps of descent i,
                           // [1 + kGroupMax + i] its status (1 converged, 2 sweep limit, 3 non-finite)
   int* dflags = nullptr;  // device address of hflags
-  int* dactive = nullptr; // device memory: descents still sweeping (copied into hflags[0] after each batch)
+  int* dactive = nullptr; // device memory: descents still sweeping (the last to stop zeroes hflags[0])
   int cap = 0, count = 0, pmax = 2;
   int nsmall = 0;         // descents with N = kWholeSolveN (solved whole by one workgroup each)
   std::vector<int> off;   // host copy of the offsets (kGroupKinds x (count + 1))
