@@ -49,6 +49,35 @@ def test_batch_instance_equals_solo_run(P, precision):
         assert got[k]["sigma"] == want["sigma"] and got[k]["gen"] == want["gen"] == gens
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_of_uneven_block_sizes_equals_solo_runs(P, precision):
+    """Descents whose padded sizes differ (N = 64, 128 and 160: 3, 7 and 9
+    rounds per sweep) share one grouped eigensolve, each deciding its sweeps
+    at its own rounds; every one must still evolve exactly as it does alone
+    (n > 64 alone takes the single-descent block path)."""
+    ns, lams, seeds = [40, 100, 130], [12, 20, 24], [21, 22, 23]
+    sig = [2.0, 1.5, 1.0]
+    gens = 5
+    with P.CMAESBatch(ns, lams, sig, seeds, precision=precision, eigen_interval=1) as b:
+        for k, n in enumerate(ns):
+            R, xs = synth.problem(n, 200 + k)
+            b.set_objective(k, "rastrigin", R, xs)
+        for _ in range(gens):
+            b.generation()
+        got = [b.state(k) for k in range(len(ns))]
+    for k, n in enumerate(ns):
+        R, xs = synth.problem(n, 200 + k)
+        with P.CMAES(n, lams[k], sig[k], seed=seeds[k], precision=precision, objective="rastrigin", R=R,
+                     xstar=xs, eigen_interval=1) as es:
+            es.set_eigen_correction(False)
+            for _ in range(gens):
+                es.generation()
+            want = es.state()
+        for key in ("m", "C", "B", "D", "p_sigma", "p_c", "f"):
+            assert np.array_equal(got[k][key], want[key]), (k, key)
+        assert got[k]["sigma"] == want["sigma"] and got[k]["gen"] == want["gen"] == gens
+
+
 def test_batch_restart_on_finish_keeps_lambda(P):
     with P.CMAESBatch([12, 12], [8, 16], [2.0, 2.0], [1, 2], precision="fp64", max_gens=3) as b:
         for k in range(2):
