@@ -1647,16 +1647,21 @@ int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int m
   const int rounds = ge.pmax - 1;
   const int per_wait = std::max(1, kWaitRounds / rounds);
   int rg = 0;
-  auto queue_batch = [&]() -> int {
-    for (int r = 0; r < rounds; ++r, ++rg)
+  auto queue_rounds = [&](int nr) -> int {
+    for (int r = 0; r < nr; ++r, ++rg)
       kg_round<<<wgs_of(1), 256, 0, st>>>(tab, off_of(0), off_of(1), count, rg, max_sweeps, ge.dactive, hactive,
                                           hsweeps);
     CMX_HIP(hipGetLastError());
     return 0;
   };
+  auto queue_batch = [&]() -> int { return queue_rounds(rounds); };
+  // The first batch ends one round into the next sweep: a sweep is decided
+  // at the start of the round after it, so every wait then follows the
+  // decision on the last sweep queued before it.
   int queued = 0;
   for (; queued < std::min(std::max(ahead, per_wait), max_sweeps); ++queued)
     if (int rc = queue_batch()) return rc;
+  if (int rc = queue_rounds(1)) return rc;
   for (;;) {
     CMX_HIP(hipStreamSynchronize(st));
     if (__atomic_load_n(&ge.hflags[0], __ATOMIC_ACQUIRE) <= 0) break;
