@@ -1019,8 +1019,22 @@ __global__ void __launch_bounds__(256) kg_first(const GEigDesc* __restrict__ g, 
 // so off[i] - offq[i] is descent i's first tile-or-V workgroup): the pair
 // solves, the round's critical path, are then dispatched ahead of the rest
 // and spread over distinct CUs instead of sharing some CUs two by two.
+// uq > 0: every descent of the group has the same q = uq and uq + ur tile
+// and V workgroups, so the slot follows by division (no search).
 __device__ __forceinline__ void round_slot(const int* __restrict__ offq, const int* __restrict__ off, int count,
-                                           int w, int& i, int& b) {
+                                           int uq, int ur, int w, int& i, int& b) {
+  if (uq > 0) {
+    const int tq = uq * count;
+    if (w < tq) {
+      i = w / uq;
+      b = w - i * uq;
+    } else {
+      w -= tq;
+      i = w / ur;
+      b = uq + (w - i * ur);
+    }
+    return;
+  }
   const int tq = offq[count];
   if (w < tq) {
     i = group_find(offq, count, w);
@@ -1048,13 +1062,14 @@ __device__ __forceinline__ void round_slot(const int* __restrict__ offq, const i
 // invalidate each, which slowed the pair solves running beside them; a
 // launch of its own between the rounds costs a dependent launch per sweep.)
 __global__ void __launch_bounds__(256) kg_round(const GEigDesc* __restrict__ g, const int* __restrict__ offq,
-                                                const int* __restrict__ off, int count, int rg, int max_sweeps,
+                                                const int* __restrict__ off, int count, int uq, int ur, int rg,
+                                                int max_sweeps,
                                                 int* __restrict__ dactive, int* __restrict__ hactive,
                                                 int* __restrict__ hsweeps) {
   __shared__ double lds[kRoundLds];
   __shared__ double red[3][256];
   int i, b;
-  round_slot(offq, off, count, blockIdx.x, i, b);
+  round_slot(offq, off, count, uq, ur, blockIdx.x, i, b);
   const GEigDesc& e = g[i];
   int* c = e.ctl;
   if (!c[GC_DUE] || rg >= c[GC_STOPR]) return;
@@ -1571,9 +1586,11 @@ int group_eig_build(hipStream_t st, GroupEig& ge, const std::vector<GEigDesc>& d
     for (int k = 0; k < kGroupKinds; ++k) off[k * (count + 1) + i + 1] = off[k * (count + 1) + i] + wgs[k];
   }
   int pmax = 2, nsmall = 0;
+  bool uniform = true;  // every descent has the same padded size
   for (const auto& e : descs) {
     pmax = std::max(pmax, e.N / kNB);
     nsmall += e.N == kS ? 1 : 0;
+    uniform = uniform && e.N == descs[0].N;
   }
   const size_t tab_bytes = sizeof(GEigDesc) * count, off_bytes = sizeof(int) * off.size();
   if (ge.cap < count) {
@@ -1597,6 +1614,11 @@ int group_eig_build(hipStream_t st, GroupEig& ge, const std::vector<GEigDesc>& d
   ge.count = count;
   ge.pmax = pmax;
   ge.nsmall = nsmall;
+  {
+    const int q = descs[0].N / kNB / 2;
+    ge.uq = uniform ? q : 0;
+    ge.ur = uniform ? off[1 * (count + 1) + 1] - q : 0;  // tile and V workgroups of one descent
+  }
   ge.off = off;
   // the table and the offsets, on the group's stream; consumed before return
   CMX_HIP(hipMemcpyAsync(ge.dtab, descs.data(), tab_bytes, hipMemcpyHostToDevice, st));
@@ -1649,8 +1671,8 @@ int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int m
   int rg = 0;
   auto queue_rounds = [&](int nr) -> int {
     for (int r = 0; r < nr; ++r, ++rg)
-      kg_round<<<wgs_of(1), 256, 0, st>>>(tab, off_of(0), off_of(1), count, rg, max_sweeps, ge.dactive, hactive,
-                                          hsweeps);
+      kg_round<<<wgs_of(1), 256, 0, st>>>(tab, off_of(0), off_of(1), count, ge.uq, ge.ur, rg, max_sweeps,
+                                          ge.dactive, hactive, hsweeps);
     CMX_HIP(hipGetLastError());
     return 0;
   };

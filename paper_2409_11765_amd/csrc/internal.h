@@ -306,6 +306,7 @@ struct GroupEig {
   int* dactive = nullptr; // device memory: descents still sweeping (the last to stop zeroes hflags[0])
   int cap = 0, count = 0, pmax = 2;
   int nsmall = 0;         // descents with N = kWholeSolveN (solved whole by one workgroup each)
+  int uq = 0, ur = 0;     // all descents of one size: pair-solve and tile / V workgroups each (else 0)
   std::vector<int> off;   // host copy of the offsets (kGroupKinds x (count + 1))
 };
 // (re)load the table of descents (their buffers must stay allocated while in use)
