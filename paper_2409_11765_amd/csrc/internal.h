@@ -320,8 +320,22 @@ int group_eig_solve(hipStream_t st, GroupEig& ge, const GroupDueMask& due, int m
 void group_eig_release(GroupEig& ge);
 
 // workgroup w of a grouped launch belongs to entry i with off[i] <= w < off[i + 1]
+// (the last entry with off[i] <= w).  First guess: the entry w would fall in
+// if all entries were the same size, exact for a group of equal descents, so
+// usually two dependent loads instead of a search of log2(count) of them.
 __device__ __forceinline__ int group_find(const int* __restrict__ off, int count, int w) {
   int lo = 0, hi = count;
+  if (count == 1) return 0;
+  const int total = off[count];
+  if (total > 0) {
+    const int g = min(static_cast<int>(static_cast<int64_t>(w) * count / total), count - 1);
+    const int a = off[g], b = off[g + 1];
+    if (a <= w && w < b) return g;
+    if (w < a)
+      hi = g;
+    else
+      lo = g + 1;
+  }
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (off[mid] <= w)
