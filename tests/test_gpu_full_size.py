@@ -56,3 +56,29 @@ def test_full_size_generation(P, n, lam, kind, precision):
     assert np.max(np.abs(g["f"] - f_ref)) <= ftol * np.max(np.abs(f_ref))
     tau = 1e-10 if precision == "fp64" else 1e-4
     assert rank_agreement(f_ref, g["order"], info["order"], tau) == 0
+
+
+@pytest.mark.parametrize("kind,rotated", [("sphere", False), ("ellipsoid", True), ("rastrigin", True)])
+@pytest.mark.parametrize("n,lam", [(1, 4), (10, 10), (37, 53), (100, 17), (130, 301), (200, 19), (257, 1030)])
+def test_one_generation_bf16x3(P, kind, rotated, n, lam):
+    """bf16 x 3 sampling at the one-generation parity sizes (from a single
+    partial tile to several tiles with ragged edges), by the criteria of the
+    full-size case: the state update against the oracle driven by the
+    device's fitness values, f against the oracle's, ranks where fitness gaps
+    exceed tau."""
+    print(f"case n={n} lam={lam} {kind} rot={rotated}", flush=True)
+    st = synth.random_state(n, lam, seed=n * 7 + lam, cond=100.0)
+    R, xs = synth.problem(n, seed=n + 3) if rotated else (None, synth.optimum(n, n + 3))
+    Z = synth.normal_matrix(n, lam, seed=lam * 11 + n)
+    g, o, info = one_generation(P, st, Z, kind, R, xs, "mixed_bf16x3")
+    o = oracle_state(st)
+    O.generation(o, None, Z=Z, fvals=g["f"])
+    errs = {"m": rel(g["m"], o.m), "C": rel(g["C"], o.C), "sigma": abs(g["sigma"] - o.sigma) / o.sigma,
+            "p_sigma": rel(g["p_sigma"], o.ps), "p_c": rel(g["p_c"], o.pc)}
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v < TOL["mixed"], (k, v)
+    f_ref = info["f"]
+    assert np.max(np.abs(g["f"] - f_ref)) <= 2e-5 * np.max(np.abs(f_ref))
+    assert rank_agreement(f_ref, g["order"], info["order"], 1e-4) == 0
+
